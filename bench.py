@@ -1,0 +1,193 @@
+"""Throughput benchmark of the batched rotamer sweep on one MI355X.
+
+Default workload: 10,000 ligands (20-80 atoms, 2-12 rotamers) x 256 rigid
+orientations x 256 angle steps against a 128^3 pocket (synthetic, seeded).
+Inputs are resident in HBM before the timed region; one step = one
+dock_batch_async call over the whole batch (every restart of every ligand,
+the per-ligand best reduction and the pose write-back).
+
+Prints one JSON line (rank 0): ligands/s, the sweep kernel's roofline
+fraction (HIP events around that kernel on its own stream) and the FP64
+reference timed on a bounded sample on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "ligands/sec on 1 MI355X (plain vs learned proposal at ≤0.5% score loss)"
+
+# MI355X: 256 CUs x 64 lanes x 2.4 GHz, one FP32 VALU lane-operation per lane per clock
+VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+# Lane-operation counts (FP32 VALU instructions per lane) of the sweep's units:
+#   direct kernel, per angle: 8 per cross pair (3 sub, mul, 2 fma, cmp, or),
+#     23 per Rodrigues rotation, 22 per voxel lookup and add
+#   pruned kernel: 25 per candidate cross pair per rotamer (bound test and the
+#     pair's harmonic coefficients), 4 per executed (pair, angle) test
+#     (fma, mul, cmp, or), 26 per (moving atom, angle) evaluation
+#     (6 fma rotation + 20 voxel index, gather and add)
+OPS_PAIR, OPS_ROT, OPS_VOX = 8, 23, 22
+OPS_CAND, OPS_TEST, OPS_EVAL = 25, 4, 26
+
+WORKLOADS = {
+    1: "C1: 64^3 pocket @0.5A, 1 ligand (32 atoms, 4 rotamers), 8 orientations, 64 steps",
+    2: "C2: 128^3 pocket @0.375A, 10000 ligands (20-80 atoms, 2-12 rotamers), "
+       "256 orientations, 256 steps",
+    3: "C3: 128^3 pocket @0.375A, 100000 ligands (lognormal 8-150 atoms, 0-40 rotamers), "
+       "128 orientations, 128 steps",
+    5: "C5: 256^3 irregular pocket @0.25A, 2000 ligands (100-250 atoms, 60-120 rotamers), "
+       "64 orientations, 360 steps",
+}
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def batch_counts(ligs):
+    """Per-batch sums over rotamers of m_r q_r and m_r (one orientation)."""
+    n = np.diff(ligs.atom_offset).astype(np.int64)
+    R = np.diff(ligs.rot_offset)
+    lig_of_rot = np.repeat(np.arange(ligs.n_ligands), R)
+    m = np.diff(ligs.move_offset).astype(np.int64)
+    q = n[lig_of_rot] - m - 2
+    return float((m * q).sum()), float(m.sum())
+
+
+def algorithmic_ops(ligs, n_orient, S, bump, pair_tests):
+    """Lane-operations of one whole batch (see the unit costs above)."""
+    mq, msum = batch_counts(ligs)
+    if bump == "direct":
+        return (OPS_PAIR * mq + (OPS_ROT + OPS_VOX) * msum) * S * n_orient
+    return (OPS_CAND * mq + OPS_EVAL * msum * S) * n_orient + OPS_TEST * pair_tests
+
+
+def cpu_baseline(pocket, ligs, orient, S, budget_s=15.0):
+    """The FP64 reference on a bounded sample of the same workload."""
+    import oracle
+    threads = min(16, os.cpu_count() or 1)
+    sample = 8
+    t_used = 0.0
+    while True:
+        sub = ligs.subset(range(sample))
+        t0 = time.perf_counter()
+        oracle.dock_batch(pocket, sub, orient, S, n_threads=threads)
+        t_used = time.perf_counter() - t0
+        if t_used > budget_s / 4 or sample * 2 > ligs.n_ligands:
+            break
+        sample *= 2
+    return {"value": sample / t_used, "unit": "ligands/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {sample} ligands of the workload, all orientations and steps, "
+                      f"FP64, {threads} threads, {t_used:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", type=int, default=2, choices=sorted(WORKLOADS))
+    ap.add_argument("--ligands", type=int, default=0, help="override the ligand count")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--bump", choices=("pruned", "direct"), default="pruned",
+                    help="pruned: test only pairs that can clash; direct: every pair")
+    ap.add_argument("--waves", type=int, default=4, help="waves per block of the sweep")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the batch shards by ligand with no exchange; see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1901_06229_amd import dock, synth
+
+    cfg = args.config
+    preset = synth.PRESETS[cfg]
+    S, O = preset["angle_steps"], preset["n_orient"]
+    L = args.ligands or preset["n_ligands"]
+    log(f"config {cfg}: generating {L} ligands")
+    pocket = synth.pocket(cfg)
+    ligs = synth.ligands(cfg, count=L)
+    orient = synth.orientations(cfg)
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
+    h = dock.dock_init_pocket(pocket.grid, pocket.origin, pocket.spacing)
+    d = dict(n_ligands=ligs.n_ligands, total_atoms=int(ligs.atom_offset[-1]),
+             total_rot=int(ligs.rot_offset[-1]), total_move=int(ligs.move_offset[-1]))
+    for k, dt in (("atom_offset", torch.int32), ("xyz", torch.float32), ("rot_offset", torch.int32),
+                  ("rot_axis", torch.int32), ("move_offset", torch.int32), ("move_atoms", torch.int16)):
+        d[k] = torch.from_numpy(np.ascontiguousarray(getattr(ligs, k))).to(dev, dt)
+    orient_d = torch.from_numpy(orient).to(dev)
+    NA, NR = d["total_atoms"], d["total_rot"]
+    out = dict(best_score=torch.empty(L, device=dev), best_orient=torch.empty(L, dtype=torch.int32, device=dev),
+               angle_idx=torch.empty(max(NR, 1), dtype=torch.int16, device=dev),
+               xyz=torch.empty(max(NA, 1), 3, device=dev),
+               status=torch.empty(L, dtype=torch.int32, device=dev))
+    ws = torch.empty(dock.dock_workspace_size(L, NR, O, S), dtype=torch.uint8, device=dev)
+    max_atoms = int(np.diff(ligs.atom_offset).max())
+    flags = dock.DOCK_FLAG_TIME_SWEEP | (dock.DOCK_FLAG_DIRECT_BUMP if args.bump == "direct" else 0)
+    prm = dock.make_params(r_bump=synth.R_BUMP, max_atoms=max_atoms, flags=flags)
+    dock.dock_set_launch(h, args.waves)
+    stream = torch.cuda.Stream()
+    torch.cuda.synchronize()
+
+    pair_tests = []
+
+    def step():
+        dock.dock_batch_async(h, d, orient_d, S, out, prm, workspace=ws, stream=stream)
+        ms = dock.dock_last_sweep_ms(h)
+        pair_tests.append(dock.dock_last_sweep_pairs(h))
+        return ms
+
+    for w in range(args.warmup):
+        ms = step()
+        log(f"warmup {w}: sweep {ms:.1f} ms")
+    torch.cuda.synchronize()
+    assert int((out["status"] != 0).sum()) == 0
+    sweep_ms = []
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        sweep_ms.append(step())
+        log(f"step {s}: sweep {sweep_ms[-1]:.1f} ms")
+    stream.synchronize()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    value = args.steps * L / elapsed
+    ops = algorithmic_ops(ligs, O, S, args.bump, pair_tests[-1])
+    mean_s = float(np.mean(sweep_ms)) / 1e3
+    achieved = ops / mean_s / 1e12
+    line = {
+        "metric": METRIC, "value": round(value, 2), "unit": "ligands/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * elapsed / args.steps, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic", "mode": "plain", "bump": args.bump,
+        "config": {"workload": WORKLOADS[cfg] if L == preset["n_ligands"] else
+                   WORKLOADS[cfg] + f" (ligands overridden to {L})",
+                   "n_ligands": L, "n_orient": O, "angle_steps": S, "r_bump": synth.R_BUMP},
+        "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 2),
+                     "unit": "TOP/s", "frac": round(achieved / VALU_PEAK_TOPS, 4), "traffic": None,
+                     "kernel": "sweep_pruned_kernel" if args.bump == "pruned" else "sweep_kernel",
+                     "kernel_ms": round(1e3 * mean_s, 3),
+                     "work": ("lane-ops: 25 per candidate pair per rotamer + 4 per executed "
+                              "(pair, angle) test + 26 per (moving atom, angle)")
+                     if args.bump == "pruned" else
+                     "dense lane-ops per angle: 8 per cross pair + 45 per moving atom",
+                     "pair_angle_tests": pair_tests[-1]},
+    }
+    if not args.no_cpu_baseline:
+        log("timing the FP64 reference on a sample")
+        line["cpu_baseline"] = cpu_baseline(pocket, ligs, orient, S)
+    print(json.dumps(line), flush=True)
+    h.close()
+
+
+if __name__ == "__main__":
+    main()

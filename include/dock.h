@@ -1,0 +1,195 @@
+/* dock.h -- C-ABI of the MI355X (gfx950) greedy rotamer-sweep library.
+ *
+ * The library implements the pose-optimisation phase of a geometric docking
+ * mini-app (paper §3.1 and Listing 1: load the pocket once, then for every
+ * ligand and every restart optimise the pose; §4.1 and Listing 2: every
+ * fragment in sequence is rotated about its 1-D bond axis, all candidate
+ * angles are evaluated in parallel and reduced to the best).
+ *
+ * What one (ligand, orientation) item computes:
+ *   1. X = R_o X_ref + t_o                             (rigid starting pose)
+ *   2. for pass in [0, passes), for rotamer r in input order:
+ *        u = (X_b - X_a)/|X_b - X_a|
+ *        for k in [0, S): theta_k = 2 pi k / S; Y = X with the moving atoms
+ *          rotated about u through X_a (Rodrigues); k = 0 is the identity.
+ *          valid_k  <=>  |Y_i - X_j|^2 >= r_bump^2 for every moving atom i
+ *                        and every atom j outside the moving set and the axis
+ *          s_k = sum over all atoms of grid[clamp(floor((p - o)/h))]
+ *        k* = lowest k maximising s_k over valid k (-1: none, no move)
+ *        X <- Y(k*)
+ *   3. final score S_o = sum over atoms of the voxel values of X
+ * Per ligand the best orientation (lowest index on ties) is reported with its
+ * pose, score and chosen angle indices.  Arithmetic is FP32 on the GPU.
+ *
+ * Conventions
+ *   - Every function returns DOCK_OK (0) or a negative DOCK_E_* code; no C++
+ *     exception crosses this boundary.  dock_last_error() gives a
+ *     thread-local detail string for the last failing call on that thread.
+ *   - The caller owns every array passed in or out.  Synchronous calls keep
+ *     no caller pointer after they return; asynchronous calls keep them until
+ *     the stream has passed the enqueued work.
+ *   - A dock_pocket owns its device copy of the grid until dock_free_pocket.
+ *     One handle may be shared across threads; concurrent calls on one
+ *     handle must use distinct streams (each call uses its own workspace).
+ */
+#ifndef DOCK_H
+#define DOCK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DOCK_OK 0
+#define DOCK_E_INVAL (-1)     /* malformed argument (NULL, bad CSR, bad index) */
+#define DOCK_E_LIMIT (-2)     /* outside a documented limit                    */
+#define DOCK_E_NOMEM (-3)     /* device or host allocation failed              */
+#define DOCK_E_DEVICE (-4)    /* HIP runtime error                             */
+#define DOCK_E_CANCELLED (-5) /* reserved                                      */
+#define DOCK_E_STATE (-6)     /* e.g. learned mode without a loaded proposal   */
+
+#define DOCK_MAX_ATOMS 256    /* atoms per ligand                 */
+#define DOCK_MAX_ROT 255      /* rotamers per ligand              */
+#define DOCK_MAX_STEPS 4096   /* angle steps S                    */
+#define DOCK_MAX_PASSES 16    /* refinement passes (num_repetitions) */
+
+#define DOCK_MODE_PLAIN 0     /* full angle sweep                          */
+#define DOCK_MODE_LEARNED 1   /* learned top-k proposal with full fallback */
+
+#define DOCK_FLAG_NO_LPT 1u   /* keep input order instead of cost-sorted items */
+#define DOCK_FLAG_TIME_SWEEP 2u /* record HIP events around the sweep kernel
+                                   (read with dock_last_sweep_ms)           */
+#define DOCK_FLAG_DIRECT_BUMP 4u /* test every cross pair at every angle
+                                    (default: only pairs that can clash)    */
+
+typedef struct dock_pocket dock_pocket;
+
+/* A batch of ligands in CSR form.  All indices inside a ligand are local
+ * (0 .. n_l - 1).
+ *   atom_offset[n_ligands+1]   ligand l owns atoms [atom_offset[l], atom_offset[l+1])
+ *   xyz[total_atoms][3]        reference coordinates (A), FP32
+ *   rot_offset[n_ligands+1]    ligand l owns rotamers [rot_offset[l], rot_offset[l+1])
+ *   rot_axis[total_rot][2]     (a, b) axis atoms; b is on the moving side
+ *   move_offset[total_rot+1]   rotamer r moves move_atoms[move_offset[r] .. move_offset[r+1])
+ *                              (global positions into move_atoms)
+ *   move_atoms[total_move]     local atom indices, strictly ascending per
+ *                              rotamer, never a or b
+ * total_* must equal atom_offset[n_ligands], rot_offset[n_ligands] and
+ * move_offset[total_rot]. */
+typedef struct {
+  int32_t n_ligands;
+  int64_t total_atoms, total_rot, total_move;
+  const int32_t *atom_offset;
+  const float *xyz;
+  const int32_t *rot_offset;
+  const int32_t *rot_axis;
+  const int32_t *move_offset;
+  const int16_t *move_atoms;
+} dock_ligands;
+
+typedef struct {
+  float r_bump;      /* bump radius (A), >= 0                                   */
+  int32_t passes;    /* sweeps over all rotamers (paper: num_repetitions), >= 1 */
+  int32_t mode;      /* DOCK_MODE_PLAIN or DOCK_MODE_LEARNED                    */
+  int32_t top_k;     /* learned mode: bins nominated per step (1..64)          */
+  float margin;      /* learned mode: fall back to the full sweep when the
+                        predicted best minus the (top_k+1)-th is below this   */
+  uint32_t flags;    /* DOCK_FLAG_*                                             */
+  int32_t max_atoms; /* async calls: upper bound on atoms per ligand (0: 256)   */
+} dock_params;
+
+/* Outputs.  Sizes follow from the inputs.
+ *   best_score[n_ligands]       FP32 final score of the best orientation
+ *   best_orient[n_ligands]      its index (-1 if the ligand was rejected)
+ *   angle_idx[total_rot*passes] chosen angle per step of the best
+ *                               orientation; ligand l's steps start at
+ *                               rot_offset[l]*passes, step = pass*R_l + r
+ *   xyz_out[total_atoms][3]     final pose of the best orientation
+ *   all_scores[n_ligands][n_orient]          optional (NULL): every S_o
+ *   all_angle_idx[total_rot*passes*n_orient] optional (NULL): every item's
+ *                               steps; (l, o) starts at
+ *                               (rot_offset[l]*n_orient + o*R_l)*passes
+ *   status[n_ligands]           optional (NULL): 0 or a DOCK_E_* code per
+ *                               ligand (async calls validate on the device)
+ *   n_fallback[n_ligands]       optional (NULL): learned mode, steps that
+ *                               fell back to the full sweep               */
+typedef struct {
+  float *best_score;
+  int32_t *best_orient;
+  int16_t *angle_idx;
+  float *xyz_out;
+  float *all_scores;
+  int16_t *all_angle_idx;
+  int32_t *status;
+  int32_t *n_fallback;
+} dock_results;
+
+/* Stage a pocket grid on the current HIP device (paper Listing 1: the pocket
+ * is loaded once; §4.1: the constructor copies data to the device).
+ *   grid[nz][ny][nx]   host FP32 values, x fastest; voxel (ix,iy,iz) covers
+ *                      origin + [i, i+1) * spacing on each axis
+ *   1 <= nx,ny,nz <= 4096, spacing > 0.
+ * On success *out owns a device copy; the host array may be freed.
+ * Errors: DOCK_E_INVAL, DOCK_E_LIMIT, DOCK_E_NOMEM, DOCK_E_DEVICE. */
+int dock_init_pocket(const float *grid, int nx, int ny, int nz,
+                     const float origin[3], float spacing, dock_pocket **out);
+
+/* Release a pocket and every workspace it cached.  NULL is a no-op. */
+void dock_free_pocket(dock_pocket *p);
+
+/* Synchronous batch: host arrays in, host arrays out (paper §4.1: data moves
+ * once per ligand, at the start and at the end).  Inputs are validated on
+ * the host first (DOCK_E_INVAL / DOCK_E_LIMIT, nothing launched).
+ *   orient[n_orient][12]  rigid transforms, row-major R (9) then t (3)
+ *   angle_steps           S, 1 .. DOCK_MAX_STEPS                           */
+int dock_batch(dock_pocket *p, const dock_ligands *ligs, const float *orient,
+               int n_orient, int angle_steps, const dock_params *prm,
+               dock_results *out);
+
+/* Device-resident batch on a caller stream (hipStream_t passed as void*,
+ * NULL = default stream).  Every pointer in ligs, orient and out is a
+ * device pointer; the totals in ligs must be set.  The call only enqueues
+ * work and returns; results are ready when the stream reaches that point.
+ * Per-ligand input errors are found on the device: such ligands are skipped,
+ * get best_orient = -1 and, if out->status is set, their DOCK_E_* code.
+ * workspace: device memory of at least dock_workspace_size() bytes, or NULL
+ * to let the library allocate (and cache on the handle) its own. */
+int dock_batch_async(dock_pocket *p, const dock_ligands *ligs,
+                     const float *orient, int n_orient, int angle_steps,
+                     const dock_params *prm, dock_results *out,
+                     void *workspace, size_t workspace_bytes, void *stream);
+
+/* Bytes of device workspace dock_batch_async needs for these sizes. */
+size_t dock_workspace_size(int32_t n_ligands, int64_t total_rot, int n_orient,
+                           int angle_steps, int passes);
+
+/* Duration in ms of the sweep kernel of the last call on this handle that
+ * set DOCK_FLAG_TIME_SWEEP (waits for that kernel to finish).  Errors:
+ * DOCK_E_INVAL (NULL), DOCK_E_STATE (no timed call yet), DOCK_E_DEVICE. */
+int dock_last_sweep_ms(dock_pocket *p, float *ms);
+
+/* Number of (cross pair, angle) bump tests the sweep kernel executed in the
+ * last call with DOCK_FLAG_TIME_SWEEP (pruned mode: only the pairs that can
+ * clash; direct mode: not counted, 0).  Waits for that call's sweep. */
+int dock_last_sweep_pairs(dock_pocket *p, uint64_t *pair_angle_tests);
+
+/* Launch mapping of the sweep kernel for calls on this handle (the knob the
+ * autotuner turns): waves_per_block in {1, 2, 4}, each wave working on its
+ * own (ligand, orientation) items; blocks_per_cu >= 0 caps resident blocks
+ * per compute unit (0: occupancy limit).  Results do not depend on it.
+ * Errors: DOCK_E_INVAL. */
+int dock_set_launch(dock_pocket *p, int waves_per_block, int blocks_per_cu);
+
+/* Static description of a DOCK_E_* code. */
+const char *dock_strerror(int code);
+
+/* Thread-local detail of the last failing call on this thread ("" if none). */
+const char *dock_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DOCK_H */

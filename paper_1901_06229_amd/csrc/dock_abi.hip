@@ -1,0 +1,483 @@
+// Host runtime and C-ABI of the rotamer-sweep library (see include/dock.h).
+//
+// dock_init_pocket stages the grid once (paper Listing 1: the pocket is
+// loaded before the ligand loop; §4.1: device data is owned by the object and
+// copied at construction).  dock_batch moves a batch in once and the results
+// out once (§4.1: data moves only at the start and the end of docking).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <string>
+
+#include "dock.h"
+#include "dock_internal.h"
+
+using namespace dock;
+
+struct dock_pocket {
+  int device = 0;
+  float *d_grid = nullptr;
+  GridView view{};
+  int n_cu = 0;
+  hipStream_t stream = nullptr;
+  std::mutex mu;              // guards the cached buffers below
+  void *ws = nullptr;         // workspace for async calls that pass none
+  size_t ws_bytes = 0;
+  void *io = nullptr;         // device staging of synchronous calls
+  size_t io_bytes = 0;
+  void *sync_ws = nullptr;    // workspace of synchronous calls
+  size_t sync_ws_bytes = 0;
+  hipEvent_t ev_sweep[3] = {nullptr, nullptr, nullptr};  // sweep start/end, counter copied
+  bool timed = false;
+  unsigned long long *h_pairs = nullptr;  // pinned copy of the pair-test count
+  LaunchPlan plan{4, 0};
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+  return fail(e == hipErrorOutOfMemory ? DOCK_E_NOMEM : DOCK_E_DEVICE, "%s: %s", what,
+              hipGetErrorString(e));
+}
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) == hipSuccess && prev != dev) (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+struct WsLayout {
+  size_t small, keys, order, bucket, status, kstar, cs, total;
+};
+
+WsLayout ws_layout(int64_t L, int64_t total_rot, int O, int S, int passes) {
+  WsLayout w;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = off;
+    off = align_up(off + bytes);
+    return at;
+  };
+  w.small = take(sizeof(int32_t) * kSmallInts);
+  w.keys = take(sizeof(unsigned long long) * (size_t)L);
+  w.order = take(sizeof(int32_t) * (size_t)L);
+  w.bucket = take(sizeof(int32_t) * (size_t)L);
+  w.status = take(sizeof(int32_t) * (size_t)L);
+  w.kstar = take(sizeof(int16_t) * (size_t)total_rot * (size_t)passes * (size_t)O);
+  w.cs = take(sizeof(float2) * (size_t)S);
+  w.total = off;
+  return w;
+}
+
+int grow(void **buf, size_t *have, size_t need) {
+  if (*have >= need && *buf) return DOCK_OK;
+  if (*buf) (void)hipFree(*buf);
+  *buf = nullptr;
+  *have = 0;
+  hipError_t e = hipMalloc(buf, need < kAlign ? kAlign : need);
+  if (e != hipSuccess) {
+    *buf = nullptr;
+    return hip_fail(e, "hipMalloc(workspace)");
+  }
+  *have = need;
+  return DOCK_OK;
+}
+
+int check_params(const dock_params *prm, int n_orient, int S) {
+  if (!prm) return fail(DOCK_E_INVAL, "params is NULL");
+  if (n_orient < 1) return fail(DOCK_E_INVAL, "n_orient must be >= 1");
+  if (S < 1 || S > DOCK_MAX_STEPS) return fail(DOCK_E_LIMIT, "angle_steps %d outside [1, %d]", S, DOCK_MAX_STEPS);
+  if (!(prm->r_bump >= 0.0f) || !std::isfinite(prm->r_bump))
+    return fail(DOCK_E_INVAL, "r_bump must be finite and >= 0");
+  if (prm->passes < 1 || prm->passes > DOCK_MAX_PASSES)
+    return fail(DOCK_E_LIMIT, "passes %d outside [1, %d]", prm->passes, DOCK_MAX_PASSES);
+  if (prm->mode != DOCK_MODE_PLAIN && prm->mode != DOCK_MODE_LEARNED)
+    return fail(DOCK_E_INVAL, "unknown mode %d", prm->mode);
+  if (prm->max_atoms < 0 || prm->max_atoms > DOCK_MAX_ATOMS)
+    return fail(DOCK_E_LIMIT, "max_atoms %d outside [0, %d]", prm->max_atoms, DOCK_MAX_ATOMS);
+  return DOCK_OK;
+}
+
+// Full host-side check of a CSR batch (synchronous path).
+int check_ligands_host(const dock_ligands *L, int *max_n) {
+  if (!L) return fail(DOCK_E_INVAL, "ligands is NULL");
+  if (L->n_ligands < 0) return fail(DOCK_E_INVAL, "n_ligands < 0");
+  if (!L->atom_offset || !L->rot_offset) return fail(DOCK_E_INVAL, "offset array is NULL");
+  const int nl = L->n_ligands;
+  if (L->atom_offset[0] != 0 || L->rot_offset[0] != 0)
+    return fail(DOCK_E_INVAL, "offsets must start at 0");
+  if (L->atom_offset[nl] != L->total_atoms || L->rot_offset[nl] != L->total_rot)
+    return fail(DOCK_E_INVAL, "total_atoms/total_rot do not match the offsets");
+  if (L->total_rot > 0 && (!L->rot_axis || !L->move_offset))
+    return fail(DOCK_E_INVAL, "rot_axis/move_offset is NULL");
+  if (L->total_atoms > 0 && !L->xyz) return fail(DOCK_E_INVAL, "xyz is NULL");
+  if (L->total_rot > 0) {
+    if (L->move_offset[0] != 0 || L->move_offset[L->total_rot] != L->total_move)
+      return fail(DOCK_E_INVAL, "move_offset must run from 0 to total_move");
+    if (L->total_move > 0 && !L->move_atoms) return fail(DOCK_E_INVAL, "move_atoms is NULL");
+  }
+  int mx = 0;
+  for (int l = 0; l < nl; ++l) {
+    int n = L->atom_offset[l + 1] - L->atom_offset[l];
+    int R = L->rot_offset[l + 1] - L->rot_offset[l];
+    if (n < 1) return fail(DOCK_E_INVAL, "ligand %d has %d atoms", l, n);
+    if (R < 0) return fail(DOCK_E_INVAL, "ligand %d: rot_offset decreases", l);
+    if (n > DOCK_MAX_ATOMS) return fail(DOCK_E_LIMIT, "ligand %d has %d atoms (max %d)", l, n, DOCK_MAX_ATOMS);
+    if (R > DOCK_MAX_ROT) return fail(DOCK_E_LIMIT, "ligand %d has %d rotamers (max %d)", l, R, DOCK_MAX_ROT);
+    mx = n > mx ? n : mx;
+    for (int r = L->rot_offset[l]; r < L->rot_offset[l + 1]; ++r) {
+      int a = L->rot_axis[2 * r], b = L->rot_axis[2 * r + 1];
+      if (a < 0 || a >= n || b < 0 || b >= n || a == b)
+        return fail(DOCK_E_INVAL, "ligand %d rotamer %d: bad axis (%d, %d)", l, r, a, b);
+      int m0 = L->move_offset[r], m1 = L->move_offset[r + 1];
+      if (m1 < m0 || m1 - m0 > n - 2)
+        return fail(DOCK_E_INVAL, "ligand %d rotamer %d: bad moving-set size", l, r);
+      int prev = -1;
+      for (int t = m0; t < m1; ++t) {
+        int i = L->move_atoms[t];
+        if (i <= prev || i >= n || i == a || i == b)
+          return fail(DOCK_E_INVAL, "ligand %d rotamer %d: bad moving atom %d", l, r, i);
+        prev = i;
+      }
+    }
+  }
+  *max_n = mx;
+  return DOCK_OK;
+}
+
+int maxn_bucket(int max_atoms) { return max_atoms <= 64 ? 64 : (max_atoms <= 128 ? 128 : 256); }
+
+int enqueue_batch(dock_pocket *p, const dock_ligands *ligs, const float *orient, int O, int S,
+                  const dock_params *prm, const dock_results *out, void *ws, size_t ws_bytes,
+                  hipStream_t st) {
+  const int64_t L = ligs->n_ligands;
+  const int max_atoms = prm->max_atoms > 0 ? prm->max_atoms : DOCK_MAX_ATOMS;
+  if (L * (int64_t)O >= ((int64_t)1 << 31)) return fail(DOCK_E_LIMIT, "n_ligands * n_orient >= 2^31");
+  if (prm->mode == DOCK_MODE_LEARNED) return fail(DOCK_E_STATE, "no learned proposal loaded");
+  WsLayout w = ws_layout(L, ligs->total_rot, O, S, prm->passes);
+  if (ws_bytes < w.total) return fail(DOCK_E_INVAL, "workspace too small: %zu < %zu", ws_bytes, w.total);
+  char *base = (char *)ws;
+  SweepArgs A{};
+  A.grid = p->view;
+  A.lig = LigView{ligs->n_ligands, ligs->total_atoms, ligs->total_rot, ligs->total_move,
+                  ligs->atom_offset, ligs->xyz, ligs->rot_offset, ligs->rot_axis,
+                  ligs->move_offset, ligs->move_atoms};
+  A.orient = orient;
+  A.n_orient = O;
+  A.S = S;
+  A.passes = prm->passes;
+  A.r2 = prm->r_bump * prm->r_bump;
+  A.cs = (const float2 *)(base + w.cs);
+  A.order = (const int32_t *)(base + w.order);
+  A.status = out->status ? out->status : (const int32_t *)(base + w.status);
+  A.small = (int32_t *)(base + w.small);
+  A.queue = A.small;
+  A.n_items = (int32_t)(L * O);
+  const bool timed = (prm->flags & DOCK_FLAG_TIME_SWEEP) != 0;
+  A.pair_tests = timed ? (unsigned long long *)(A.small + 4) : nullptr;
+  A.keys = (unsigned long long *)(base + w.keys);
+  A.kstar = (int16_t *)(base + w.kstar);
+  A.all_scores = out->all_scores;
+  int32_t *counts = A.small + 64, *cursor = A.small + 64 + kLptBuckets;
+  bool lpt = !(prm->flags & DOCK_FLAG_NO_LPT);
+  hipError_t e = enqueue_prepare(A, max_atoms, lpt, (int32_t *)(base + w.bucket), counts, cursor,
+                                 A.small + 1, st);
+  if (e != hipSuccess) return hip_fail(e, "prepare kernels");
+  const int maxn = maxn_bucket(max_atoms);
+  if (timed && (e = hipEventRecord(p->ev_sweep[0], st)) != hipSuccess)
+    return hip_fail(e, "hipEventRecord");
+  const SweepMode mode = (prm->flags & DOCK_FLAG_DIRECT_BUMP) ? kSweepDirect : kSweepPruned;
+  if (mode == kSweepDirect)
+    e = enqueue_sweep(A, maxn, p->plan, p->n_cu, st);
+  else
+    e = enqueue_sweep_pruned(A, max_atoms, p->plan, p->n_cu, st);
+  if (e != hipSuccess) return hip_fail(e, "sweep kernel");
+  if (timed) {
+    if ((e = hipEventRecord(p->ev_sweep[1], st)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+    e = hipMemcpyAsync(p->h_pairs, A.small + 4, sizeof(unsigned long long), hipMemcpyDeviceToHost, st);
+    if (e != hipSuccess) return hip_fail(e, "copy pair count");
+    if ((e = hipEventRecord(p->ev_sweep[2], st)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+    p->timed = true;
+  }
+  FinalOut F{out->best_score, out->best_orient, out->angle_idx, out->xyz_out};
+  e = enqueue_finalize(A, F, maxn, mode, st);
+  if (e != hipSuccess) return hip_fail(e, "finalize kernel");
+  if (out->all_angle_idx && ligs->total_rot > 0) {
+    e = hipMemcpyAsync(out->all_angle_idx, A.kstar,
+                       sizeof(int16_t) * (size_t)ligs->total_rot * prm->passes * O,
+                       hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) return hip_fail(e, "copy all_angle_idx");
+  }
+  return DOCK_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *dock_strerror(int code) {
+  switch (code) {
+    case DOCK_OK: return "ok";
+    case DOCK_E_INVAL: return "invalid argument";
+    case DOCK_E_LIMIT: return "outside a documented limit";
+    case DOCK_E_NOMEM: return "out of memory";
+    case DOCK_E_DEVICE: return "HIP device error";
+    case DOCK_E_CANCELLED: return "cancelled";
+    case DOCK_E_STATE: return "invalid state";
+    default: return "unknown error";
+  }
+}
+
+const char *dock_last_error(void) { return g_last_error.c_str(); }
+
+int dock_last_sweep_pairs(dock_pocket *p, uint64_t *pair_angle_tests) {
+  g_last_error.clear();
+  if (!p || !pair_angle_tests) return fail(DOCK_E_INVAL, "NULL argument");
+  if (!p->timed) return fail(DOCK_E_STATE, "no call with DOCK_FLAG_TIME_SWEEP yet");
+  DeviceGuard g(p->device);
+  hipError_t e = hipEventSynchronize(p->ev_sweep[2]);
+  if (e != hipSuccess) return hip_fail(e, "sweep counters");
+  *pair_angle_tests = (uint64_t)*(volatile unsigned long long *)p->h_pairs;
+  return DOCK_OK;
+}
+
+int dock_set_launch(dock_pocket *p, int waves_per_block, int blocks_per_cu) {
+  g_last_error.clear();
+  if (!p) return fail(DOCK_E_INVAL, "NULL pocket");
+  if (waves_per_block != 1 && waves_per_block != 2 && waves_per_block != 4)
+    return fail(DOCK_E_INVAL, "waves_per_block must be 1, 2 or 4");
+  if (blocks_per_cu < 0) return fail(DOCK_E_INVAL, "blocks_per_cu must be >= 0");
+  p->plan = LaunchPlan{waves_per_block, blocks_per_cu};
+  return DOCK_OK;
+}
+
+int dock_last_sweep_ms(dock_pocket *p, float *ms) {
+  g_last_error.clear();
+  if (!p || !ms) return fail(DOCK_E_INVAL, "NULL argument");
+  if (!p->timed) return fail(DOCK_E_STATE, "no call with DOCK_FLAG_TIME_SWEEP yet");
+  DeviceGuard g(p->device);
+  hipError_t e = hipEventSynchronize(p->ev_sweep[1]);
+  if (e == hipSuccess) e = hipEventElapsedTime(ms, p->ev_sweep[0], p->ev_sweep[1]);
+  return e == hipSuccess ? DOCK_OK : hip_fail(e, "sweep timing");
+}
+
+size_t dock_workspace_size(int32_t n_ligands, int64_t total_rot, int n_orient, int angle_steps,
+                           int passes) {
+  if (n_ligands < 0 || total_rot < 0 || n_orient < 1 || angle_steps < 1 || passes < 1) return 0;
+  return ws_layout(n_ligands, total_rot, n_orient, angle_steps, passes).total;
+}
+
+int dock_init_pocket(const float *grid, int nx, int ny, int nz, const float origin[3],
+                     float spacing, dock_pocket **out) {
+  g_last_error.clear();
+  if (!out) return fail(DOCK_E_INVAL, "out is NULL");
+  *out = nullptr;
+  if (!grid || !origin) return fail(DOCK_E_INVAL, "grid or origin is NULL");
+  if (nx < 1 || ny < 1 || nz < 1 || nx > 4096 || ny > 4096 || nz > 4096)
+    return fail(DOCK_E_LIMIT, "grid dims %d x %d x %d outside [1, 4096]", nx, ny, nz);
+  if (!(spacing > 0.0f) || !std::isfinite(spacing)) return fail(DOCK_E_INVAL, "spacing must be > 0");
+  for (int a = 0; a < 3; ++a)
+    if (!std::isfinite(origin[a])) return fail(DOCK_E_INVAL, "origin must be finite");
+  dock_pocket *p = new (std::nothrow) dock_pocket;
+  if (!p) return fail(DOCK_E_NOMEM, "host allocation");
+  hipError_t e = hipGetDevice(&p->device);
+  if (e != hipSuccess) {
+    delete p;
+    return hip_fail(e, "hipGetDevice");
+  }
+  e = hipDeviceGetAttribute(&p->n_cu, hipDeviceAttributeMultiprocessorCount, p->device);
+  if (e != hipSuccess) {
+    delete p;
+    return hip_fail(e, "hipDeviceGetAttribute");
+  }
+  size_t bytes = sizeof(float) * (size_t)nx * ny * nz;
+  e = hipMalloc((void **)&p->d_grid, bytes);
+  if (e != hipSuccess) {
+    delete p;
+    return hip_fail(e, "hipMalloc(grid)");
+  }
+  e = hipStreamCreateWithFlags(&p->stream, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreate(&p->ev_sweep[0]);
+  if (e == hipSuccess) e = hipEventCreate(&p->ev_sweep[1]);
+  if (e == hipSuccess) e = hipEventCreate(&p->ev_sweep[2]);
+  if (e == hipSuccess) e = hipHostMalloc((void **)&p->h_pairs, sizeof(unsigned long long), 0);
+  if (e == hipSuccess) e = hipMemcpyAsync(p->d_grid, grid, bytes, hipMemcpyHostToDevice, p->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+  if (e != hipSuccess) {
+    int code = hip_fail(e, "grid upload");
+    dock_free_pocket(p);
+    return code;
+  }
+  p->view = GridView{p->d_grid, nx, ny, nz, origin[0], origin[1], origin[2], 1.0f / spacing};
+  *out = p;
+  return DOCK_OK;
+}
+
+void dock_free_pocket(dock_pocket *p) {
+  if (!p) return;
+  {
+    DeviceGuard g(p->device);
+    if (p->stream) (void)hipStreamSynchronize(p->stream);
+    if (p->d_grid) (void)hipFree(p->d_grid);
+    if (p->ws) (void)hipFree(p->ws);
+    if (p->io) (void)hipFree(p->io);
+    if (p->sync_ws) (void)hipFree(p->sync_ws);
+    if (p->stream) (void)hipStreamDestroy(p->stream);
+    for (hipEvent_t ev : p->ev_sweep)
+      if (ev) (void)hipEventDestroy(ev);
+    if (p->h_pairs) (void)hipHostFree(p->h_pairs);
+  }
+  delete p;
+}
+
+int dock_batch_async(dock_pocket *p, const dock_ligands *ligs, const float *orient, int n_orient,
+                     int angle_steps, const dock_params *prm, dock_results *out, void *workspace,
+                     size_t workspace_bytes, void *stream) {
+  g_last_error.clear();
+  if (!p || !ligs || !orient || !out) return fail(DOCK_E_INVAL, "NULL argument");
+  int rc = check_params(prm, n_orient, angle_steps);
+  if (rc) return rc;
+  if (ligs->n_ligands < 0 || ligs->total_atoms < 0 || ligs->total_rot < 0 || ligs->total_move < 0)
+    return fail(DOCK_E_INVAL, "negative size in ligands");
+  if (ligs->n_ligands > 0 && (!ligs->atom_offset || !ligs->rot_offset || !ligs->xyz))
+    return fail(DOCK_E_INVAL, "ligand array is NULL");
+  if (ligs->total_rot > 0 && (!ligs->rot_axis || !ligs->move_offset))
+    return fail(DOCK_E_INVAL, "rotamer array is NULL");
+  if (ligs->total_move > 0 && !ligs->move_atoms) return fail(DOCK_E_INVAL, "move_atoms is NULL");
+  if (ligs->n_ligands > 0 && (!out->best_score || !out->best_orient || !out->xyz_out))
+    return fail(DOCK_E_INVAL, "result array is NULL");
+  if (ligs->total_rot > 0 && !out->angle_idx) return fail(DOCK_E_INVAL, "angle_idx is NULL");
+  DeviceGuard g(p->device);
+  if (!workspace) {
+    std::lock_guard<std::mutex> lk(p->mu);
+    size_t need = dock_workspace_size(ligs->n_ligands, ligs->total_rot, n_orient, angle_steps,
+                                      prm->passes);
+    rc = grow(&p->ws, &p->ws_bytes, need);
+    if (rc) return rc;
+    return enqueue_batch(p, ligs, orient, n_orient, angle_steps, prm, out, p->ws, p->ws_bytes,
+                         (hipStream_t)stream);
+  }
+  return enqueue_batch(p, ligs, orient, n_orient, angle_steps, prm, out, workspace,
+                       workspace_bytes, (hipStream_t)stream);
+}
+
+int dock_batch(dock_pocket *p, const dock_ligands *ligs, const float *orient, int n_orient,
+               int angle_steps, const dock_params *prm, dock_results *out) {
+  g_last_error.clear();
+  if (!p || !ligs || !orient || !out) return fail(DOCK_E_INVAL, "NULL argument");
+  int rc = check_params(prm, n_orient, angle_steps);
+  if (rc) return rc;
+  int max_n = 0;
+  rc = check_ligands_host(ligs, &max_n);
+  if (rc) return rc;
+  const int64_t L = ligs->n_ligands, NA = ligs->total_atoms, NR = ligs->total_rot,
+                NM = ligs->total_move;
+  const int passes = prm->passes;
+  if (L > 0 && (!out->best_score || !out->best_orient || !out->xyz_out))
+    return fail(DOCK_E_INVAL, "result array is NULL");
+  if (NR > 0 && !out->angle_idx) return fail(DOCK_E_INVAL, "angle_idx is NULL");
+  for (int a = 0; a < n_orient * 12; ++a)
+    if (!std::isfinite(orient[a])) return fail(DOCK_E_INVAL, "orientation table is not finite");
+  for (int64_t a = 0; a < NA * 3; ++a)
+    if (!std::isfinite(ligs->xyz[a])) return fail(DOCK_E_INVAL, "coordinates are not finite");
+  if (L == 0) return DOCK_OK;
+
+  // device staging: inputs then outputs, each 256-B aligned
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = off;
+    off = align_up(off + bytes);
+    return at;
+  };
+  const size_t o_ao = take(4 * (L + 1)), o_xyz = take(12 * NA), o_ro = take(4 * (L + 1)),
+               o_ax = take(8 * NR), o_mo = take(4 * (NR + 1)), o_mv = take(2 * NM),
+               o_or = take(48 * (size_t)n_orient), o_bs = take(4 * L), o_bo = take(4 * L),
+               o_ai = take(2 * NR * passes), o_xo = take(12 * NA),
+               o_as = out->all_scores ? take(4 * L * n_orient) : 0,
+               o_aai = out->all_angle_idx ? take(2 * NR * passes * n_orient) : 0,
+               o_st = take(4 * L);
+  std::lock_guard<std::mutex> lk(p->mu);
+  DeviceGuard g(p->device);
+  rc = grow(&p->io, &p->io_bytes, off);
+  if (rc) return rc;
+  const size_t need_ws = dock_workspace_size((int32_t)L, NR, n_orient, angle_steps, passes);
+  rc = grow(&p->sync_ws, &p->sync_ws_bytes, need_ws);
+  if (rc) return rc;
+  char *d = (char *)p->io;
+  hipStream_t st = p->stream;
+  hipError_t e = hipSuccess;
+  auto h2d = [&](size_t at, const void *src, size_t bytes) {
+    if (e == hipSuccess && bytes) e = hipMemcpyAsync(d + at, src, bytes, hipMemcpyHostToDevice, st);
+  };
+  h2d(o_ao, ligs->atom_offset, 4 * (L + 1));
+  h2d(o_xyz, ligs->xyz, 12 * NA);
+  h2d(o_ro, ligs->rot_offset, 4 * (L + 1));
+  if (NR > 0) {
+    h2d(o_ax, ligs->rot_axis, 8 * NR);
+    h2d(o_mo, ligs->move_offset, 4 * (NR + 1));
+  }
+  if (NM > 0) h2d(o_mv, ligs->move_atoms, 2 * NM);
+  h2d(o_or, orient, 48 * (size_t)n_orient);
+  if (e != hipSuccess) return hip_fail(e, "batch upload");
+  dock_ligands dl = *ligs;
+  dl.atom_offset = (const int32_t *)(d + o_ao);
+  dl.xyz = (const float *)(d + o_xyz);
+  dl.rot_offset = (const int32_t *)(d + o_ro);
+  dl.rot_axis = NR > 0 ? (const int32_t *)(d + o_ax) : nullptr;
+  dl.move_offset = NR > 0 ? (const int32_t *)(d + o_mo) : nullptr;
+  dl.move_atoms = NM > 0 ? (const int16_t *)(d + o_mv) : nullptr;
+  dock_results dr{};
+  dr.best_score = (float *)(d + o_bs);
+  dr.best_orient = (int32_t *)(d + o_bo);
+  dr.angle_idx = NR > 0 ? (int16_t *)(d + o_ai) : nullptr;
+  dr.xyz_out = (float *)(d + o_xo);
+  dr.all_scores = out->all_scores ? (float *)(d + o_as) : nullptr;
+  dr.all_angle_idx = out->all_angle_idx ? (int16_t *)(d + o_aai) : nullptr;
+  dr.status = (int32_t *)(d + o_st);
+  dock_params pr = *prm;
+  pr.max_atoms = max_n;
+  rc = enqueue_batch(p, &dl, (const float *)(d + o_or), n_orient, angle_steps, &pr, &dr,
+                     p->sync_ws, p->sync_ws_bytes, st);
+  if (rc) return rc;
+  auto d2h = [&](void *dst, size_t at, size_t bytes) {
+    if (e == hipSuccess && dst && bytes)
+      e = hipMemcpyAsync(dst, d + at, bytes, hipMemcpyDeviceToHost, st);
+  };
+  d2h(out->best_score, o_bs, 4 * L);
+  d2h(out->best_orient, o_bo, 4 * L);
+  if (NR > 0) d2h(out->angle_idx, o_ai, 2 * NR * passes);
+  d2h(out->xyz_out, o_xo, 12 * NA);
+  if (out->all_scores) d2h(out->all_scores, o_as, 4 * L * n_orient);
+  if (out->all_angle_idx && NR > 0) d2h(out->all_angle_idx, o_aai, 2 * NR * passes * n_orient);
+  d2h(out->status, o_st, 4 * L);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e, "batch run");
+  return DOCK_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,77 @@
+// Internal types shared by the host runtime and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sweep_common.h"
+
+namespace dock {
+
+constexpr int kLptBuckets = 128;
+// small integer block at the head of the workspace:
+//   [0] work-queue counter, [1] rejected-ligand count,
+//   [4, 6) 64-bit count of executed (pair, angle) bump tests,
+//   [64, 64+B) bucket counts, [64+B, 64+2B) bucket cursors
+constexpr int kSmallInts = 64 + 2 * kLptBuckets;
+// pruned sweep: LDS capacity of the per-wave list of pairs that can clash,
+// and the margin (A^2) added to r_bump^2 when dropping pairs that cannot
+constexpr int kPairCap = 128;
+constexpr float kPruneMargin = 1e-3f;
+
+enum SweepMode { kSweepDirect = 0, kSweepPruned = 1 };
+
+struct LigView {
+  int32_t n_ligands;
+  int64_t total_atoms, total_rot, total_move;
+  const int32_t *atom_offset;
+  const float *xyz;
+  const int32_t *rot_offset;
+  const int32_t *rot_axis;
+  const int32_t *move_offset;
+  const int16_t *move_atoms;
+};
+
+struct SweepArgs {
+  GridView grid;
+  LigView lig;
+  const float *orient;  // [n_orient][12]
+  int n_orient;
+  int S;
+  int passes;
+  float r2;             // r_bump^2
+  const float2 *cs;     // [S] (cos, sin) of 2 pi k / S
+  const int32_t *order; // [n_ligands] ligand processed at each slot
+  const int32_t *status;
+  int32_t *small;       // kSmallInts counters (queue at [0])
+  int32_t *queue;
+  int32_t n_items;
+  unsigned long long *pair_tests;  // accumulated once per wave
+  unsigned long long *keys;  // [n_ligands] best (score, orientation) key
+  int16_t *kstar;            // [total_rot * passes * n_orient]
+  float *all_scores;         // optional [n_ligands][n_orient]
+};
+
+struct FinalOut {
+  float *best_score;
+  int32_t *best_orient;
+  int16_t *angle_idx;
+  float *xyz_out;
+};
+
+struct LaunchPlan {
+  int waves_per_block;  // 1, 2 or 4
+  int blocks_per_cu;    // 0 = as many as occupancy allows
+};
+
+hipError_t enqueue_prepare(const SweepArgs &A, int max_atoms, bool lpt, int32_t *bucket_of,
+                           int32_t *counts, int32_t *cursor, int32_t *n_bad,
+                           hipStream_t st);
+hipError_t enqueue_sweep(const SweepArgs &A, int maxn, const LaunchPlan &plan, int n_cu,
+                         hipStream_t st);
+hipError_t enqueue_sweep_pruned(const SweepArgs &A, int max_atoms, const LaunchPlan &plan,
+                                int n_cu, hipStream_t st);
+hipError_t enqueue_finalize(const SweepArgs &A, const FinalOut &F, int maxn, SweepMode mode,
+                            hipStream_t st);
+
+}  // namespace dock

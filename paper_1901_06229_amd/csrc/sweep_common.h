@@ -1,0 +1,157 @@
+// Device helpers shared by the sweep kernels (gfx950, wave64).
+//
+// Every floating-point step a pose goes through (orientation, axis,
+// rotation, voxel index) lives here as one function, so the evaluation of an
+// angle, the application of the chosen angle and the final replay of the
+// winning orientation perform bit-identical arithmetic.  The library is built
+// with -ffp-contract=off; fused multiply-adds appear only where written.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dock {
+
+constexpr int kWave = 64;
+
+struct GridView {
+  const float *grid;
+  int nx, ny, nz;
+  float ox, oy, oz;  // corner of voxel (0,0,0)
+  float inv_h;       // 1 / spacing, rounded to FP32
+};
+
+// Cell containing p: floor((p - o)/h), clamped to the box on each axis.
+__device__ __forceinline__ int voxel_index(const GridView &g, float px, float py,
+                                           float pz) {
+  float fx = floorf((px - g.ox) * g.inv_h);
+  float fy = floorf((py - g.oy) * g.inv_h);
+  float fz = floorf((pz - g.oz) * g.inv_h);
+  fx = fminf(fmaxf(fx, 0.0f), (float)(g.nx - 1));
+  fy = fminf(fmaxf(fy, 0.0f), (float)(g.ny - 1));
+  fz = fminf(fmaxf(fz, 0.0f), (float)(g.nz - 1));
+  return ((int)fz * g.ny + (int)fy) * g.nx + (int)fx;
+}
+
+__device__ __forceinline__ float voxel_value(const GridView &g, float px, float py,
+                                             float pz) {
+  return g.grid[voxel_index(g, px, py, pz)];
+}
+
+// Rigid starting pose X = R x + t (row-major R).
+__device__ __forceinline__ float3 orient_point(const float *T, float x, float y,
+                                               float z) {
+  float3 r;
+  r.x = fmaf(T[0], x, fmaf(T[1], y, fmaf(T[2], z, T[9])));
+  r.y = fmaf(T[3], x, fmaf(T[4], y, fmaf(T[5], z, T[10])));
+  r.z = fmaf(T[6], x, fmaf(T[7], y, fmaf(T[8], z, T[11])));
+  return r;
+}
+
+// Unit bond axis from a to b.
+__device__ __forceinline__ float3 bond_axis(float4 xa, float4 xb) {
+  float dx = xb.x - xa.x, dy = xb.y - xa.y, dz = xb.z - xa.z;
+  float len2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+  float inv = 1.0f / sqrtf(len2);
+  return make_float3(dx * inv, dy * inv, dz * inv);
+}
+
+// Rodrigues rotation of x about unit axis u through a, by the angle with
+// cosine c and sine s:  Y = a + c v + s (u x v) + (1 - c)(u . v) u, v = x - a.
+__device__ __forceinline__ float3 rodrigues(float4 x, float4 a, float3 u, float c,
+                                            float s) {
+  float vx = x.x - a.x, vy = x.y - a.y, vz = x.z - a.z;
+  float cx = u.y * vz - u.z * vy;
+  float cy = u.z * vx - u.x * vz;
+  float cz = u.x * vy - u.y * vx;
+  float udv = fmaf(u.x, vx, fmaf(u.y, vy, u.z * vz));
+  float w = (1.0f - c) * udv;
+  float3 y;
+  y.x = fmaf(w, u.x, fmaf(s, cx, fmaf(c, vx, a.x)));
+  y.y = fmaf(w, u.y, fmaf(s, cy, fmaf(c, vy, a.y)));
+  y.z = fmaf(w, u.z, fmaf(s, cz, fmaf(c, vz, a.z)));
+  return y;
+}
+
+// Cylindrical decomposition of x about the axis (a, u): axial coordinate
+// z = (x - a).u and radial vector r = (x - a) - z u.  A rotation by theta
+// moves x to  a + z u + cos(theta) r + sin(theta) (u x r)  -- the same
+// Rodrigues rotation, with the parts that do not depend on theta factored
+// out once per rotamer.
+struct Cyl {
+  float rx, ry, rz, z;
+};
+
+__device__ __forceinline__ Cyl cyl_of(float4 x, float4 a, float3 u) {
+  float vx = x.x - a.x, vy = x.y - a.y, vz = x.z - a.z;
+  float z = fmaf(u.x, vx, fmaf(u.y, vy, u.z * vz));
+  Cyl c;
+  c.rx = fmaf(-z, u.x, vx);
+  c.ry = fmaf(-z, u.y, vy);
+  c.rz = fmaf(-z, u.z, vz);
+  c.z = z;
+  return c;
+}
+
+// Angle-independent parts of the rotation of one atom: p = a + z u (on the
+// axis), e = r, f = u x r.
+struct RotBasis {
+  float px, py, pz, ex, ey, ez, fx, fy, fz;
+};
+
+__device__ __forceinline__ RotBasis rot_basis(Cyl c, float4 a, float3 u) {
+  RotBasis b;
+  b.px = fmaf(c.z, u.x, a.x);
+  b.py = fmaf(c.z, u.y, a.y);
+  b.pz = fmaf(c.z, u.z, a.z);
+  b.ex = c.rx;
+  b.ey = c.ry;
+  b.ez = c.rz;
+  b.fx = u.y * c.rz - u.z * c.ry;
+  b.fy = u.z * c.rx - u.x * c.rz;
+  b.fz = u.x * c.ry - u.y * c.rx;
+  return b;
+}
+
+__device__ __forceinline__ float3 rot_apply(const RotBasis &b, float c, float s) {
+  return make_float3(fmaf(s, b.fx, fmaf(c, b.ex, b.px)), fmaf(s, b.fy, fmaf(c, b.ey, b.py)),
+                     fmaf(s, b.fz, fmaf(c, b.ez, b.pz)));
+}
+
+// Orderable encoding of an FP32 value (monotone as an unsigned integer).
+__device__ __forceinline__ uint32_t float_order(float f) {
+  uint32_t b = __float_as_uint(f);
+  return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+__device__ __forceinline__ float order_float(uint32_t o) {
+  uint32_t b = (o & 0x80000000u) ? (o & 0x7FFFFFFFu) : ~o;
+  return __uint_as_float(b);
+}
+
+// Key for "highest score, then lowest index": (order(score), ~index).
+__device__ __forceinline__ uint64_t best_key(float score, uint32_t idx) {
+  return ((uint64_t)float_order(score) << 32) | (uint64_t)(0xFFFFFFFFu - idx);
+}
+__device__ __forceinline__ uint32_t key_index(uint64_t key) {
+  return 0xFFFFFFFFu - (uint32_t)(key & 0xFFFFFFFFu);
+}
+__device__ __forceinline__ float key_score(uint64_t key) {
+  return order_float((uint32_t)(key >> 32));
+}
+
+__device__ __forceinline__ uint64_t wave_max_u64(uint64_t v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    uint64_t o = __shfl_xor(v, off, kWave);
+    v = o > v ? o : v;
+  }
+  return v;
+}
+
+// Order LDS traffic between lanes of one wave (no cross-wave barrier).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+}  // namespace dock

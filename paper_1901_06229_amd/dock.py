@@ -1,0 +1,240 @@
+"""Python binding of libdock.so (include/dock.h): argument marshalling only.
+
+Every step of the sweep runs in the HIP library.  There is no CPU fallback:
+if ``libdock.so`` is missing or cannot be loaded, every call raises.
+torch is used only for device memory and streams (``dock_batch_async``).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+from .build import LIB_PATH
+
+DOCK_OK, DOCK_E_INVAL, DOCK_E_LIMIT, DOCK_E_NOMEM, DOCK_E_DEVICE, DOCK_E_CANCELLED, DOCK_E_STATE = \
+    0, -1, -2, -3, -4, -5, -6
+DOCK_MODE_PLAIN, DOCK_MODE_LEARNED = 0, 1
+DOCK_FLAG_NO_LPT = 1
+DOCK_FLAG_TIME_SWEEP = 2
+DOCK_FLAG_DIRECT_BUMP = 4
+DOCK_MAX_ATOMS, DOCK_MAX_ROT, DOCK_MAX_STEPS = 256, 255, 4096
+
+_P = ctypes.c_void_p
+
+
+class dock_ligands(ctypes.Structure):
+    _fields_ = [("n_ligands", ctypes.c_int32), ("total_atoms", ctypes.c_int64),
+                ("total_rot", ctypes.c_int64), ("total_move", ctypes.c_int64),
+                ("atom_offset", _P), ("xyz", _P), ("rot_offset", _P), ("rot_axis", _P),
+                ("move_offset", _P), ("move_atoms", _P)]
+
+
+class dock_params(ctypes.Structure):
+    _fields_ = [("r_bump", ctypes.c_float), ("passes", ctypes.c_int32), ("mode", ctypes.c_int32),
+                ("top_k", ctypes.c_int32), ("margin", ctypes.c_float), ("flags", ctypes.c_uint32),
+                ("max_atoms", ctypes.c_int32)]
+
+
+class dock_results(ctypes.Structure):
+    _fields_ = [("best_score", _P), ("best_orient", _P), ("angle_idx", _P), ("xyz_out", _P),
+                ("all_scores", _P), ("all_angle_idx", _P), ("status", _P), ("n_fallback", _P)]
+
+
+class DockError(RuntimeError):
+    def __init__(self, code: int, where: str, detail: str):
+        super().__init__(f"{where}: {detail or 'error'} (code {code})")
+        self.code = code
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libdock.so; raises if it is not built (no fallback path exists)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is not built: run __graft_entry__.build() first")
+    lib = ctypes.CDLL(path)
+    c = ctypes
+    lib.dock_init_pocket.argtypes = [_P, c.c_int, c.c_int, c.c_int, _P, c.c_float, c.POINTER(_P)]
+    lib.dock_init_pocket.restype = c.c_int
+    lib.dock_free_pocket.argtypes = [_P]
+    lib.dock_free_pocket.restype = None
+    lib.dock_batch.argtypes = [_P, c.POINTER(dock_ligands), _P, c.c_int, c.c_int,
+                               c.POINTER(dock_params), c.POINTER(dock_results)]
+    lib.dock_batch.restype = c.c_int
+    lib.dock_batch_async.argtypes = [_P, c.POINTER(dock_ligands), _P, c.c_int, c.c_int,
+                                     c.POINTER(dock_params), c.POINTER(dock_results), _P,
+                                     c.c_size_t, _P]
+    lib.dock_batch_async.restype = c.c_int
+    lib.dock_workspace_size.argtypes = [c.c_int32, c.c_int64, c.c_int, c.c_int, c.c_int]
+    lib.dock_workspace_size.restype = c.c_size_t
+    lib.dock_last_sweep_ms.argtypes = [_P, c.POINTER(c.c_float)]
+    lib.dock_last_sweep_ms.restype = c.c_int
+    lib.dock_last_sweep_pairs.argtypes = [_P, c.POINTER(c.c_uint64)]
+    lib.dock_last_sweep_pairs.restype = c.c_int
+    lib.dock_set_launch.argtypes = [_P, c.c_int, c.c_int]
+    lib.dock_set_launch.restype = c.c_int
+    lib.dock_strerror.argtypes = [c.c_int]
+    lib.dock_strerror.restype = c.c_char_p
+    lib.dock_last_error.argtypes = []
+    lib.dock_last_error.restype = c.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(rc: int, where: str):
+    if rc != DOCK_OK:
+        lib = load_library()
+        raise DockError(rc, where, (lib.dock_last_error() or b"").decode() or
+                        lib.dock_strerror(rc).decode())
+
+
+def _np_ptr(a):
+    return None if a is None else a.ctypes.data_as(_P)
+
+
+def _c(a, dt):
+    return np.ascontiguousarray(a, dtype=dt)
+
+
+class Pocket:
+    """Owns a dock_pocket handle (device copy of the grid)."""
+
+    def __init__(self, handle, dims, origin, spacing):
+        self.handle = handle
+        self.dims = dims
+        self.origin = origin
+        self.spacing = spacing
+
+    def close(self):
+        if self.handle:
+            load_library().dock_free_pocket(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def dock_init_pocket(grid: np.ndarray, origin, spacing: float) -> Pocket:
+    """grid: [nz, ny, nx] float32 (x fastest)."""
+    lib = load_library()
+    g = _c(grid, np.float32)
+    nz, ny, nx = g.shape
+    o = _c(origin, np.float32)
+    h = _P()
+    _check(lib.dock_init_pocket(_np_ptr(g), nx, ny, nz, _np_ptr(o), float(spacing),
+                                ctypes.byref(h)), "dock_init_pocket")
+    return Pocket(h, (nx, ny, nz), o.copy(), float(spacing))
+
+
+def dock_free_pocket(p: Pocket):
+    p.close()
+
+
+def make_params(r_bump=2.0, passes=1, mode=DOCK_MODE_PLAIN, top_k=16, margin=0.0, flags=0,
+                max_atoms=0) -> dock_params:
+    return dock_params(float(r_bump), int(passes), int(mode), int(top_k), float(margin),
+                       int(flags), int(max_atoms))
+
+
+def dock_batch(pocket: Pocket, ligs, orient, angle_steps: int, r_bump: float = 2.0,
+               passes: int = 1, mode: int = DOCK_MODE_PLAIN, top_k: int = 16,
+               margin: float = 0.0, flags: int = 0, want_all: bool = False) -> dict:
+    """Synchronous batch on host arrays (``ligs``: any object with the CSR fields)."""
+    lib = load_library()
+    ao = _c(ligs.atom_offset, np.int32)
+    xyz = _c(ligs.xyz, np.float32)
+    ro = _c(ligs.rot_offset, np.int32)
+    ax = _c(ligs.rot_axis, np.int32)
+    mo = _c(ligs.move_offset, np.int32)
+    mv = _c(ligs.move_atoms, np.int16)
+    orient = _c(orient, np.float32).reshape(-1, 12)
+    L, O = len(ao) - 1, orient.shape[0]
+    NA, NR = int(ao[-1]) if L else 0, int(ro[-1]) if L else 0
+    NM = int(mo[NR]) if NR else 0
+    dl = dock_ligands(L, NA, NR, NM, _np_ptr(ao), _np_ptr(xyz), _np_ptr(ro), _np_ptr(ax),
+                      _np_ptr(mo), _np_ptr(mv))
+    out = dict(best_score=np.empty(L, np.float32), best_orient=np.empty(L, np.int32),
+               angle_idx=np.empty(max(NR * passes, 1), np.int16),
+               xyz=np.empty((max(NA, 1), 3), np.float32), status=np.empty(max(L, 1), np.int32))
+    if want_all:
+        out["all_scores"] = np.empty((L, O), np.float32)
+        out["all_angle_idx"] = np.empty(max(NR * passes * O, 1), np.int16)
+    if mode == DOCK_MODE_LEARNED:
+        out["n_fallback"] = np.empty(max(L, 1), np.int32)
+    dr = dock_results(_np_ptr(out["best_score"]), _np_ptr(out["best_orient"]),
+                      _np_ptr(out["angle_idx"]), _np_ptr(out["xyz"]),
+                      _np_ptr(out.get("all_scores")), _np_ptr(out.get("all_angle_idx")),
+                      _np_ptr(out["status"]), _np_ptr(out.get("n_fallback")))
+    prm = make_params(r_bump, passes, mode, top_k, margin, flags)
+    _check(lib.dock_batch(pocket.handle, ctypes.byref(dl), _np_ptr(orient), O, int(angle_steps),
+                          ctypes.byref(prm), ctypes.byref(dr)), "dock_batch")
+    out["angle_idx"] = out["angle_idx"][:NR * passes]
+    out["xyz"] = out["xyz"][:NA]
+    out["status"] = out["status"][:L]
+    if want_all:
+        out["all_angle_idx"] = out["all_angle_idx"][:NR * passes * O]
+    return out
+
+
+def dock_workspace_size(n_ligands: int, total_rot: int, n_orient: int, angle_steps: int,
+                        passes: int = 1) -> int:
+    return int(load_library().dock_workspace_size(n_ligands, total_rot, n_orient, angle_steps,
+                                                  passes))
+
+
+def dock_last_sweep_ms(pocket: Pocket) -> float:
+    ms = ctypes.c_float()
+    _check(load_library().dock_last_sweep_ms(pocket.handle, ctypes.byref(ms)), "dock_last_sweep_ms")
+    return float(ms.value)
+
+
+def dock_last_sweep_pairs(pocket: Pocket) -> int:
+    v = ctypes.c_uint64()
+    _check(load_library().dock_last_sweep_pairs(pocket.handle, ctypes.byref(v)),
+           "dock_last_sweep_pairs")
+    return int(v.value)
+
+
+def dock_set_launch(pocket: Pocket, waves_per_block: int, blocks_per_cu: int = 0):
+    _check(load_library().dock_set_launch(pocket.handle, int(waves_per_block), int(blocks_per_cu)),
+           "dock_set_launch")
+
+
+def _tptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def dock_batch_async(pocket: Pocket, dev: dict, orient_dev, angle_steps: int, out: dict,
+                     params: dock_params, workspace=None, stream=None):
+    """Enqueue a batch whose arrays are device tensors (torch) on ``stream``.
+
+    dev: atom_offset, xyz, rot_offset, rot_axis, move_offset, move_atoms (device
+    tensors) and the python ints n_ligands, total_atoms, total_rot, total_move.
+    out: best_score, best_orient, angle_idx, xyz (device tensors) and optional
+    all_scores, all_angle_idx, status, n_fallback.
+    """
+    lib = load_library()
+    dl = dock_ligands(int(dev["n_ligands"]), int(dev["total_atoms"]), int(dev["total_rot"]),
+                      int(dev["total_move"]), _tptr(dev["atom_offset"]), _tptr(dev["xyz"]),
+                      _tptr(dev["rot_offset"]), _tptr(dev.get("rot_axis")),
+                      _tptr(dev.get("move_offset")), _tptr(dev.get("move_atoms")))
+    dr = dock_results(_tptr(out["best_score"]), _tptr(out["best_orient"]),
+                      _tptr(out.get("angle_idx")), _tptr(out["xyz"]),
+                      _tptr(out.get("all_scores")), _tptr(out.get("all_angle_idx")),
+                      _tptr(out.get("status")), _tptr(out.get("n_fallback")))
+    n_orient = int(orient_dev.shape[0])
+    ws_ptr = _tptr(workspace)
+    ws_bytes = 0 if workspace is None else workspace.numel() * workspace.element_size()
+    st = None if stream is None else ctypes.c_void_p(stream.cuda_stream)
+    _check(lib.dock_batch_async(pocket.handle, ctypes.byref(dl), _tptr(orient_dev), n_orient,
+                                int(angle_steps), ctypes.byref(params), ctypes.byref(dr), ws_ptr,
+                                ws_bytes, st), "dock_batch_async")

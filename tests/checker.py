@@ -1,0 +1,175 @@
+"""Ambiguity-aware replay checker: GPU sweep vs the FP64 reference.
+
+A voxel lookup and the bump threshold are step functions, so an FP32 pose can
+land on the other side of a voxel face or of r_bump than the FP64 pose.  The
+checker therefore replays the reference along the GPU's own angle choices and
+accepts a different choice at a step only when
+  * the reference's score gap between the two angles is <= 1e-5 max(|s|, 1)
+    (a tie in FP32 terms), or
+  * the reference marks one of the two angles as ambiguous: an atom within
+    1e-4 A of a voxel face whose alternative voxel closes the gap, or a cross
+    pair within 1e-4 A of r_bump.
+Coordinates must then match within 1e-4 A and scores within 1e-5 relative
+(or inside the reference's ambiguity interval).
+"""
+from __future__ import annotations
+
+from collections import Counter
+from concurrent.futures import ThreadPoolExecutor
+from dataclasses import dataclass, field
+
+import numpy as np
+
+import oracle
+
+COORD_TOL = 1e-4
+REL_TOL = 1e-5
+
+V, VAMB, SAMB = oracle.FLAG_VALID, oracle.FLAG_VAMB, oracle.FLAG_SAMB
+
+
+def tol_of(s: float) -> float:
+    return REL_TOL * max(abs(s), 1.0)
+
+
+@dataclass
+class Report:
+    steps: Counter = field(default_factory=Counter)
+    failures: list = field(default_factory=list)
+    items: int = 0
+    max_coord_err: float = 0.0
+    max_score_rel: float = 0.0
+
+    def ok(self) -> bool:
+        return not self.failures
+
+    def summary(self) -> str:
+        return (f"items={self.items} steps={dict(self.steps)} max|dx|={self.max_coord_err:.2e} "
+                f"max score rel={self.max_score_rel:.2e} failures={len(self.failures)} "
+                f"{self.failures[:5]}")
+
+
+def classify_step(tr, s: int, kg: int) -> str | None:
+    """'exact' / 'tie' / 'ambiguous', or None if the GPU choice is not acceptable."""
+    ko = int(tr.k_star[s])
+    if kg == ko:
+        return "exact"
+    f, sc, lo, hi = tr.prof_flags[s], tr.prof_s[s], tr.prof_lo[s], tr.prof_hi[s]
+    if kg == -1:
+        clearly_valid = (f & V) & ~((f & VAMB) >> 1)
+        return "ambiguous" if not clearly_valid.any() else None
+    if kg < 0 or kg >= len(f):
+        return None
+    if ko == -1:
+        return "ambiguous" if f[kg] & VAMB else None
+    if not (f[kg] & V) and not (f[kg] & VAMB):
+        return None
+    tol = tol_of(sc[ko])
+    if (f[kg] & V) and sc[ko] - sc[kg] <= tol:
+        return "tie"
+    if hi[kg] + tol >= lo[ko]:
+        return "ambiguous"
+    if f[ko] & VAMB:
+        return "ambiguous"
+    return None
+
+
+def check_item(pocket, lig, orient, S, r_bump, passes, gpu_k, gpu_score, gpu_xyz=None):
+    """Replay one item along the GPU's choices; returns (counts, failures, dx, rel)."""
+    tr = oracle.trace_item(pocket, lig, orient, S, r_bump, passes, forced_k=gpu_k)
+    counts, fails = Counter(), []
+    for s, kg in enumerate(gpu_k):
+        c = classify_step(tr, s, int(kg))
+        if c is None:
+            fails.append(("step", s, int(kg), int(tr.k_star[s])))
+        else:
+            counts[c] += 1
+    tol = tol_of(tr.score)
+    rel = abs(gpu_score - tr.score) / max(abs(tr.score), 1.0)
+    if abs(gpu_score - tr.score) > tol and not (tr.score_lo - tol <= gpu_score <= tr.score_hi + tol):
+        fails.append(("score", float(gpu_score), tr.score, tr.score_lo, tr.score_hi))
+    dx = 0.0
+    if gpu_xyz is not None:
+        dx = float(np.abs(np.asarray(gpu_xyz, np.float64) - tr.xyz).max()) if len(tr.xyz) else 0.0
+        if dx > COORD_TOL:
+            fails.append(("coords", dx))
+    return counts, fails, dx, rel
+
+
+def item_steps(ligs, l, o, O, passes, all_angle_idx):
+    R = ligs.n_rot(l)
+    base = (int(ligs.rot_offset[l]) * O + o * R) * passes
+    return all_angle_idx[base:base + R * passes]
+
+
+def check_batch(pocket, ligs, orient, S, res, r_bump=2.0, passes=1, ligands=None,
+                orients=None, threads=8) -> Report:
+    """Check GPU results ``res`` (dock_batch output with want_all=True).
+
+    ligands: ligand indices to check (default all); orients: orientation
+    indices per ligand (default all) -- the winning orientation is always
+    checked, including its final coordinates.
+    """
+    O = orient.shape[0]
+    rep = Report()
+    ligands = range(ligs.n_ligands) if ligands is None else ligands
+    jobs = []
+    for l in ligands:
+        l = int(l)
+        lig = ligs.ligand(l)
+        ob = int(res["best_orient"][l])
+        if ob < 0:
+            rep.failures.append(("rejected", l))
+            continue
+        osel = set(range(O) if orients is None else (int(x) for x in orients)) | {ob}
+        for o in sorted(osel):
+            k = item_steps(ligs, l, o, O, passes, res["all_angle_idx"])
+            xyz = None
+            if o == ob:
+                a0, a1 = ligs.atom_offset[l], ligs.atom_offset[l + 1]
+                xyz = res["xyz"][a0:a1]
+            jobs.append((l, o, lig, k, float(res["all_scores"][l, o]), xyz))
+
+    def run(job):
+        l, o, lig, k, sc, xyz = job
+        return (l, o) + check_item(pocket, lig, orient[o], S, r_bump, passes, k, sc, xyz)
+
+    with ThreadPoolExecutor(max(1, threads)) as ex:
+        for l, o, counts, fails, dx, rel in ex.map(run, jobs):
+            rep.items += 1
+            rep.steps.update(counts)
+            rep.max_coord_err = max(rep.max_coord_err, dx)
+            rep.max_score_rel = max(rep.max_score_rel, rel)
+            rep.failures.extend((l, o) + f for f in fails)
+    # per-ligand reduction: GPU's own argmax over its scores, lowest index on ties
+    for l in ligands:
+        l = int(l)
+        s = res["all_scores"][l]
+        ob = int(res["best_orient"][l])
+        if ob >= 0 and (ob != int(np.argmax(s)) or res["best_score"][l] != s[ob]):
+            rep.failures.append(("best_orient", l, ob, int(np.argmax(s))))
+        R = ligs.n_rot(l)
+        if ob >= 0 and R:
+            a = res["angle_idx"][int(ligs.rot_offset[l]) * passes:][:R * passes]
+            if not np.array_equal(a, item_steps(ligs, l, ob, O, passes, res["all_angle_idx"])):
+                rep.failures.append(("angle_idx", l))
+    return rep
+
+
+def check_best_orientation(pocket, ligs, orient, S, res, ref, r_bump=2.0, ligands=None) -> list:
+    """The GPU's winning orientation must be a reference winner up to ties or
+    ambiguity: reference S(o*_gpu) within tolerance of the reference best."""
+    bad = []
+    ligands = range(ligs.n_ligands) if ligands is None else ligands
+    for l in ligands:
+        l = int(l)
+        og, oo = int(res["best_orient"][l]), int(ref.best_orient[l])
+        if og == oo:
+            continue
+        sg, so = ref.all_scores[l, og], ref.all_scores[l, oo]
+        if so - sg <= tol_of(so):
+            continue
+        # the two items' GPU scores disagree with the reference ordering: only
+        # acceptable if the GPU trajectory itself was ambiguity-accepted
+        bad.append((l, og, oo, float(sg), float(so)))
+    return bad

@@ -1,0 +1,219 @@
+"""GPU sweep vs the FP64 reference through the C-ABI (libdock.so).
+
+Every item (ligand x orientation) checked here is replayed by the reference
+along the GPU's own angle choices (tests/checker.py): the bar is 1e-4 A on
+coordinates, 1e-5 relative on scores and the same angle indices except at
+reference gaps below 1e-5 or at recorded FP32/FP64 ambiguities.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1901_06229_amd import dock, synth
+from tests.checker import check_batch, tol_of
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pockets():
+    cache = {}
+
+    def get(cfg):
+        if cfg not in cache:
+            p = synth.pocket(cfg)
+            cache[cfg] = (p, dock.dock_init_pocket(p.grid, p.origin, p.spacing))
+        return cache[cfg]
+    yield get
+    for _, h in cache.values():
+        h.close()
+
+
+def _run(pockets, cfg, ligs, orient, S, **kw):
+    p, h = pockets(cfg)
+    print(f"[gpu] config {cfg}: {ligs.n_ligands} ligands x {orient.shape[0]} orientations, S={S}",
+          flush=True)
+    res = dock.dock_batch(h, ligs, orient, S, want_all=True, **kw)
+    return p, res
+
+
+def test_c1_parity(pockets):
+    ligs = synth.ligands(1)
+    orient = synth.orientations(1)
+    p, res = _run(pockets, 1, ligs, orient, 64)
+    rep = check_batch(p, ligs, orient, 64, res)
+    print(rep.summary())
+    assert rep.ok(), rep.summary()
+    ref = oracle.dock_batch(p, ligs, orient, 64)
+    assert abs(res["best_score"][0] - ref.best_score[0]) <= tol_of(ref.best_score[0])
+    assert np.abs(res["all_scores"] - ref.all_scores).max() <= tol_of(np.abs(ref.all_scores).max())
+    assert (res["status"] == 0).all()
+
+
+def test_c2_subset_parity(pockets):
+    """C2 shapes (128^3 pocket, 256 orientations, 256 steps) on 200 ligands:
+    every orientation of 6 ligands, 8 sampled orientations of all 200."""
+    ligs = synth.ligands(2, count=200)
+    orient = synth.orientations(2)
+    p, res = _run(pockets, 2, ligs, orient, 256)
+    assert (res["status"] == 0).all()
+    rep = check_batch(p, ligs, orient, 256, res, ligands=range(6))
+    print(rep.summary())
+    assert rep.ok(), rep.summary()
+    rng = np.random.default_rng(0)
+    rep2 = check_batch(p, ligs, orient, 256, res, ligands=range(200),
+                       orients=rng.choice(256, 8, replace=False))
+    print(rep2.summary())
+    assert rep2.ok(), rep2.summary()
+    amb = rep2.steps["ambiguous"] / max(1, sum(rep2.steps.values()))
+    assert amb < 0.01
+
+
+def test_c3_subset_parity(pockets):
+    """C3 shapes (lognormal sizes 8-150, 0-40 rotamers, 128 orientations, 128 steps)."""
+    ligs = synth.ligands(3, count=300)
+    orient = synth.orientations(3)
+    p, res = _run(pockets, 3, ligs, orient, 128)
+    rng = np.random.default_rng(1)
+    rep = check_batch(p, ligs, orient, 128, res, ligands=range(300),
+                      orients=rng.choice(128, 4, replace=False))
+    print(rep.summary())
+    assert rep.ok(), rep.summary()
+
+
+def test_c5_subset_parity(pockets):
+    """C5 shapes (256^3 irregular pocket, 100-250 atoms, 60-120 rotamers, 360 steps)."""
+    ligs = synth.ligands(5, count=12)
+    orient = synth.orientations(5)
+    p, res = _run(pockets, 5, ligs, orient, 360)
+    rng = np.random.default_rng(2)
+    rep = check_batch(p, ligs, orient, 360, res, ligands=range(12),
+                      orients=rng.choice(64, 2, replace=False))
+    print(rep.summary())
+    assert rep.ok(), rep.summary()
+
+
+def test_determinism_and_order_independence(pockets):
+    ligs = synth.ligands(2, count=300, first=1000)
+    orient = synth.orientations(2, 64)
+    p, a = _run(pockets, 2, ligs, orient, 128)
+    _, b = _run(pockets, 2, ligs, orient, 128)
+    _, c = _run(pockets, 2, ligs, orient, 128, flags=dock.DOCK_FLAG_NO_LPT)
+    for k in ("best_score", "best_orient", "angle_idx", "xyz", "all_scores", "all_angle_idx"):
+        assert np.array_equal(a[k], b[k]), k
+        assert np.array_equal(a[k], c[k]), k
+
+
+def test_edge_cases(pockets):
+    p, h = pockets(1)
+    base = synth.ligands(1)
+    lig = base.ligand(0)
+    n = len(lig["xyz"])
+    no_rot = dict(xyz=lig["xyz"], rot_axis=np.zeros((0, 2), np.int32),
+                  move_offset=np.zeros(1, np.int32), move_atoms=np.zeros(0, np.int16))
+    one_atom = dict(xyz=lig["xyz"][:1], rot_axis=np.zeros((0, 2), np.int32),
+                    move_offset=np.zeros(1, np.int32), move_atoms=np.zeros(0, np.int16))
+    ligs = synth.Ligands.from_parts([lig, no_rot, one_atom, lig])
+    orient = synth.orientations(1, 3)
+    for S in (1, 2, 63, 64, 65, 200):
+        res = dock.dock_batch(h, ligs, orient, S, want_all=True)
+        rep = check_batch(p, ligs, orient, S, res)
+        assert rep.ok(), (S, rep.summary())
+        assert np.array_equal(res["best_score"][0], res["best_score"][3])
+    # a bump radius so large that no angle (not even k = 0) is valid: k* = -1, no move
+    res = dock.dock_batch(h, ligs, orient, 16, r_bump=50.0, want_all=True)
+    assert (res["angle_idx"] == -1).all()
+    rep = check_batch(p, ligs, orient, 16, res, r_bump=50.0)
+    assert rep.ok(), rep.summary()
+    # empty batch
+    empty = synth.Ligands.from_parts([])
+    res = dock.dock_batch(h, empty, orient, 16)
+    assert res["best_score"].shape == (0,)
+
+
+def test_max_size_ligand(pockets):
+    """A 256-atom ligand (the per-ligand maximum) with 255 rotamers."""
+    p, h = pockets(5)
+    big = synth.ligands(5, count=40)
+    l = int(np.argmax(np.diff(big.atom_offset)))
+    lig = big.ligand(l)
+    n = len(lig["xyz"])
+    # pad to 256 atoms with far-away isolated atoms and repeat rotamers up to 255
+    extra = 256 - n
+    far = np.stack([np.array([30.0, 30.0, 30.0]) + 3.0 * np.array([i % 6, (i // 6) % 6, i // 36])
+                    for i in range(extra)]).astype(np.float32)
+    R = len(lig["rot_axis"])
+    reps = [r % R for r in range(255)]
+    moff = [0]
+    mv = []
+    for r in reps:
+        seg = lig["move_atoms"][lig["move_offset"][r]:lig["move_offset"][r + 1]]
+        mv.extend(seg.tolist())
+        moff.append(len(mv))
+    big_lig = dict(xyz=np.concatenate([lig["xyz"], far]), rot_axis=lig["rot_axis"][reps],
+                   move_offset=np.asarray(moff, np.int32), move_atoms=np.asarray(mv, np.int16))
+    ligs = synth.Ligands.from_parts([big_lig])
+    orient = synth.orientations(5, 2)
+    res = dock.dock_batch(h, ligs, orient, 32, want_all=True)
+    rep = check_batch(p, ligs, orient, 32, res)
+    print(rep.summary())
+    assert rep.ok(), rep.summary()
+
+
+def test_passes_refinement(pockets):
+    """num_repetitions > 1 (paper Listing 1): the sweep over all rotamers repeats."""
+    p, res = None, None
+    ligs = synth.ligands(2, count=20, first=50)
+    orient = synth.orientations(2, 8)
+    p, res = _run(pockets, 2, ligs, orient, 64, passes=3)
+    rep = check_batch(p, ligs, orient, 64, res, passes=3)
+    print(rep.summary())
+    assert rep.ok(), rep.summary()
+
+
+def test_invalid_inputs_rejected_before_launch(pockets):
+    p, h = pockets(1)
+    lig = synth.ligands(1).ligand(0)
+    bad = dict(lig)
+    bad["move_atoms"] = lig["move_atoms"].copy()
+    bad["move_atoms"][0] = 99
+    ligs = synth.Ligands.from_parts([bad])
+    with pytest.raises(dock.DockError) as e:
+        dock.dock_batch(h, ligs, synth.orientations(1), 16)
+    assert e.value.code == dock.DOCK_E_INVAL
+    with pytest.raises(dock.DockError) as e:
+        dock.dock_batch(h, synth.ligands(1), synth.orientations(1), 5000)
+    assert e.value.code == dock.DOCK_E_LIMIT
+
+
+def test_direct_bump_mode_parity(pockets):
+    """The literal form (every cross pair tested at every angle) on the same
+    inputs, checked against the reference like the default kernel."""
+    ligs = synth.ligands(2, count=40, first=300)
+    orient = synth.orientations(2, 32)
+    p, res = _run(pockets, 2, ligs, orient, 256, flags=dock.DOCK_FLAG_DIRECT_BUMP)
+    rep = check_batch(p, ligs, orient, 256, res, ligands=range(40), orients=range(0, 32, 4))
+    print(rep.summary())
+    assert rep.ok(), rep.summary()
+    ligs1 = synth.ligands(1)
+    o1 = synth.orientations(1)
+    p1, r1 = _run(pockets, 1, ligs1, o1, 64, flags=dock.DOCK_FLAG_DIRECT_BUMP)
+    rep = check_batch(p1, ligs1, o1, 64, r1)
+    assert rep.ok(), rep.summary()
+
+
+def test_results_independent_of_launch_mapping(pockets):
+    """Bitwise-identical results for every waves-per-block / blocks-per-CU plan."""
+    p, h = pockets(2)
+    ligs = synth.ligands(2, count=150, first=2000)
+    orient = synth.orientations(2, 32)
+    ref = None
+    for waves, bpc in ((4, 0), (1, 0), (2, 1), (4, 2), (1, 3)):
+        dock.dock_set_launch(h, waves, bpc)
+        res = dock.dock_batch(h, ligs, orient, 128, want_all=True)
+        if ref is None:
+            ref = res
+            continue
+        for k in ("best_score", "best_orient", "angle_idx", "xyz", "all_scores", "all_angle_idx"):
+            assert np.array_equal(ref[k], res[k]), (waves, bpc, k)
+    dock.dock_set_launch(h, 4, 0)
