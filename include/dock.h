@@ -63,6 +63,10 @@ extern "C" {
                                    (read with dock_last_sweep_ms)           */
 #define DOCK_FLAG_DIRECT_BUMP 4u /* test every cross pair at every angle
                                     (default: only pairs that can clash)    */
+#define DOCK_FLAG_GRAPH 8u       /* dock_batch_async: capture the launch
+                                    sequence in a HIP graph and replay it
+                                    while arguments repeat (needs a
+                                    non-default stream)                      */
 
 typedef struct dock_pocket dock_pocket;
 
@@ -130,7 +134,7 @@ typedef struct {
  * is loaded once; §4.1: the constructor copies data to the device).
  *   grid[nz][ny][nx]   host FP32 values, x fastest; voxel (ix,iy,iz) covers
  *                      origin + [i, i+1) * spacing on each axis
- *   1 <= nx,ny,nz <= 4096, spacing > 0.
+ *   1 <= nx,ny,nz <= 4096, nx*ny*nz < 2^30, spacing > 0.
  * On success *out owns a device copy; the host array may be freed.
  * Errors: DOCK_E_INVAL, DOCK_E_LIMIT, DOCK_E_NOMEM, DOCK_E_DEVICE. */
 int dock_init_pocket(const float *grid, int nx, int ny, int nz,
@@ -175,12 +179,31 @@ int dock_last_sweep_ms(dock_pocket *p, float *ms);
  * clash; direct mode: not counted, 0).  Waits for that call's sweep. */
 int dock_last_sweep_pairs(dock_pocket *p, uint64_t *pair_angle_tests);
 
-/* Launch mapping of the sweep kernel for calls on this handle (the knob the
+/* Launch mapping of the sweep kernel for calls on this handle (the knobs the
  * autotuner turns): waves_per_block in {1, 2, 4}, each wave working on its
  * own (ligand, orientation) items; blocks_per_cu >= 0 caps resident blocks
- * per compute unit (0: occupancy limit).  Results do not depend on it.
- * Errors: DOCK_E_INVAL. */
-int dock_set_launch(dock_pocket *p, int waves_per_block, int blocks_per_cu);
+ * per compute unit (0: occupancy limit); items_per_claim in [1, 64] is how
+ * many consecutive items a wave takes from the work queue per atomic.
+ * Results are bitwise identical under every mapping.  Errors: DOCK_E_INVAL. */
+int dock_set_launch(dock_pocket *p, int waves_per_block, int blocks_per_cu,
+                    int items_per_claim);
+int dock_get_launch(dock_pocket *p, int *waves_per_block, int *blocks_per_cu,
+                    int *items_per_claim);
+
+/* One measured mapping of dock_autotune. */
+typedef struct {
+  int32_t waves_per_block, blocks_per_cu, items_per_claim;
+  float sweep_ms;
+} dock_tune_entry;
+
+/* Autotuner: time the sweep kernel for every candidate launch mapping on a
+ * seeded subset of sample_ligands ligands of this (host) batch, keep the
+ * fastest on the handle, and report each timing in entries[0..*n_entries).
+ * Same validation and errors as dock_batch. */
+int dock_autotune(dock_pocket *p, const dock_ligands *ligs, const float *orient,
+                  int n_orient, int angle_steps, const dock_params *prm,
+                  int sample_ligands, uint64_t seed, dock_tune_entry *entries,
+                  int max_entries, int *n_entries);
 
 /* Static description of a DOCK_E_* code. */
 const char *dock_strerror(int code);

@@ -9,10 +9,12 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
 #include <mutex>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "dock.h"
 #include "dock_internal.h"
@@ -35,7 +37,11 @@ struct dock_pocket {
   hipEvent_t ev_sweep[3] = {nullptr, nullptr, nullptr};  // sweep start/end, counter copied
   bool timed = false;
   unsigned long long *h_pairs = nullptr;  // pinned copy of the pair-test count
-  LaunchPlan plan{4, 0};
+  LaunchPlan plan{4, 0, 1};
+  // last captured launch sequence of dock_batch_async (DOCK_FLAG_GRAPH)
+  std::vector<unsigned char> graph_key;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
 };
 
 namespace {
@@ -198,6 +204,7 @@ int enqueue_batch(dock_pocket *p, const dock_ligands *ligs, const float *orient,
   A.small = (int32_t *)(base + w.small);
   A.queue = A.small;
   A.n_items = (int32_t)(L * O);
+  A.claim = p->plan.items_per_claim;
   const bool timed = (prm->flags & DOCK_FLAG_TIME_SWEEP) != 0;
   A.pair_tests = timed ? (unsigned long long *)(A.small + 4) : nullptr;
   A.keys = (unsigned long long *)(base + w.keys);
@@ -266,13 +273,121 @@ int dock_last_sweep_pairs(dock_pocket *p, uint64_t *pair_angle_tests) {
   return DOCK_OK;
 }
 
-int dock_set_launch(dock_pocket *p, int waves_per_block, int blocks_per_cu) {
+int dock_set_launch(dock_pocket *p, int waves_per_block, int blocks_per_cu,
+                    int items_per_claim) {
   g_last_error.clear();
   if (!p) return fail(DOCK_E_INVAL, "NULL pocket");
   if (waves_per_block != 1 && waves_per_block != 2 && waves_per_block != 4)
     return fail(DOCK_E_INVAL, "waves_per_block must be 1, 2 or 4");
   if (blocks_per_cu < 0) return fail(DOCK_E_INVAL, "blocks_per_cu must be >= 0");
-  p->plan = LaunchPlan{waves_per_block, blocks_per_cu};
+  if (items_per_claim < 1 || items_per_claim > 64)
+    return fail(DOCK_E_INVAL, "items_per_claim must be in [1, 64]");
+  p->plan = LaunchPlan{waves_per_block, blocks_per_cu, items_per_claim};
+  return DOCK_OK;
+}
+
+int dock_get_launch(dock_pocket *p, int *waves_per_block, int *blocks_per_cu,
+                    int *items_per_claim) {
+  g_last_error.clear();
+  if (!p || !waves_per_block || !blocks_per_cu || !items_per_claim)
+    return fail(DOCK_E_INVAL, "NULL argument");
+  *waves_per_block = p->plan.waves_per_block;
+  *blocks_per_cu = p->plan.blocks_per_cu;
+  *items_per_claim = p->plan.items_per_claim;
+  return DOCK_OK;
+}
+
+// Seeded subset of ligand indices (SplitMix64-driven partial shuffle).
+static std::vector<int> sample_ligands(int n, int count, uint64_t seed) {
+  std::vector<int> idx(n);
+  for (int i = 0; i < n; ++i) idx[i] = i;
+  uint64_t st = seed;
+  auto next = [&]() {
+    uint64_t z = (st += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+  };
+  if (count > n) count = n;
+  for (int i = 0; i < count; ++i) {
+    int j = i + (int)(next() % (uint64_t)(n - i));
+    std::swap(idx[i], idx[j]);
+  }
+  idx.resize(count);
+  std::sort(idx.begin(), idx.end());
+  return idx;
+}
+
+int dock_autotune(dock_pocket *p, const dock_ligands *ligs, const float *orient, int n_orient,
+                  int angle_steps, const dock_params *prm, int sample_ligands_n, uint64_t seed,
+                  dock_tune_entry *entries, int max_entries, int *n_entries) {
+  g_last_error.clear();
+  if (!p || !ligs || !orient || !prm) return fail(DOCK_E_INVAL, "NULL argument");
+  int rc = check_params(prm, n_orient, angle_steps);
+  if (rc) return rc;
+  int max_n = 0;
+  rc = check_ligands_host(ligs, &max_n);
+  if (rc) return rc;
+  if (ligs->n_ligands < 1 || sample_ligands_n < 1)
+    return fail(DOCK_E_INVAL, "autotune needs at least one ligand");
+  // seeded sub-batch
+  std::vector<int> pick = sample_ligands(ligs->n_ligands, sample_ligands_n, seed);
+  std::vector<int32_t> ao{0}, ro{0}, ax, mo{0};
+  std::vector<float> xyz;
+  std::vector<int16_t> mv;
+  for (int l : pick) {
+    int a0 = ligs->atom_offset[l], a1 = ligs->atom_offset[l + 1];
+    int r0 = ligs->rot_offset[l], r1 = ligs->rot_offset[l + 1];
+    xyz.insert(xyz.end(), ligs->xyz + 3 * (size_t)a0, ligs->xyz + 3 * (size_t)a1);
+    ao.push_back(ao.back() + (a1 - a0));
+    for (int r = r0; r < r1; ++r) {
+      ax.push_back(ligs->rot_axis[2 * r]);
+      ax.push_back(ligs->rot_axis[2 * r + 1]);
+      for (int t = ligs->move_offset[r]; t < ligs->move_offset[r + 1]; ++t)
+        mv.push_back(ligs->move_atoms[t]);
+      mo.push_back((int32_t)mv.size());
+    }
+    ro.push_back(ro.back() + (r1 - r0));
+  }
+  dock_ligands sub{(int32_t)pick.size(), ao.back(), ro.back(), (int64_t)mv.size(), ao.data(),
+                   xyz.data(), ro.data(), ax.data(), mo.data(), mv.data()};
+  const int64_t L = sub.n_ligands, NR = sub.total_rot, NA = sub.total_atoms;
+  std::vector<float> bs(L), xo(3 * NA + 3);
+  std::vector<int32_t> bo(L), stv(L);
+  std::vector<int16_t> ai(NR * prm->passes + 1);
+  dock_results res{bs.data(), bo.data(), ai.data(), xo.data(), nullptr, nullptr, stv.data(), nullptr};
+  dock_params tp = *prm;
+  tp.flags |= DOCK_FLAG_TIME_SWEEP;
+  const int waves[] = {1, 2, 4};
+  const int claims[] = {1, 2, 8};
+  LaunchPlan best_plan = p->plan;
+  float best_ms = 0.0f;
+  int n = 0;
+  for (int w : waves)
+    for (int c : claims) {
+      p->plan = LaunchPlan{w, 0, c};
+      float ms_sum = 0.0f;
+      for (int rep = 0; rep < 3; ++rep) {
+        rc = dock_batch(p, &sub, orient, n_orient, angle_steps, &tp, &res);
+        if (rc) {
+          p->plan = best_plan;
+          return rc;
+        }
+        float ms = 0.0f;
+        rc = dock_last_sweep_ms(p, &ms);
+        if (rc) return rc;
+        if (rep > 0) ms_sum += ms;  // first run warms caches
+      }
+      const float ms = ms_sum / 2.0f;
+      if (entries && n < max_entries) entries[n] = dock_tune_entry{w, 0, c, ms};
+      ++n;
+      if (best_ms == 0.0f || ms < best_ms) {
+        best_ms = ms;
+        best_plan = LaunchPlan{w, 0, c};
+      }
+    }
+  p->plan = best_plan;
+  if (n_entries) *n_entries = n < max_entries ? n : max_entries;
   return DOCK_OK;
 }
 
@@ -300,6 +415,8 @@ int dock_init_pocket(const float *grid, int nx, int ny, int nz, const float orig
   if (!grid || !origin) return fail(DOCK_E_INVAL, "grid or origin is NULL");
   if (nx < 1 || ny < 1 || nz < 1 || nx > 4096 || ny > 4096 || nz > 4096)
     return fail(DOCK_E_LIMIT, "grid dims %d x %d x %d outside [1, 4096]", nx, ny, nz);
+  if ((int64_t)nx * ny * nz >= ((int64_t)1 << 30))
+    return fail(DOCK_E_LIMIT, "grid holds 2^30 voxels or more");
   if (!(spacing > 0.0f) || !std::isfinite(spacing)) return fail(DOCK_E_INVAL, "spacing must be > 0");
   for (int a = 0; a < 3; ++a)
     if (!std::isfinite(origin[a])) return fail(DOCK_E_INVAL, "origin must be finite");
@@ -351,6 +468,8 @@ void dock_free_pocket(dock_pocket *p) {
     for (hipEvent_t ev : p->ev_sweep)
       if (ev) (void)hipEventDestroy(ev);
     if (p->h_pairs) (void)hipHostFree(p->h_pairs);
+    if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
   }
   delete p;
 }
@@ -373,17 +492,63 @@ int dock_batch_async(dock_pocket *p, const dock_ligands *ligs, const float *orie
     return fail(DOCK_E_INVAL, "result array is NULL");
   if (ligs->total_rot > 0 && !out->angle_idx) return fail(DOCK_E_INVAL, "angle_idx is NULL");
   DeviceGuard g(p->device);
+  std::lock_guard<std::mutex> lk(p->mu);
   if (!workspace) {
-    std::lock_guard<std::mutex> lk(p->mu);
     size_t need = dock_workspace_size(ligs->n_ligands, ligs->total_rot, n_orient, angle_steps,
                                       prm->passes);
     rc = grow(&p->ws, &p->ws_bytes, need);
     if (rc) return rc;
-    return enqueue_batch(p, ligs, orient, n_orient, angle_steps, prm, out, p->ws, p->ws_bytes,
-                         (hipStream_t)stream);
+    workspace = p->ws;
+    workspace_bytes = p->ws_bytes;
   }
-  return enqueue_batch(p, ligs, orient, n_orient, angle_steps, prm, out, workspace,
-                       workspace_bytes, (hipStream_t)stream);
+  hipStream_t st = (hipStream_t)stream;
+  if (!(prm->flags & DOCK_FLAG_GRAPH))
+    return enqueue_batch(p, ligs, orient, n_orient, angle_steps, prm, out, workspace,
+                         workspace_bytes, st);
+  if (!st) return fail(DOCK_E_INVAL, "DOCK_FLAG_GRAPH needs a non-default stream");
+  // The launch sequence depends only on these values: replay it if they repeat.
+  std::vector<unsigned char> key;
+  auto put = [&](const void *v, size_t bytes) {
+    key.insert(key.end(), (const unsigned char *)v, (const unsigned char *)v + bytes);
+  };
+  put(ligs, sizeof *ligs);
+  put(&orient, sizeof orient);
+  put(&n_orient, sizeof n_orient);
+  put(&angle_steps, sizeof angle_steps);
+  put(prm, sizeof *prm);
+  put(out, sizeof *out);
+  put(&workspace, sizeof workspace);
+  put(&workspace_bytes, sizeof workspace_bytes);
+  put(&p->plan, sizeof p->plan);
+  hipError_t e;
+  if (!p->graph_exec || key != p->graph_key) {
+    if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    p->graph_exec = nullptr;
+    p->graph = nullptr;
+    p->graph_key.clear();
+    if ((e = hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed)) != hipSuccess)
+      return hip_fail(e, "hipStreamBeginCapture");
+    rc = enqueue_batch(p, ligs, orient, n_orient, angle_steps, prm, out, workspace,
+                       workspace_bytes, st);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(st, &graph);
+    if (rc) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return rc;
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    hipGraphExec_t exec = nullptr;
+    if ((e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0)) != hipSuccess) {
+      (void)hipGraphDestroy(graph);
+      return hip_fail(e, "hipGraphInstantiate");
+    }
+    p->graph = graph;
+    p->graph_exec = exec;
+    p->graph_key = key;
+  }
+  if ((e = hipGraphLaunch(p->graph_exec, st)) != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+  return DOCK_OK;
 }
 
 int dock_batch(dock_pocket *p, const dock_ligands *ligs, const float *orient, int n_orient,

@@ -14,9 +14,8 @@ constexpr int kLptBuckets = 128;
 //   [4, 6) 64-bit count of executed (pair, angle) bump tests,
 //   [64, 64+B) bucket counts, [64+B, 64+2B) bucket cursors
 constexpr int kSmallInts = 64 + 2 * kLptBuckets;
-// pruned sweep: LDS capacity of the per-wave list of pairs that can clash,
-// and the margin (A^2) added to r_bump^2 when dropping pairs that cannot
-constexpr int kPairCap = 128;
+// pruned sweep: margin (A^2) added to r_bump^2 when dropping the pairs whose
+// distance lower bound shows they cannot clash
 constexpr float kPruneMargin = 1e-3f;
 
 enum SweepMode { kSweepDirect = 0, kSweepPruned = 1 };
@@ -46,6 +45,7 @@ struct SweepArgs {
   int32_t *small;       // kSmallInts counters (queue at [0])
   int32_t *queue;
   int32_t n_items;
+  int32_t claim;                   // consecutive items a wave takes per queue atomic
   unsigned long long *pair_tests;  // accumulated once per wave
   unsigned long long *keys;  // [n_ligands] best (score, orientation) key
   int16_t *kstar;            // [total_rot * passes * n_orient]
@@ -62,6 +62,7 @@ struct FinalOut {
 struct LaunchPlan {
   int waves_per_block;  // 1, 2 or 4
   int blocks_per_cu;    // 0 = as many as occupancy allows
+  int items_per_claim;  // 1 .. 64
 };
 
 hipError_t enqueue_prepare(const SweepArgs &A, int max_atoms, bool lpt, int32_t *bucket_of,

@@ -38,6 +38,45 @@ __device__ __forceinline__ float voxel_value(const GridView &g, float px, float 
   return g.grid[voxel_index(g, px, py, pz)];
 }
 
+// Byte offset of the voxel holding a point given in voxel units ((p - o)/h).
+// Clamping t to [0, n - 1/2] and truncating equals floor-then-clamp to
+// [0, n - 1] for every finite t, in two instructions per axis.  Grids stay
+// below 2^30 voxels, so the offset fits 32 bits and the products fit the
+// 24-bit multiplier.
+struct GridScaled {
+  float hx, hy, hz;      // n - 1/2 per axis
+  uint32_t ny, nx4;      // ny, 4 nx
+};
+
+__device__ __forceinline__ GridScaled grid_scaled(const GridView &g) {
+  return GridScaled{(float)g.nx - 0.5f, (float)g.ny - 0.5f, (float)g.nz - 0.5f, (uint32_t)g.ny,
+                    4u * (uint32_t)g.nx};
+}
+
+__device__ __forceinline__ uint32_t voxel_byte_offset(const GridScaled &g, float tx, float ty,
+                                                      float tz) {
+  const uint32_t ix = (uint32_t)__builtin_amdgcn_fmed3f(tx, 0.0f, g.hx);
+  const uint32_t iy = (uint32_t)__builtin_amdgcn_fmed3f(ty, 0.0f, g.hy);
+  const uint32_t iz = (uint32_t)__builtin_amdgcn_fmed3f(tz, 0.0f, g.hz);
+  return __umul24(__umul24(iz, g.ny) + iy, g.nx4) + (ix << 2);
+}
+
+// Grid read through a buffer resource (32-bit offsets, reads past the end
+// return 0 instead of faulting).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t grid_rsrc(const GridView &g) {
+  const uint32_t bytes = 4u * (uint32_t)g.nx * (uint32_t)g.ny * (uint32_t)g.nz;
+  return __builtin_amdgcn_make_buffer_rsrc((void *)g.grid, (short)0, (int)bytes, 0x00020000);
+}
+
+__device__ __forceinline__ float grid_load(__amdgpu_buffer_rsrc_t r, uint32_t byte_off) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)byte_off, 0, 0));
+}
+
+// Value held by lane `src` (uniform) of the wave.
+__device__ __forceinline__ float lane_bcast(float v, int src) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
+}
+
 // Rigid starting pose X = R x + t (row-major R).
 __device__ __forceinline__ float3 orient_point(const float *T, float x, float y,
                                                float z) {
@@ -145,6 +184,14 @@ __device__ __forceinline__ uint64_t wave_max_u64(uint64_t v) {
     uint64_t o = __shfl_xor(v, off, kWave);
     v = o > v ? o : v;
   }
+  return v;
+}
+
+// Sum over the 64 lanes by a fixed butterfly (every lane gets the result;
+// the order of additions depends only on lane positions).
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) v += __shfl_xor(v, off, kWave);
   return v;
 }
 

@@ -19,6 +19,7 @@ DOCK_MODE_PLAIN, DOCK_MODE_LEARNED = 0, 1
 DOCK_FLAG_NO_LPT = 1
 DOCK_FLAG_TIME_SWEEP = 2
 DOCK_FLAG_DIRECT_BUMP = 4
+DOCK_FLAG_GRAPH = 8
 DOCK_MAX_ATOMS, DOCK_MAX_ROT, DOCK_MAX_STEPS = 256, 255, 4096
 
 _P = ctypes.c_void_p
@@ -42,6 +43,11 @@ class dock_results(ctypes.Structure):
                 ("all_scores", _P), ("all_angle_idx", _P), ("status", _P), ("n_fallback", _P)]
 
 
+class dock_tune_entry(ctypes.Structure):
+    _fields_ = [("waves_per_block", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
+                ("items_per_claim", ctypes.c_int32), ("sweep_ms", ctypes.c_float)]
+
+
 class DockError(RuntimeError):
     def __init__(self, code: int, where: str, detail: str):
         super().__init__(f"{where}: {detail or 'error'} (code {code})")
@@ -51,13 +57,33 @@ class DockError(RuntimeError):
 _lib = None
 
 
-def load_library(path: str = LIB_PATH):
-    """Load libdock.so; raises if it is not built (no fallback path exists)."""
+def _bind_torch_runtime():
+    """Load torch's HIP runtime first when torch is installed.
+
+    torch ships its own libamdhip64 / libhsa-runtime64 (same sonames as the
+    system ROCm).  Loading torch first makes libdock.so bind to that runtime,
+    so one HIP runtime serves the whole process and torch's device memory and
+    streams are valid handles for the library.  Without torch, libdock.so
+    uses the system ROCm runtime.
+    """
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+
+
+def load_library(path: str = None):
+    """Load libdock.so; raises if it is not built (no fallback path exists).
+
+    PAPER_1901_06229_AMD_LIB may name another build of the same library.
+    """
     global _lib
     if _lib is not None:
         return _lib
+    path = path or os.environ.get("PAPER_1901_06229_AMD_LIB") or LIB_PATH
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is not built: run __graft_entry__.build() first")
+    _bind_torch_runtime()
     lib = ctypes.CDLL(path)
     c = ctypes
     lib.dock_init_pocket.argtypes = [_P, c.c_int, c.c_int, c.c_int, _P, c.c_float, c.POINTER(_P)]
@@ -77,8 +103,14 @@ def load_library(path: str = LIB_PATH):
     lib.dock_last_sweep_ms.restype = c.c_int
     lib.dock_last_sweep_pairs.argtypes = [_P, c.POINTER(c.c_uint64)]
     lib.dock_last_sweep_pairs.restype = c.c_int
-    lib.dock_set_launch.argtypes = [_P, c.c_int, c.c_int]
+    lib.dock_set_launch.argtypes = [_P, c.c_int, c.c_int, c.c_int]
     lib.dock_set_launch.restype = c.c_int
+    lib.dock_get_launch.argtypes = [_P, c.POINTER(c.c_int), c.POINTER(c.c_int), c.POINTER(c.c_int)]
+    lib.dock_get_launch.restype = c.c_int
+    lib.dock_autotune.argtypes = [_P, c.POINTER(dock_ligands), _P, c.c_int, c.c_int,
+                                  c.POINTER(dock_params), c.c_int, c.c_uint64,
+                                  c.POINTER(dock_tune_entry), c.c_int, c.POINTER(c.c_int)]
+    lib.dock_autotune.restype = c.c_int
     lib.dock_strerror.argtypes = [c.c_int]
     lib.dock_strerror.restype = c.c_char_p
     lib.dock_last_error.argtypes = []
@@ -204,9 +236,46 @@ def dock_last_sweep_pairs(pocket: Pocket) -> int:
     return int(v.value)
 
 
-def dock_set_launch(pocket: Pocket, waves_per_block: int, blocks_per_cu: int = 0):
-    _check(load_library().dock_set_launch(pocket.handle, int(waves_per_block), int(blocks_per_cu)),
-           "dock_set_launch")
+def dock_set_launch(pocket: Pocket, waves_per_block: int, blocks_per_cu: int = 0,
+                    items_per_claim: int = 1):
+    _check(load_library().dock_set_launch(pocket.handle, int(waves_per_block), int(blocks_per_cu),
+                                          int(items_per_claim)), "dock_set_launch")
+
+
+def dock_get_launch(pocket: Pocket):
+    w, b, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    _check(load_library().dock_get_launch(pocket.handle, ctypes.byref(w), ctypes.byref(b),
+                                          ctypes.byref(c)), "dock_get_launch")
+    return int(w.value), int(b.value), int(c.value)
+
+
+def _host_ligands(ligs):
+    keep = dict(ao=_c(ligs.atom_offset, np.int32), xyz=_c(ligs.xyz, np.float32),
+                ro=_c(ligs.rot_offset, np.int32), ax=_c(ligs.rot_axis, np.int32),
+                mo=_c(ligs.move_offset, np.int32), mv=_c(ligs.move_atoms, np.int16))
+    L = len(keep["ao"]) - 1
+    NA, NR = (int(keep["ao"][-1]), int(keep["ro"][-1])) if L else (0, 0)
+    NM = int(keep["mo"][NR]) if NR else 0
+    dl = dock_ligands(L, NA, NR, NM, _np_ptr(keep["ao"]), _np_ptr(keep["xyz"]),
+                      _np_ptr(keep["ro"]), _np_ptr(keep["ax"]), _np_ptr(keep["mo"]),
+                      _np_ptr(keep["mv"]))
+    return dl, keep
+
+
+def dock_autotune(pocket: Pocket, ligs, orient, angle_steps: int, sample_ligands: int,
+                  seed: int = 0, **param_kw):
+    """Time every candidate mapping on a seeded subset; keeps the fastest on the handle."""
+    lib = load_library()
+    dl, keep = _host_ligands(ligs)
+    orient = _c(orient, np.float32).reshape(-1, 12)
+    prm = make_params(**param_kw)
+    entries = (dock_tune_entry * 64)()
+    n = ctypes.c_int()
+    _check(lib.dock_autotune(pocket.handle, ctypes.byref(dl), _np_ptr(orient), orient.shape[0],
+                             int(angle_steps), ctypes.byref(prm), int(sample_ligands), int(seed),
+                             entries, 64, ctypes.byref(n)), "dock_autotune")
+    return [dict(waves_per_block=e.waves_per_block, blocks_per_cu=e.blocks_per_cu,
+                 items_per_claim=e.items_per_claim, sweep_ms=e.sweep_ms) for e in entries[:n.value]]
 
 
 def _tptr(t):

@@ -208,12 +208,83 @@ def test_results_independent_of_launch_mapping(pockets):
     ligs = synth.ligands(2, count=150, first=2000)
     orient = synth.orientations(2, 32)
     ref = None
-    for waves, bpc in ((4, 0), (1, 0), (2, 1), (4, 2), (1, 3)):
-        dock.dock_set_launch(h, waves, bpc)
+    for waves, bpc, claim in ((4, 0, 1), (1, 0, 1), (2, 1, 4), (4, 2, 8), (1, 3, 64), (4, 0, 3)):
+        dock.dock_set_launch(h, waves, bpc, claim)
         res = dock.dock_batch(h, ligs, orient, 128, want_all=True)
         if ref is None:
             ref = res
             continue
         for k in ("best_score", "best_orient", "angle_idx", "xyz", "all_scores", "all_angle_idx"):
-            assert np.array_equal(ref[k], res[k]), (waves, bpc, k)
-    dock.dock_set_launch(h, 4, 0)
+            assert np.array_equal(ref[k], res[k]), (waves, bpc, claim, k)
+    dock.dock_set_launch(h, 4, 0, 1)
+
+
+def test_autotune_picks_fastest_and_keeps_results(pockets):
+    p, h = pockets(2)
+    ligs = synth.ligands(2, count=400, first=3000)
+    orient = synth.orientations(2, 64)
+    before = dock.dock_batch(h, ligs, orient, 128, want_all=True)
+    entries = dock.dock_autotune(h, ligs, orient, 128, sample_ligands=100, seed=7)
+    print(entries)
+    assert len(entries) == 9
+    best = min(entries, key=lambda e: e["sweep_ms"])
+    assert dock.dock_get_launch(h) == (best["waves_per_block"], best["blocks_per_cu"],
+                                       best["items_per_claim"])
+    after = dock.dock_batch(h, ligs, orient, 128, want_all=True)
+    for k in ("best_score", "best_orient", "angle_idx", "xyz", "all_scores", "all_angle_idx"):
+        assert np.array_equal(before[k], after[k]), k
+    dock.dock_set_launch(h, 4, 0, 1)
+
+
+def _device_batch(ligs, orient, S, torch):
+    dev = torch.device("cuda:0")
+    d = dict(n_ligands=ligs.n_ligands, total_atoms=int(ligs.atom_offset[-1]),
+             total_rot=int(ligs.rot_offset[-1]), total_move=int(ligs.move_offset[-1]))
+    for k, dt in (("atom_offset", torch.int32), ("xyz", torch.float32), ("rot_offset", torch.int32),
+                  ("rot_axis", torch.int32), ("move_offset", torch.int32), ("move_atoms", torch.int16)):
+        d[k] = torch.from_numpy(np.ascontiguousarray(getattr(ligs, k))).to(dev, dt)
+    L, NA, NR = ligs.n_ligands, d["total_atoms"], d["total_rot"]
+    out = dict(best_score=torch.empty(L, device=dev),
+               best_orient=torch.empty(L, dtype=torch.int32, device=dev),
+               angle_idx=torch.empty(NR, dtype=torch.int16, device=dev),
+               xyz=torch.empty(NA, 3, device=dev), status=torch.empty(L, dtype=torch.int32, device=dev),
+               all_scores=torch.empty(L, orient.shape[0], device=dev),
+               all_angle_idx=torch.empty(NR * orient.shape[0], dtype=torch.int16, device=dev))
+    return d, torch.from_numpy(orient).to(dev), out
+
+
+def test_async_and_graph_replay_match_sync(pockets):
+    """dock_batch_async on device tensors, eager and as a replayed HIP graph
+    (several replays with eager work and synchronisation in between), against
+    the synchronous host-array call."""
+    import torch
+    p, h = pockets(2)
+    ligs = synth.ligands(2, count=120, first=4000)
+    orient = synth.orientations(2, 32)
+    ref = dock.dock_batch(h, ligs, orient, 128, want_all=True)
+    d, od, out = _device_batch(ligs, orient, 128, torch)
+    ws = torch.empty(dock.dock_workspace_size(ligs.n_ligands, d["total_rot"], 32, 128),
+                     dtype=torch.uint8, device="cuda:0")
+    st = torch.cuda.Stream()
+    names = ("best_score", "best_orient", "angle_idx", "xyz", "all_scores", "all_angle_idx")
+
+    def check():
+        st.synchronize()
+        got = {k: out[k].cpu().numpy() for k in names}
+        got["xyz"] = got["xyz"].reshape(-1, 3)
+        for k in names:
+            assert np.array_equal(np.asarray(ref[k]).reshape(got[k].shape), got[k]), k
+        for k in names:
+            out[k].fill_(0)
+        torch.cuda.synchronize()
+
+    prm = dock.make_params(max_atoms=int(np.diff(ligs.atom_offset).max()))
+    dock.dock_batch_async(h, d, od, 128, out, prm, workspace=ws, stream=st)
+    check()
+    gprm = dock.make_params(max_atoms=int(np.diff(ligs.atom_offset).max()), flags=dock.DOCK_FLAG_GRAPH)
+    for rep in range(4):
+        dock.dock_batch_async(h, d, od, 128, out, gprm, workspace=ws, stream=st)
+        check()
+        # unrelated eager work between replays
+        x = torch.randn(1000, 1000, device="cuda:0")
+        (x @ x).sum().item()
