@@ -97,11 +97,12 @@ typedef struct {
   float r_bump;      /* bump radius (A), >= 0                                   */
   int32_t passes;    /* sweeps over all rotamers (paper: num_repetitions), >= 1 */
   int32_t mode;      /* DOCK_MODE_PLAIN or DOCK_MODE_LEARNED                    */
-  int32_t top_k;     /* learned mode: bins nominated per step (1..64)          */
+  int32_t top_k;     /* learned mode: bins nominated per step (1..63)          */
   float margin;      /* learned mode: fall back to the full sweep when the
                         predicted best minus the (top_k+1)-th is below this   */
   uint32_t flags;    /* DOCK_FLAG_*                                             */
   int32_t max_atoms; /* async calls: upper bound on atoms per ligand (0: 256)   */
+  int32_t max_rot;   /* async learned calls: upper bound on rotamers (0: 255)   */
 } dock_params;
 
 /* Outputs.  Sizes follow from the inputs.
@@ -204,6 +205,61 @@ int dock_autotune(dock_pocket *p, const dock_ligands *ligs, const float *orient,
                   int n_orient, int angle_steps, const dock_params *prm,
                   int sample_ligands, uint64_t seed, dock_tune_entry *entries,
                   int max_entries, int *n_entries);
+
+/* ------------------------------------------------------------------------
+ * Learned angle proposal.  A small MLP maps 64 features of a rotamer step
+ * (grid samples in the rotamer's local frame) to a 256-bin profile of the
+ * angle scores; in DOCK_MODE_LEARNED the best predicted bins among the
+ * angles that pass the exact bump test are scored exactly, with the full
+ * sweep as fallback.  Network: 64 -> 256 -> 256 -> 256 -> 256, GELU after
+ * the hidden layers, BF16 weights and activations, FP32 accumulation,
+ * trained with a mean-squared error by the kernels below (all on the GPU).
+ * Packed FP32 parameters (dock_mlp_param_count() floats), row-major
+ * [out][in] weights: W1[256][64] b1[256] W2[256][256] b2 W3 b3 W4 b4.
+ * Rows are passed as BF16 bit patterns (uint16_t), row-major; `rows` must be
+ * a positive multiple of 64.  Device pointers unless stated.
+ * ------------------------------------------------------------------------ */
+typedef struct dock_mlp dock_mlp;
+
+size_t dock_mlp_param_count(void);
+
+/* Create a network on the current device from host FP32 parameters.
+ * Errors: DOCK_E_INVAL, DOCK_E_NOMEM, DOCK_E_DEVICE. */
+int dock_mlp_create(const float *init_params, dock_mlp **out);
+void dock_mlp_free(dock_mlp *m);
+int dock_mlp_get_params(dock_mlp *m, float *host_params);
+int dock_mlp_set_params(dock_mlp *m, const float *host_params);
+
+/* y[rows][256] (FP32) = network(x[rows][64]). */
+int dock_mlp_forward(dock_mlp *m, const uint16_t *x_bf16, int rows, float *y, void *stream);
+
+/* Loss = mean over rows x 256 of (y - t)^2 and its gradient w.r.t. the packed
+ * parameters (kept inside the network for dock_mlp_adam; also copied to
+ * grad_out if not NULL).  loss_out (host, may be NULL) waits for the stream. */
+int dock_mlp_loss_grad(dock_mlp *m, const uint16_t *x_bf16, const uint16_t *t_bf16, int rows,
+                       float *grad_out, float *loss_out, void *stream);
+
+/* One Adam step (Kingma & Ba) on the FP32 master parameters with the last
+ * gradient; refreshes the BF16 copy used by forward passes. */
+int dock_mlp_adam(dock_mlp *m, float lr, float beta1, float beta2, float eps, void *stream);
+
+/* Install a trained network as the pocket's learned proposal (device copy of
+ * its current weights; the network may be freed afterwards).  Needed by
+ * DOCK_MODE_LEARNED, which also requires angle_steps = 256 (one output bin
+ * per angle step) and 1 <= top_k <= 63. */
+int dock_load_proposal(dock_pocket *p, dock_mlp *m);
+
+/* Training data for the learned proposal: run the plain sweep (S = 256) on a
+ * host batch and write, for every step of every (ligand, orientation) item
+ * in the layout of all_angle_idx (item (l, o) starts at
+ * (rot_offset[l]*n_orient + o*R_l)*passes), its 64 features (x_out, BF16),
+ * its score landscape over the 256 angles, max(s_k - max_k' s_k', -4)
+ * (t_out, BF16), and the exact validity mask of the 256 angles (mask_out,
+ * 8 x uint32, bit k%32 of word k/32).  Outputs are device arrays of
+ * total_rot*passes*n_orient rows. */
+int dock_emit_profiles(dock_pocket *p, const dock_ligands *ligs, const float *orient,
+                       int n_orient, const dock_params *prm, uint16_t *x_out,
+                       uint16_t *t_out, uint32_t *mask_out);
 
 /* Static description of a DOCK_E_* code. */
 const char *dock_strerror(int code);

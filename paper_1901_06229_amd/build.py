@@ -11,7 +11,8 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB_PATH = os.path.join(PKG, "libdock.so")
 
-SOURCES = ["sweep_kernels.hip", "sweep_pruned.hip", "dock_abi.hip"]
+SOURCES = ["sweep_kernels.hip", "sweep_pruned.hip", "learned.hip", "mlp.hip", "mlp_abi.hip",
+           "dock_abi.hip"]
 
 HIP_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

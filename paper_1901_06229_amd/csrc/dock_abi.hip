@@ -18,6 +18,8 @@
 
 #include "dock.h"
 #include "dock_internal.h"
+#include "learned_internal.h"
+#include "mlp_internal.h"
 
 using namespace dock;
 
@@ -42,6 +44,19 @@ struct dock_pocket {
   std::vector<unsigned char> graph_key;
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
+  // learned proposal: BF16 weights and FP32 parameters (biases) of the MLP
+  uint16_t *prop_wb = nullptr;
+  float *prop_w = nullptr;
+  // learned-mode buffers, grown on demand
+  int64_t lw_items = 0, lw_rows = 0;
+  int lw_nmax = 0;
+  float4 *lw_pose = nullptr;
+  uint16_t *lw_feat = nullptr;
+  uint64_t *lw_valid = nullptr;
+  float *lw_z[4] = {nullptr, nullptr, nullptr, nullptr};  // z1, z2, z3, y
+  uint16_t *lw_a[3] = {nullptr, nullptr, nullptr};
+  int32_t *lw_fallback = nullptr;
+  int64_t lw_fallback_n = 0;
 };
 
 namespace {
@@ -57,6 +72,23 @@ int fail(int code, const char *fmt, ...) {
   g_last_error = buf;
   return code;
 }
+
+}  // namespace
+
+namespace dock {
+// Shared with the other translation units of the library.
+int abi_fail(int code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return code;
+}
+}  // namespace dock
+
+namespace {
 
 int hip_fail(hipError_t e, const char *what) {
   return fail(e == hipErrorOutOfMemory ? DOCK_E_NOMEM : DOCK_E_DEVICE, "%s: %s", what,
@@ -130,7 +162,7 @@ int check_params(const dock_params *prm, int n_orient, int S) {
 }
 
 // Full host-side check of a CSR batch (synchronous path).
-int check_ligands_host(const dock_ligands *L, int *max_n) {
+int check_ligands_host(const dock_ligands *L, int *max_n, int *max_r = nullptr) {
   if (!L) return fail(DOCK_E_INVAL, "ligands is NULL");
   if (L->n_ligands < 0) return fail(DOCK_E_INVAL, "n_ligands < 0");
   if (!L->atom_offset || !L->rot_offset) return fail(DOCK_E_INVAL, "offset array is NULL");
@@ -147,7 +179,7 @@ int check_ligands_host(const dock_ligands *L, int *max_n) {
       return fail(DOCK_E_INVAL, "move_offset must run from 0 to total_move");
     if (L->total_move > 0 && !L->move_atoms) return fail(DOCK_E_INVAL, "move_atoms is NULL");
   }
-  int mx = 0;
+  int mx = 0, mr = 0;
   for (int l = 0; l < nl; ++l) {
     int n = L->atom_offset[l + 1] - L->atom_offset[l];
     int R = L->rot_offset[l + 1] - L->rot_offset[l];
@@ -156,6 +188,7 @@ int check_ligands_host(const dock_ligands *L, int *max_n) {
     if (n > DOCK_MAX_ATOMS) return fail(DOCK_E_LIMIT, "ligand %d has %d atoms (max %d)", l, n, DOCK_MAX_ATOMS);
     if (R > DOCK_MAX_ROT) return fail(DOCK_E_LIMIT, "ligand %d has %d rotamers (max %d)", l, R, DOCK_MAX_ROT);
     mx = n > mx ? n : mx;
+    mr = R > mr ? R : mr;
     for (int r = L->rot_offset[l]; r < L->rot_offset[l + 1]; ++r) {
       int a = L->rot_axis[2 * r], b = L->rot_axis[2 * r + 1];
       if (a < 0 || a >= n || b < 0 || b >= n || a == b)
@@ -173,18 +206,66 @@ int check_ligands_host(const dock_ligands *L, int *max_n) {
     }
   }
   *max_n = mx;
+  if (max_r) *max_r = mr;
   return DOCK_OK;
 }
 
 int maxn_bucket(int max_atoms) { return max_atoms <= 64 ? 64 : (max_atoms <= 128 ? 128 : 256); }
 
+void free_learned(dock_pocket *p) {
+  for (void *q : {(void *)p->lw_pose, (void *)p->lw_feat, (void *)p->lw_valid, (void *)p->lw_z[0],
+                  (void *)p->lw_z[1], (void *)p->lw_z[2], (void *)p->lw_z[3], (void *)p->lw_a[0],
+                  (void *)p->lw_a[1], (void *)p->lw_a[2]})
+    if (q) (void)hipFree(q);
+  p->lw_pose = nullptr;
+  p->lw_feat = nullptr;
+  p->lw_valid = nullptr;
+  for (auto &z : p->lw_z) z = nullptr;
+  for (auto &a : p->lw_a) a = nullptr;
+  p->lw_items = p->lw_rows = 0;
+  p->lw_nmax = 0;
+}
+
+int grow_learned(dock_pocket *p, int64_t items, int nmax) {
+  const int64_t rows = (items + 63) / 64 * 64;
+  if (items <= p->lw_items && nmax <= p->lw_nmax && p->lw_pose) return DOCK_OK;
+  free_learned(p);
+  hipError_t e = hipSuccess;
+  auto A = [&](void **q, size_t b) {
+    if (e == hipSuccess) e = hipMalloc(q, b < 256 ? 256 : b);
+  };
+  A((void **)&p->lw_pose, sizeof(float4) * (size_t)items * nmax);
+  A((void **)&p->lw_feat, sizeof(uint16_t) * (size_t)rows * 64);
+  A((void **)&p->lw_valid, sizeof(uint64_t) * (size_t)items * 4);
+  for (auto &z : p->lw_z) A((void **)&z, sizeof(float) * (size_t)rows * 256);
+  for (auto &a : p->lw_a) A((void **)&a, sizeof(uint16_t) * (size_t)rows * 256);
+  // padding rows of the feature matrix stay zero
+  if (e == hipSuccess) e = hipMemset(p->lw_feat, 0, sizeof(uint16_t) * (size_t)rows * 64);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) {
+    free_learned(p);
+    return hip_fail(e, "learned-mode buffers");
+  }
+  p->lw_items = items;
+  p->lw_rows = rows;
+  p->lw_nmax = nmax;
+  return DOCK_OK;
+}
+
 int enqueue_batch(dock_pocket *p, const dock_ligands *ligs, const float *orient, int O, int S,
                   const dock_params *prm, const dock_results *out, void *ws, size_t ws_bytes,
-                  hipStream_t st) {
+                  hipStream_t st, uint16_t *emit_x = nullptr, uint16_t *emit_t = nullptr,
+                  uint32_t *emit_mask = nullptr) {
   const int64_t L = ligs->n_ligands;
   const int max_atoms = prm->max_atoms > 0 ? prm->max_atoms : DOCK_MAX_ATOMS;
   if (L * (int64_t)O >= ((int64_t)1 << 31)) return fail(DOCK_E_LIMIT, "n_ligands * n_orient >= 2^31");
-  if (prm->mode == DOCK_MODE_LEARNED) return fail(DOCK_E_STATE, "no learned proposal loaded");
+  const bool learned = prm->mode == DOCK_MODE_LEARNED;
+  if (learned) {
+    if (!p->prop_wb) return fail(DOCK_E_STATE, "no learned proposal loaded (dock_load_proposal)");
+    if (S != 256) return fail(DOCK_E_LIMIT, "learned mode needs angle_steps = 256 (one bin per step)");
+    if (prm->top_k < 1 || prm->top_k > 63) return fail(DOCK_E_LIMIT, "top_k outside [1, 63]");
+    if (prm->max_rot < 0 || prm->max_rot > DOCK_MAX_ROT) return fail(DOCK_E_LIMIT, "max_rot outside [0, 255]");
+  }
   WsLayout w = ws_layout(L, ligs->total_rot, O, S, prm->passes);
   if (ws_bytes < w.total) return fail(DOCK_E_INVAL, "workspace too small: %zu < %zu", ws_bytes, w.total);
   char *base = (char *)ws;
@@ -210,12 +291,72 @@ int enqueue_batch(dock_pocket *p, const dock_ligands *ligs, const float *orient,
   A.keys = (unsigned long long *)(base + w.keys);
   A.kstar = (int16_t *)(base + w.kstar);
   A.all_scores = out->all_scores;
+  A.emit_x = emit_x;
+  A.emit_t = emit_t;
+  A.emit_mask = emit_mask;
   int32_t *counts = A.small + 64, *cursor = A.small + 64 + kLptBuckets;
-  bool lpt = !(prm->flags & DOCK_FLAG_NO_LPT);
+  bool lpt = !(prm->flags & DOCK_FLAG_NO_LPT) && !learned;
   hipError_t e = enqueue_prepare(A, max_atoms, lpt, (int32_t *)(base + w.bucket), counts, cursor,
                                  A.small + 1, st);
   if (e != hipSuccess) return hip_fail(e, "prepare kernels");
   const int maxn = maxn_bucket(max_atoms);
+  if (learned) {
+    const int nmax = (max_atoms + 15) / 16 * 16;
+    int rc = grow_learned(p, L * O, nmax);
+    if (rc) return rc;
+    int32_t *nfb = out->n_fallback;
+    if (!nfb) {
+      if (p->lw_fallback_n < L) {
+        if (p->lw_fallback) (void)hipFree(p->lw_fallback);
+        p->lw_fallback = nullptr;
+        p->lw_fallback_n = 0;
+        if ((e = hipMalloc((void **)&p->lw_fallback, sizeof(int32_t) * (L > 0 ? L : 1))) != hipSuccess)
+          return hip_fail(e, "hipMalloc(n_fallback)");
+        p->lw_fallback_n = L;
+      }
+      nfb = p->lw_fallback;
+    }
+    if ((e = enqueue_fill_i32(nfb, (int)L, 0, st)) != hipSuccess) return hip_fail(e, "fill");
+    LearnedArgs LA{};
+    LA.sw = A;
+    LA.nmax = nmax;
+    LA.pose = p->lw_pose;
+    LA.feat = p->lw_feat;
+    LA.valid = p->lw_valid;
+    LA.pred = p->lw_z[3];
+    LA.top_k = prm->top_k;
+    LA.margin = prm->margin;
+    LA.n_fallback = nfb;
+    if (timed && (e = hipEventRecord(p->ev_sweep[0], st)) != hipSuccess)
+      return hip_fail(e, "hipEventRecord");
+    if ((e = enqueue_learned_begin(LA, p->n_cu, st)) != hipSuccess)
+      return hip_fail(e, "learned begin kernel");
+    const int steps = (prm->max_rot > 0 ? prm->max_rot : DOCK_MAX_ROT) * prm->passes;
+    const int rows = (int)((L * O + 63) / 64 * 64);
+    for (int s = 0; s < steps; ++s) {
+      e = mlp_forward(p->lw_feat, rows, p->prop_wb, p->prop_w, p->lw_z[0], p->lw_a[0], p->lw_z[1],
+                      p->lw_a[1], p->lw_z[2], p->lw_a[2], p->lw_z[3], st);
+      if (e == hipSuccess) e = enqueue_learned_step(LA, s, p->n_cu, st);
+      if (e != hipSuccess) return hip_fail(e, "learned step");
+    }
+    if (timed) {
+      if ((e = hipEventRecord(p->ev_sweep[1], st)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+      e = hipMemcpyAsync(p->h_pairs, A.small + 4, sizeof(unsigned long long), hipMemcpyDeviceToHost, st);
+      if (e == hipSuccess) e = hipEventRecord(p->ev_sweep[2], st);
+      if (e != hipSuccess) return hip_fail(e, "timing");
+      p->timed = true;
+    }
+    FinalOut F{out->best_score, out->best_orient, out->angle_idx, out->xyz_out};
+    e = enqueue_finalize(A, F, maxn, kSweepPruned, st);
+    if (e != hipSuccess) return hip_fail(e, "finalize kernel");
+    if (out->all_angle_idx && ligs->total_rot > 0) {
+      e = hipMemcpyAsync(out->all_angle_idx, A.kstar,
+                         sizeof(int16_t) * (size_t)ligs->total_rot * prm->passes * O,
+                         hipMemcpyDeviceToDevice, st);
+      if (e != hipSuccess) return hip_fail(e, "copy all_angle_idx");
+    }
+    return DOCK_OK;
+  }
   if (timed && (e = hipEventRecord(p->ev_sweep[0], st)) != hipSuccess)
     return hip_fail(e, "hipEventRecord");
   const SweepMode mode = (prm->flags & DOCK_FLAG_DIRECT_BUMP) ? kSweepDirect : kSweepPruned;
@@ -470,6 +611,10 @@ void dock_free_pocket(dock_pocket *p) {
     if (p->h_pairs) (void)hipHostFree(p->h_pairs);
     if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
     if (p->graph) (void)hipGraphDestroy(p->graph);
+    free_learned(p);
+    if (p->lw_fallback) (void)hipFree(p->lw_fallback);
+    if (p->prop_wb) (void)hipFree(p->prop_wb);
+    if (p->prop_w) (void)hipFree(p->prop_w);
   }
   delete p;
 }
@@ -551,21 +696,17 @@ int dock_batch_async(dock_pocket *p, const dock_ligands *ligs, const float *orie
   return DOCK_OK;
 }
 
-int dock_batch(dock_pocket *p, const dock_ligands *ligs, const float *orient, int n_orient,
-               int angle_steps, const dock_params *prm, dock_results *out) {
-  g_last_error.clear();
-  if (!p || !ligs || !orient || !out) return fail(DOCK_E_INVAL, "NULL argument");
+static int run_sync(dock_pocket *p, const dock_ligands *ligs, const float *orient, int n_orient,
+                    int angle_steps, const dock_params *prm, dock_results *out,
+                    uint16_t *emit_x, uint16_t *emit_t, uint32_t *emit_mask) {
   int rc = check_params(prm, n_orient, angle_steps);
   if (rc) return rc;
-  int max_n = 0;
-  rc = check_ligands_host(ligs, &max_n);
+  int max_n = 0, max_r = 0;
+  rc = check_ligands_host(ligs, &max_n, &max_r);
   if (rc) return rc;
   const int64_t L = ligs->n_ligands, NA = ligs->total_atoms, NR = ligs->total_rot,
                 NM = ligs->total_move;
   const int passes = prm->passes;
-  if (L > 0 && (!out->best_score || !out->best_orient || !out->xyz_out))
-    return fail(DOCK_E_INVAL, "result array is NULL");
-  if (NR > 0 && !out->angle_idx) return fail(DOCK_E_INVAL, "angle_idx is NULL");
   for (int a = 0; a < n_orient * 12; ++a)
     if (!std::isfinite(orient[a])) return fail(DOCK_E_INVAL, "orientation table is not finite");
   for (int64_t a = 0; a < NA * 3; ++a)
@@ -585,7 +726,7 @@ int dock_batch(dock_pocket *p, const dock_ligands *ligs, const float *orient, in
                o_ai = take(2 * NR * passes), o_xo = take(12 * NA),
                o_as = out->all_scores ? take(4 * L * n_orient) : 0,
                o_aai = out->all_angle_idx ? take(2 * NR * passes * n_orient) : 0,
-               o_st = take(4 * L);
+               o_st = take(4 * L), o_fb = take(4 * L);
   std::lock_guard<std::mutex> lk(p->mu);
   DeviceGuard g(p->device);
   rc = grow(&p->io, &p->io_bytes, off);
@@ -624,10 +765,12 @@ int dock_batch(dock_pocket *p, const dock_ligands *ligs, const float *orient, in
   dr.all_scores = out->all_scores ? (float *)(d + o_as) : nullptr;
   dr.all_angle_idx = out->all_angle_idx ? (int16_t *)(d + o_aai) : nullptr;
   dr.status = (int32_t *)(d + o_st);
+  dr.n_fallback = (int32_t *)(d + o_fb);
   dock_params pr = *prm;
   pr.max_atoms = max_n;
+  pr.max_rot = max_r;
   rc = enqueue_batch(p, &dl, (const float *)(d + o_or), n_orient, angle_steps, &pr, &dr,
-                     p->sync_ws, p->sync_ws_bytes, st);
+                     p->sync_ws, p->sync_ws_bytes, st, emit_x, emit_t, emit_mask);
   if (rc) return rc;
   auto d2h = [&](void *dst, size_t at, size_t bytes) {
     if (e == hipSuccess && dst && bytes)
@@ -640,9 +783,48 @@ int dock_batch(dock_pocket *p, const dock_ligands *ligs, const float *orient, in
   if (out->all_scores) d2h(out->all_scores, o_as, 4 * L * n_orient);
   if (out->all_angle_idx && NR > 0) d2h(out->all_angle_idx, o_aai, 2 * NR * passes * n_orient);
   d2h(out->status, o_st, 4 * L);
+  if (prm->mode == DOCK_MODE_LEARNED) d2h(out->n_fallback, o_fb, 4 * L);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) return hip_fail(e, "batch run");
   return DOCK_OK;
+}
+
+int dock_batch(dock_pocket *p, const dock_ligands *ligs, const float *orient, int n_orient,
+               int angle_steps, const dock_params *prm, dock_results *out) {
+  g_last_error.clear();
+  if (!p || !ligs || !orient || !out) return fail(DOCK_E_INVAL, "NULL argument");
+  if (ligs->n_ligands > 0 && (!out->best_score || !out->best_orient || !out->xyz_out))
+    return fail(DOCK_E_INVAL, "result array is NULL");
+  if (ligs->total_rot > 0 && !out->angle_idx) return fail(DOCK_E_INVAL, "angle_idx is NULL");
+  return run_sync(p, ligs, orient, n_orient, angle_steps, prm, out, nullptr, nullptr, nullptr);
+}
+
+int dock_emit_profiles(dock_pocket *p, const dock_ligands *ligs, const float *orient,
+                       int n_orient, const dock_params *prm, uint16_t *x_out, uint16_t *t_out,
+                       uint32_t *mask_out) {
+  g_last_error.clear();
+  if (!p || !ligs || !orient || !prm || !x_out || !t_out || !mask_out)
+    return fail(DOCK_E_INVAL, "NULL argument");
+  if (prm->mode != DOCK_MODE_PLAIN) return fail(DOCK_E_INVAL, "profiles come from the plain sweep");
+  dock_results none{};
+  return run_sync(p, ligs, orient, n_orient, 256, prm, &none, x_out, t_out, mask_out);
+}
+
+int dock_load_proposal(dock_pocket *p, dock_mlp *m) {
+  g_last_error.clear();
+  if (!p || !m) return fail(DOCK_E_INVAL, "NULL argument");
+  DeviceGuard g(p->device);
+  std::lock_guard<std::mutex> lk(p->mu);
+  hipError_t e = hipSuccess;
+  if (!p->prop_wb) e = hipMalloc((void **)&p->prop_wb, sizeof(uint16_t) * kMlpParams);
+  if (e == hipSuccess && !p->prop_w) e = hipMalloc((void **)&p->prop_w, sizeof(float) * kMlpParams);
+  const uint16_t *wb = nullptr;
+  const float *w = nullptr;
+  mlp_export_weights(m, &wb, &w);
+  if (e == hipSuccess)
+    e = hipMemcpy(p->prop_wb, wb, sizeof(uint16_t) * kMlpParams, hipMemcpyDeviceToDevice);
+  if (e == hipSuccess) e = hipMemcpy(p->prop_w, w, sizeof(float) * kMlpParams, hipMemcpyDeviceToDevice);
+  return e == hipSuccess ? DOCK_OK : hip_fail(e, "dock_load_proposal");
 }
 
 }  // extern "C"

@@ -50,6 +50,12 @@ struct SweepArgs {
   unsigned long long *keys;  // [n_ligands] best (score, orientation) key
   int16_t *kstar;            // [total_rot * passes * n_orient]
   float *all_scores;         // optional [n_ligands][n_orient]
+  // profile emission (learned-proposal training data), per step in the
+  // layout of kstar: features [64] and score landscape [256] as BF16, and
+  // the 256-bit validity mask; all NULL unless emitting
+  uint16_t *emit_x;
+  uint16_t *emit_t;
+  uint32_t *emit_mask;
 };
 
 struct FinalOut {
@@ -68,6 +74,7 @@ struct LaunchPlan {
 hipError_t enqueue_prepare(const SweepArgs &A, int max_atoms, bool lpt, int32_t *bucket_of,
                            int32_t *counts, int32_t *cursor, int32_t *n_bad,
                            hipStream_t st);
+hipError_t enqueue_fill_i32(int32_t *p, int n, int32_t v, hipStream_t st);
 hipError_t enqueue_sweep(const SweepArgs &A, int maxn, const LaunchPlan &plan, int n_cu,
                          hipStream_t st);
 hipError_t enqueue_sweep_pruned(const SweepArgs &A, int max_atoms, const LaunchPlan &plan,

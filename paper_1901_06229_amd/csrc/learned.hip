@@ -1,0 +1,238 @@
+// Learned angle proposal inside the greedy sweep (phase-synchronous form).
+//
+// All items of a batch advance one rotamer step at a time so the MLP runs as
+// large matrix products over every item's features:
+//   begin:  stage the rigid pose, set up the first rotamer, write its 64
+//           features and its exact validity mask (bump test of all angles);
+//   MLP:    predicted score landscape (256 bins) for every item;
+//   step:   nominate the top_k valid bins by prediction (plus angle 0),
+//           score them exactly, keep the best; if the predicted margin
+//           (best minus the (top_k+1)-th valid prediction) is below the
+//           threshold, score every valid angle instead (the plain sweep's
+//           step, bit for bit); apply, then set up the next rotamer and
+//           write its features and mask.
+// Validity is never predicted: it is the same exact bump test as the plain
+// sweep, so a nominated angle is always a valid one.
+#include <hip/hip_runtime.h>
+
+#include "dock_internal.h"
+#include "learned_internal.h"
+#include "rotamer_step.h"
+#include "sweep_common.h"
+
+namespace dock {
+
+// Orderable 32-bit key of (prediction, -bin) for the nomination rounds.
+__device__ __forceinline__ uint32_t nom_key(float y, int k) {
+  return (float_order(y) & 0xFFFFFF00u) | (uint32_t)(255 - k);
+}
+
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t o = (uint32_t)__shfl_xor((int)v, off, kWave);
+    v = o > v ? o : v;
+  }
+  return v;
+}
+
+// Rotamer index and step bookkeeping of an item.
+struct ItemInfo {
+  int l, o, n, R, r0, a0, steps;
+};
+
+__device__ __forceinline__ ItemInfo item_info(const LearnedArgs &A, int item) {
+  ItemInfo I;
+  I.l = item / A.sw.n_orient;
+  I.o = item - I.l * A.sw.n_orient;
+  I.a0 = A.sw.lig.atom_offset[I.l];
+  I.n = A.sw.lig.atom_offset[I.l + 1] - I.a0;
+  I.r0 = A.sw.lig.rot_offset[I.l];
+  I.R = A.sw.lig.rot_offset[I.l + 1] - I.r0;
+  I.steps = I.R * A.sw.passes;
+  return I;
+}
+
+__device__ __forceinline__ RotState setup_step(const LearnedArgs &A, const WaveLds &W,
+                                               const ItemInfo &I, int step, int lane) {
+  const int r = step % I.R;
+  const int ms = A.sw.lig.move_offset[I.r0 + r];
+  return rotamer_setup(W, I.n, A.sw.lig.rot_axis[2 * (I.r0 + r)],
+                       A.sw.lig.rot_axis[2 * (I.r0 + r) + 1], A.sw.lig.move_atoms + ms,
+                       A.sw.lig.move_offset[I.r0 + r + 1] - ms, lane);
+}
+
+// Features and exact validity of the rotamer step just set up.
+__device__ __forceinline__ void write_step_inputs(const LearnedArgs &A, const WaveLds &W,
+                                                  const RotState &RS, int item, int lane) {
+  const GridView G = A.sw.grid;
+  A.feat[(size_t)item * 64 + lane] = f32_to_bf16(rotamer_feature(W, RS, G, lane));
+  float cc[4], ss[4];
+  uint32_t bump = 0;
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const float2 cs = A.sw.cs[t * kWave + lane];
+    cc[t] = cs.x;
+    ss[t] = cs.y;
+  }
+  rotamer_bumps<4>(W, RS, A.sw.r2, A.sw.r2 + kPruneMargin, cc, ss, bump, lane);
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const uint64_t vm = __ballot(!((bump >> t) & 1u));
+    if (lane == 0) A.valid[(size_t)item * 4 + t] = vm;
+  }
+}
+
+__device__ __forceinline__ void finish_item(const LearnedArgs &A, const WaveLds &W,
+                                            const ItemInfo &I, int lane) {
+  float total = 0.0f;
+  for (int i = lane; i < I.n; i += kWave) total += W.X[i].w;
+  total = wave_sum(total);
+  if (lane == 0) {
+    if (A.sw.all_scores) A.sw.all_scores[(size_t)I.l * A.sw.n_orient + I.o] = total;
+    atomicMax(A.sw.keys + I.l, (unsigned long long)best_key(total, (uint32_t)I.o));
+  }
+}
+
+__device__ __forceinline__ void save_pose(const LearnedArgs &A, const WaveLds &W, int item,
+                                          int n, int lane) {
+  float4 *dst = A.pose + (size_t)item * A.nmax;
+  for (int i = lane; i < n; i += kWave) dst[i] = W.X[i];
+}
+
+__global__ void __launch_bounds__(kWave) learned_begin_kernel(LearnedArgs A) {
+  extern __shared__ float4 dyn_lds[];
+  const int lane = threadIdx.x;
+  const WaveLds W((char *)dyn_lds, A.nmax);
+  for (int item = blockIdx.x; item < A.sw.n_items; item += gridDim.x) {
+    const ItemInfo I = item_info(A, item);
+    if (A.sw.status[I.l] != 0) continue;
+    stage_pose(W, A.sw.grid, A.sw.lig.xyz + 3 * (size_t)I.a0, I.n, A.sw.orient + 12 * I.o, lane);
+    if (I.steps == 0) {
+      finish_item(A, W, I, lane);
+    } else {
+      const RotState RS = setup_step(A, W, I, 0, lane);
+      write_step_inputs(A, W, RS, item, lane);
+      save_pose(A, W, item, I.n, lane);
+    }
+    wave_lds_sync();
+  }
+}
+
+__global__ void __launch_bounds__(kWave) learned_step_kernel(LearnedArgs A, int step) {
+  extern __shared__ float4 dyn_lds[];
+  const int lane = threadIdx.x;
+  const WaveLds W((char *)dyn_lds, A.nmax);
+  const GridView G = A.sw.grid;
+  const GridScaled GS = grid_scaled(G);
+  const __amdgpu_buffer_rsrc_t grsrc = grid_rsrc(G);
+  for (int item = blockIdx.x; item < A.sw.n_items; item += gridDim.x) {
+    const ItemInfo I = item_info(A, item);
+    if (A.sw.status[I.l] != 0 || step >= I.steps) continue;
+    const float4 *src = A.pose + (size_t)item * A.nmax;
+    for (int i = lane; i < I.n; i += kWave) W.X[i] = src[i];
+    wave_lds_sync();
+    const RotState RS = setup_step(A, W, I, step, lane);
+    const float s0 = rotamer_s0(W, RS);
+    // predictions of this item's 256 bins, invalid ones out of the race
+    const float *y = A.pred + (size_t)item * 256;
+    uint64_t vm[4];
+    uint32_t key[4];
+    bool any_valid = false;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      vm[t] = A.valid[(size_t)item * 4 + t];
+      const bool v = (vm[t] >> lane) & 1ull;
+      key[t] = v ? nom_key(y[t * kWave + lane], t * kWave + lane) : 0u;
+      any_valid = any_valid || vm[t] != 0ull;
+    }
+    // nomination rounds: the top_k valid bins, then the next one for the margin
+    int nom = -1;  // lane j < top_k receives the j-th nominated bin
+    uint32_t first = 0u, kth1 = 0u;
+    for (int j = 0; j <= A.top_k; ++j) {
+      uint32_t mine = key[0];
+#pragma unroll
+      for (int t = 1; t < 4; ++t) mine = key[t] > mine ? key[t] : mine;
+      const uint32_t win = wave_max_u32(mine);
+      if (win == 0u) break;
+      if (j == 0) first = win;
+      if (j == A.top_k) {
+        kth1 = win;
+        break;
+      }
+      const int kbin = 255 - (int)(win & 0xFFu);
+      if (lane == j) nom = kbin;
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+        if (key[t] == win) key[t] = 0u;
+    }
+    const float margin = kth1 ? order_float(first | 0xFFu) - order_float(kth1 | 0xFFu) : 3.0e38f;
+    const bool fallback = any_valid && margin < A.margin;
+    uint64_t best = 0ull;
+    if (fallback) {  // the plain step over every valid angle
+      float cc[4], ss[4], score[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const float2 cs = A.sw.cs[t * kWave + lane];
+        cc[t] = cs.x;
+        ss[t] = cs.y;
+      }
+      rotamer_scores<4>(W, RS, G, GS, grsrc, cc, ss, score, lane);
+      if (lane == 0) score[0] = s0;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int k = t * kWave + lane;
+        const uint64_t kk = (vm[t] >> lane) & 1ull ? best_key(score[t], (uint32_t)k) : 0ull;
+        best = kk > best ? kk : best;
+      }
+      if (lane == 0) atomicAdd(A.n_fallback + I.l, 1);
+    } else if (any_valid) {  // nominated bins plus the current pose
+      const bool zero_valid = vm[0] & 1ull;
+      if (lane == A.top_k && zero_valid) nom = 0;
+      const int ang = nom >= 0 ? nom : 0;
+      const float2 cs = A.sw.cs[ang];
+      float cc[1] = {cs.x}, ss[1] = {cs.y}, score[1];
+      rotamer_scores<1>(W, RS, G, GS, grsrc, cc, ss, score, lane);
+      if (ang == 0) score[0] = s0;
+      best = nom >= 0 ? best_key(score[0], (uint32_t)ang) : 0ull;
+    }
+    best = wave_max_u64(best);
+    const int kb = best ? (int)key_index(best) : -1;
+    if (lane == 0)
+      A.sw.kstar[((size_t)I.r0 * A.sw.n_orient + (size_t)I.o * I.R) * A.sw.passes + step] =
+          (int16_t)kb;
+    if (kb > 0) {
+      const float2 cs = A.sw.cs[kb];
+      rotamer_apply(W, RS, G, cs.x, cs.y, lane);
+    }
+    if (step + 1 < I.steps) {
+      const RotState RN = setup_step(A, W, I, step + 1, lane);
+      write_step_inputs(A, W, RN, item, lane);
+      save_pose(A, W, item, I.n, lane);
+    } else {
+      finish_item(A, W, I, lane);
+    }
+    wave_lds_sync();
+  }
+}
+
+static unsigned grid_for(int n_items, int n_cu) {
+  const int64_t g = (int64_t)n_cu * 16;
+  return (unsigned)(n_items < g ? (n_items > 0 ? n_items : 1) : g);
+}
+
+hipError_t enqueue_learned_begin(const LearnedArgs &A, int n_cu, hipStream_t st) {
+  if (A.sw.n_items <= 0) return hipSuccess;
+  hipLaunchKernelGGL(learned_begin_kernel, dim3(grid_for(A.sw.n_items, n_cu)), dim3(kWave),
+                     wave_lds_bytes(A.nmax), st, A);
+  return hipGetLastError();
+}
+
+hipError_t enqueue_learned_step(const LearnedArgs &A, int step, int n_cu, hipStream_t st) {
+  if (A.sw.n_items <= 0) return hipSuccess;
+  hipLaunchKernelGGL(learned_step_kernel, dim3(grid_for(A.sw.n_items, n_cu)), dim3(kWave),
+                     wave_lds_bytes(A.nmax), st, A, step);
+  return hipGetLastError();
+}
+
+}  // namespace dock

@@ -1,0 +1,337 @@
+// One rotamer step of one (ligand, orientation) item, for a 64-lane wave
+// whose pose lives in LDS.  Shared by the plain sweep, the profile emitter and
+// the learned-proposal kernels so all of them evaluate angles with identical
+// arithmetic.
+//
+// Geometry of a rotation about the fixed bond axis (a, u):
+//   * an atom is kept in cylindrical form, radial vector r and axial z; at
+//     angle theta it sits at a + z u + cos(theta) r + sin(theta) (u x r);
+//   * a cross pair (i moving, j static) has squared distance
+//     D' - 2 (cos(theta) A + sin(theta) B), A = r_i.r_j, B = u.(r_i x r_j),
+//     D' = |r_i|^2 + |r_j|^2 + (z_i - z_j)^2, never below
+//     (|r_i| - |r_j|)^2 + (z_i - z_j)^2.  Pairs whose bound clears
+//     r_bump^2 + kPruneMargin cannot bump at any angle and are dropped; the
+//     kept pairs are tested at every angle of the lane.
+// Each lane carries TG angle slots given by their (cos, sin); the slot-to-
+// angle mapping is the caller's (tiles of consecutive steps for the sweep,
+// nominated steps for the learned proposal).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "dock_internal.h"
+#include "sweep_common.h"
+
+namespace dock {
+
+constexpr int kPairCap = 128;  // LDS pair-list entries per wave
+
+__host__ __device__ inline int wave_head_bytes(int nmax) {
+  // X, C (float4), rho (float), Q, M (int16), mov (uint8)
+  const int b = nmax * 16 * 2 + nmax * 4 + nmax * 2 * 2 + nmax;
+  return (b + 15) / 16 * 16;
+}
+
+__host__ __device__ inline int wave_lds_bytes(int nmax) {
+  // then the pair list: coefficients (float4) and packed atom pairs (int32)
+  return wave_head_bytes(nmax) + kPairCap * (16 + 4);
+}
+
+struct WaveLds {
+  float4 *X;     // pose: x, y, z, voxel value
+  float4 *C;     // cylindrical coordinates about the current axis: r, z
+  float *rho;    // |r|
+  int16_t *Q;    // static cross set of the rotamer
+  int16_t *M;    // moving set of the rotamer
+  uint8_t *mov;  // moving flags
+  float4 *P;     // kept pairs: 2A, 2B, D' - r_bump^2
+  int *PI;       // kept pairs: i << 16 | j
+  __device__ WaveLds(char *base, int nmax) {
+    X = (float4 *)base;
+    C = X + nmax;
+    rho = (float *)(C + nmax);
+    Q = (int16_t *)(rho + nmax);
+    M = Q + nmax;
+    mov = (uint8_t *)(M + nmax);
+    P = (float4 *)(base + wave_head_bytes(nmax));
+    PI = (int *)(P + kPairCap);
+  }
+};
+
+struct RotState {
+  int m, q;
+  float cst;  // score of every atom that does not move
+  float4 xa;  // axis point
+  float3 u;   // unit axis
+};
+
+__device__ __forceinline__ uint64_t lanes_below_mask(int lane) {
+  return (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+}
+
+// Moving / static sets, the static score, the axis and cylindrical coords.
+__device__ __forceinline__ RotState rotamer_setup(const WaveLds &W, int n, int ra, int rb,
+                                                  const int16_t *mlist, int m, int lane) {
+  const uint64_t below = lanes_below_mask(lane);
+  for (int i = lane; i < n; i += kWave) W.mov[i] = 0;
+  wave_lds_sync();
+  for (int t = lane; t < m; t += kWave) {
+    const int i = mlist[t];
+    W.mov[i] = 1;
+    W.M[t] = (int16_t)i;
+  }
+  wave_lds_sync();
+  RotState R;
+  R.m = m;
+  int q = 0;
+  for (int base = 0; base < n; base += kWave) {
+    const int i = base + lane;
+    const bool st = i < n && !W.mov[i] && i != ra && i != rb;
+    const uint64_t mask = __ballot(st);
+    if (st) W.Q[q + __popcll(mask & below)] = (int16_t)i;
+    q += __popcll(mask);
+  }
+  R.q = q;
+  // per-lane partial sums in atom order, then a fixed butterfly over the wave
+  float cst = 0.0f;
+  for (int i = lane; i < n; i += kWave)
+    if (!W.mov[i]) cst += W.X[i].w;
+  R.cst = wave_sum(cst);
+  R.xa = W.X[ra];
+  R.u = bond_axis(R.xa, W.X[rb]);
+  for (int i = lane; i < n; i += kWave) {
+    const Cyl c = cyl_of(W.X[i], R.xa, R.u);
+    W.C[i] = make_float4(c.rx, c.ry, c.rz, c.z);
+    W.rho[i] = sqrtf(fmaf(c.rx, c.rx, fmaf(c.ry, c.ry, c.rz * c.rz)));
+  }
+  wave_lds_sync();
+  return R;
+}
+
+// Score of the current pose (angle step 0): static score plus the moving
+// atoms' own values, in atom order -- the same order the angle scores use.
+__device__ __forceinline__ float rotamer_s0(const WaveLds &W, const RotState &R) {
+  float s = R.cst;
+  for (int t = 0; t < R.m; ++t) s += W.X[W.M[t]].w;
+  return s;
+}
+
+template <int TG>
+__device__ __forceinline__ void test_kept_pairs(const WaveLds &W, const RotState &R, float r2,
+                                                int cnt, const float (&cc)[TG],
+                                                const float (&ss)[TG], uint32_t &bump,
+                                                int lane) {
+  for (int e = lane; e < cnt; e += kWave) {
+    const int ij = W.PI[e];
+    const float4 ci = W.C[ij >> 16], cj = W.C[ij & 0xFFFF];
+    const float dz = ci.w - cj.w;
+    const float a_ = fmaf(ci.x, cj.x, fmaf(ci.y, cj.y, ci.z * cj.z));
+    const float cx = ci.y * cj.z - ci.z * cj.y;
+    const float cy = ci.z * cj.x - ci.x * cj.z;
+    const float cz = ci.x * cj.y - ci.y * cj.x;
+    const float b_ = fmaf(R.u.x, cx, fmaf(R.u.y, cy, R.u.z * cz));
+    const float rho2i = fmaf(ci.x, ci.x, fmaf(ci.y, ci.y, ci.z * ci.z));
+    const float rho2j = fmaf(cj.x, cj.x, fmaf(cj.y, cj.y, cj.z * cj.z));
+    W.P[e] = make_float4(2.0f * a_, 2.0f * b_, fmaf(dz, dz, rho2i + rho2j) - r2, 0.0f);
+  }
+  wave_lds_sync();
+  for (int e = 0; e < cnt; ++e) {
+    const float4 pr = W.P[e];
+#pragma unroll
+    for (int t = 0; t < TG; ++t)
+      if (fmaf(cc[t], pr.x, ss[t] * pr.y) > pr.z) bump |= 1u << t;
+  }
+  wave_lds_sync();
+}
+
+// Bump test of the lane's TG angle slots.  Lanes sweep the flattened cross
+// pairs (i in M, j in Q), keep those whose lower bound does not clear r_bump
+// and compact them into the LDS list, which every lane then tests.  Returns
+// the number of kept pairs.
+template <int TG>
+__device__ __forceinline__ int rotamer_bumps(const WaveLds &W, const RotState &R, float r2,
+                                             float thr, const float (&cc)[TG],
+                                             const float (&ss)[TG], uint32_t &bump, int lane) {
+  const uint64_t below = lanes_below_mask(lane);
+  const int total = R.m * R.q;
+  const float inv_q = R.q > 0 ? 1.0f / (float)R.q : 0.0f;
+  int np = 0, kept = 0;
+  for (int base = 0; base < total; base += kWave) {
+    const int pidx = base + lane;
+    bool act = false;
+    int packed = 0;
+    if (pidx < total) {
+      int ii = (int)(((float)pidx + 0.5f) * inv_q);
+      int jj = pidx - ii * R.q;
+      if (jj < 0) {
+        --ii;
+        jj += R.q;
+      }
+      if (jj >= R.q) {
+        ++ii;
+        jj -= R.q;
+      }
+      const int i = W.M[ii], j = W.Q[jj];
+      const float dz = W.C[i].w - W.C[j].w;
+      const float dr = W.rho[i] - W.rho[j];
+      act = fmaf(dr, dr, dz * dz) < thr;
+      packed = (i << 16) | j;
+    }
+    const uint64_t mask = __ballot(act);
+    if (act) W.PI[np + __popcll(mask & below)] = packed;
+    np += __popcll(mask);
+    if (np > kPairCap - kWave) {
+      wave_lds_sync();
+      test_kept_pairs<TG>(W, R, r2, np, cc, ss, bump, lane);
+      kept += np;
+      np = 0;
+    }
+  }
+  wave_lds_sync();
+  test_kept_pairs<TG>(W, R, r2, np, cc, ss, bump, lane);
+  return kept + np;
+}
+
+// Scores of the lane's TG angle slots: static score plus the voxel values
+// of the rotated moving atoms, added in atom order.  Lanes hold the voxel-
+// space rotation basis ((p - o)/h, e/h, f/h) of up to 64 moving atoms; each
+// lane reads one atom's basis at a time and issues the gathers of all its
+// slots before using any of them.
+template <int TG>
+__device__ __forceinline__ void rotamer_scores(const WaveLds &W, const RotState &R,
+                                               const GridView &G, const GridScaled &GS,
+                                               __amdgpu_buffer_rsrc_t grsrc,
+                                               const float (&cc)[TG], const float (&ss)[TG],
+                                               float (&score)[TG], int lane) {
+#pragma unroll
+  for (int t = 0; t < TG; ++t) score[t] = R.cst;
+  for (int c0 = 0; c0 < R.m; c0 += kWave) {
+    float b0 = 0.f, b1 = 0.f, b2 = 0.f, b3 = 0.f, b4 = 0.f, b5 = 0.f, b6 = 0.f, b7 = 0.f,
+          b8 = 0.f;
+    if (c0 + lane < R.m) {
+      const float4 ci = W.C[W.M[c0 + lane]];
+      const RotBasis bs = rot_basis(Cyl{ci.x, ci.y, ci.z, ci.w}, R.xa, R.u);
+      b0 = (bs.px - G.ox) * G.inv_h;
+      b1 = (bs.py - G.oy) * G.inv_h;
+      b2 = (bs.pz - G.oz) * G.inv_h;
+      b3 = bs.ex * G.inv_h;
+      b4 = bs.ey * G.inv_h;
+      b5 = bs.ez * G.inv_h;
+      b6 = bs.fx * G.inv_h;
+      b7 = bs.fy * G.inv_h;
+      b8 = bs.fz * G.inv_h;
+    }
+    const int cnt = min(kWave, R.m - c0);
+    for (int tt = 0; tt < cnt; ++tt) {
+      const float px = lane_bcast(b0, tt), py = lane_bcast(b1, tt), pz = lane_bcast(b2, tt);
+      const float ex = lane_bcast(b3, tt), ey = lane_bcast(b4, tt), ez = lane_bcast(b5, tt);
+      const float fx = lane_bcast(b6, tt), fy = lane_bcast(b7, tt), fz = lane_bcast(b8, tt);
+      uint32_t off[TG];
+#pragma unroll
+      for (int t = 0; t < TG; ++t)
+        off[t] = voxel_byte_offset(GS, fmaf(ss[t], fx, fmaf(cc[t], ex, px)),
+                                   fmaf(ss[t], fy, fmaf(cc[t], ey, py)),
+                                   fmaf(ss[t], fz, fmaf(cc[t], ez, pz)));
+      float val[TG];
+#pragma unroll
+      for (int t = 0; t < TG; ++t) val[t] = grid_load(grsrc, off[t]);
+#pragma unroll
+      for (int t = 0; t < TG; ++t) score[t] += val[t];
+    }
+  }
+}
+
+// Rotate the moving atoms of the pose in LDS by the angle (c, s).
+__device__ __forceinline__ void rotamer_apply(const WaveLds &W, const RotState &R,
+                                              const GridView &G, float c, float s, int lane) {
+  for (int t = lane; t < R.m; t += kWave) {
+    const int i = W.M[t];
+    const float4 ci = W.C[i];
+    const RotBasis bs = rot_basis(Cyl{ci.x, ci.y, ci.z, ci.w}, R.xa, R.u);
+    const float3 y = rot_apply(bs, c, s);
+    W.X[i] = make_float4(y.x, y.y, y.z, voxel_value(G, y.x, y.y, y.z));
+  }
+  wave_lds_sync();
+}
+
+__device__ __forceinline__ float wave_max_f(float v) {
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) v = fmaxf(v, __shfl_xor(v, off, kWave));
+  return v;
+}
+__device__ __forceinline__ float wave_min_f(float v) {
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) v = fminf(v, __shfl_xor(v, off, kWave));
+  return v;
+}
+
+// The 64 input features of the learned proposal for this rotamer step: grid
+// values on a 4 x 4 x 4 lattice in the rotamer's local frame -- z along the
+// bond axis, x from the axis towards the moving set's centroid, y = z x x --
+// spanning the swept cylinder (radius = largest |r| of the moving atoms,
+// axial range [min z - 1, max z + 1]).  Values below -1 (outside the cavity)
+// are clamped to -1.  Lane f computes feature f = (16 ix + 4 iy + iz).
+__device__ __forceinline__ float rotamer_feature(const WaveLds &W, const RotState &R,
+                                                 const GridView &G, int lane) {
+  float sx = 0.f, sy = 0.f, sz = 0.f, rmax = 0.f, zmin = 3.0e38f, zmax = -3.0e38f;
+  for (int t = lane; t < R.m; t += kWave) {
+    const int i = W.M[t];
+    const float4 ci = W.C[i];
+    sx += ci.x;
+    sy += ci.y;
+    sz += ci.z;
+    rmax = fmaxf(rmax, W.rho[i]);
+    zmin = fminf(zmin, ci.w);
+    zmax = fmaxf(zmax, ci.w);
+  }
+  sx = wave_sum(sx);
+  sy = wave_sum(sy);
+  sz = wave_sum(sz);
+  rmax = fmaxf(wave_max_f(rmax), 1e-3f);
+  zmin = wave_min_f(zmin);
+  zmax = wave_max_f(zmax);
+  if (R.m == 0) {
+    zmin = 0.0f;
+    zmax = 0.0f;
+  }
+  const float3 u = R.u;
+  float cl2 = fmaf(sx, sx, fmaf(sy, sy, sz * sz));
+  if (!(cl2 > 1e-12f)) {  // no radial direction: any axis perpendicular to u
+    if (fabsf(u.x) < 0.9f) {
+      sx = 0.0f;
+      sy = -u.z;
+      sz = u.y;  // u x (1, 0, 0)
+    } else {
+      sx = u.z;
+      sy = 0.0f;
+      sz = -u.x;  // u x (0, 1, 0)
+    }
+    cl2 = fmaf(sx, sx, fmaf(sy, sy, sz * sz));
+  }
+  const float inv = 1.0f / sqrtf(cl2);
+  const float ex = sx * inv, ey = sy * inv, ez = sz * inv;
+  const float fx = u.y * ez - u.z * ey, fy = u.z * ex - u.x * ez, fz = u.x * ey - u.y * ex;
+  const int ia = lane >> 4, ib = (lane >> 2) & 3, ic = lane & 3;
+  const float lx = -rmax + 2.0f * rmax * (float)ia / 3.0f;
+  const float ly = -rmax + 2.0f * rmax * (float)ib / 3.0f;
+  const float z0 = zmin - 1.0f, z1 = zmax + 1.0f;
+  const float lz = z0 + (z1 - z0) * (float)ic / 3.0f;
+  const float px = R.xa.x + lx * ex + ly * fx + lz * u.x;
+  const float py = R.xa.y + lx * ey + ly * fy + lz * u.y;
+  const float pz = R.xa.z + lx * ez + ly * fz + lz * u.z;
+  return fmaxf(voxel_value(G, px, py, pz), -1.0f);
+}
+
+// Stage the rigid starting pose (orientation T) of a ligand in LDS.
+__device__ __forceinline__ void stage_pose(const WaveLds &W, const GridView &G, const float *xyz,
+                                           int n, const float *T, int lane) {
+  for (int i = lane; i < n; i += kWave) {
+    const float *p = xyz + 3 * (size_t)i;
+    const float3 x = orient_point(T, p[0], p[1], p[2]);
+    W.X[i] = make_float4(x.x, x.y, x.z, voxel_value(G, x.x, x.y, x.z));
+  }
+  wave_lds_sync();
+}
+
+}  // namespace dock

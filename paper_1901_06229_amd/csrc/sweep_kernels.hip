@@ -104,6 +104,11 @@ __global__ void lpt_scatter_kernel(int n_ligands, const int32_t *bucket_of,
   order[pos] = l;
 }
 
+__global__ void fill_i32_kernel(int32_t *p, int n, int32_t v) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
 __global__ void identity_order_kernel(int n, int32_t *order) {
   int l = blockIdx.x * blockDim.x + threadIdx.x;
   if (l < n) order[l] = l;
@@ -318,6 +323,12 @@ __global__ void __launch_bounds__(kWave) finalize_kernel(SweepArgs A, FinalOut F
 
 // ---------------------------------------------------------------- launches
 static inline unsigned blocks_for(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+hipError_t enqueue_fill_i32(int32_t *p, int n, int32_t v, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_i32_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, st, p, n, v);
+  return hipGetLastError();
+}
 
 hipError_t enqueue_prepare(const SweepArgs &A, int max_atoms, bool lpt,
                            int32_t *bucket_of, int32_t *counts, int32_t *cursor,

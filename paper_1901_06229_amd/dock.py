@@ -35,7 +35,7 @@ class dock_ligands(ctypes.Structure):
 class dock_params(ctypes.Structure):
     _fields_ = [("r_bump", ctypes.c_float), ("passes", ctypes.c_int32), ("mode", ctypes.c_int32),
                 ("top_k", ctypes.c_int32), ("margin", ctypes.c_float), ("flags", ctypes.c_uint32),
-                ("max_atoms", ctypes.c_int32)]
+                ("max_atoms", ctypes.c_int32), ("max_rot", ctypes.c_int32)]
 
 
 class dock_results(ctypes.Structure):
@@ -111,6 +111,26 @@ def load_library(path: str = None):
                                   c.POINTER(dock_params), c.c_int, c.c_uint64,
                                   c.POINTER(dock_tune_entry), c.c_int, c.POINTER(c.c_int)]
     lib.dock_autotune.restype = c.c_int
+    lib.dock_mlp_param_count.argtypes = []
+    lib.dock_mlp_param_count.restype = c.c_size_t
+    lib.dock_mlp_create.argtypes = [_P, c.POINTER(_P)]
+    lib.dock_mlp_create.restype = c.c_int
+    lib.dock_mlp_free.argtypes = [_P]
+    lib.dock_mlp_free.restype = None
+    for name in ("dock_mlp_get_params", "dock_mlp_set_params"):
+        getattr(lib, name).argtypes = [_P, _P]
+        getattr(lib, name).restype = c.c_int
+    lib.dock_mlp_forward.argtypes = [_P, _P, c.c_int, _P, _P]
+    lib.dock_mlp_forward.restype = c.c_int
+    lib.dock_mlp_loss_grad.argtypes = [_P, _P, _P, c.c_int, _P, c.POINTER(c.c_float), _P]
+    lib.dock_mlp_loss_grad.restype = c.c_int
+    lib.dock_mlp_adam.argtypes = [_P, c.c_float, c.c_float, c.c_float, c.c_float, _P]
+    lib.dock_mlp_adam.restype = c.c_int
+    lib.dock_load_proposal.argtypes = [_P, _P]
+    lib.dock_load_proposal.restype = c.c_int
+    lib.dock_emit_profiles.argtypes = [_P, c.POINTER(dock_ligands), _P, c.c_int,
+                                       c.POINTER(dock_params), _P, _P, _P]
+    lib.dock_emit_profiles.restype = c.c_int
     lib.dock_strerror.argtypes = [c.c_int]
     lib.dock_strerror.restype = c.c_char_p
     lib.dock_last_error.argtypes = []
@@ -172,9 +192,9 @@ def dock_free_pocket(p: Pocket):
 
 
 def make_params(r_bump=2.0, passes=1, mode=DOCK_MODE_PLAIN, top_k=16, margin=0.0, flags=0,
-                max_atoms=0) -> dock_params:
+                max_atoms=0, max_rot=0) -> dock_params:
     return dock_params(float(r_bump), int(passes), int(mode), int(top_k), float(margin),
-                       int(flags), int(max_atoms))
+                       int(flags), int(max_atoms), int(max_rot))
 
 
 def dock_batch(pocket: Pocket, ligs, orient, angle_steps: int, r_bump: float = 2.0,
@@ -307,3 +327,77 @@ def dock_batch_async(pocket: Pocket, dev: dict, orient_dev, angle_steps: int, ou
     _check(lib.dock_batch_async(pocket.handle, ctypes.byref(dl), _tptr(orient_dev), n_orient,
                                 int(angle_steps), ctypes.byref(params), ctypes.byref(dr), ws_ptr,
                                 ws_bytes, st), "dock_batch_async")
+
+
+# ---------------------------------------------------------------- learned proposal
+class Mlp:
+    """Owns a dock_mlp (the learned-proposal network on the current device)."""
+
+    def __init__(self, params: np.ndarray):
+        lib = load_library()
+        p = _c(params, np.float32)
+        if p.size != mlp_param_count():
+            raise ValueError(f"expected {mlp_param_count()} parameters, got {p.size}")
+        h = _P()
+        _check(lib.dock_mlp_create(_np_ptr(p), ctypes.byref(h)), "dock_mlp_create")
+        self.handle = h
+
+    def close(self):
+        if self.handle:
+            load_library().dock_mlp_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def get_params(self) -> np.ndarray:
+        out = np.empty(mlp_param_count(), np.float32)
+        _check(load_library().dock_mlp_get_params(self.handle, _np_ptr(out)), "dock_mlp_get_params")
+        return out
+
+    def set_params(self, params):
+        p = _c(params, np.float32)
+        _check(load_library().dock_mlp_set_params(self.handle, _np_ptr(p)), "dock_mlp_set_params")
+
+    def forward(self, x_bf16, y_f32, stream=None):
+        """x_bf16: device int16/bfloat16 tensor [rows, 64]; y_f32: device [rows, 256]."""
+        st = None if stream is None else ctypes.c_void_p(stream.cuda_stream)
+        _check(load_library().dock_mlp_forward(self.handle, _tptr(x_bf16), int(x_bf16.shape[0]),
+                                               _tptr(y_f32), st), "dock_mlp_forward")
+
+    def loss_grad(self, x_bf16, t_bf16, grad_out=None, stream=None, want_loss=True):
+        st = None if stream is None else ctypes.c_void_p(stream.cuda_stream)
+        loss = ctypes.c_float()
+        _check(load_library().dock_mlp_loss_grad(
+            self.handle, _tptr(x_bf16), _tptr(t_bf16), int(x_bf16.shape[0]), _tptr(grad_out),
+            ctypes.byref(loss) if want_loss else None, st), "dock_mlp_loss_grad")
+        return float(loss.value) if want_loss else None
+
+    def adam(self, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+        st = None if stream is None else ctypes.c_void_p(stream.cuda_stream)
+        _check(load_library().dock_mlp_adam(self.handle, float(lr), float(beta1), float(beta2),
+                                            float(eps), st), "dock_mlp_adam")
+
+
+def mlp_param_count() -> int:
+    return int(load_library().dock_mlp_param_count())
+
+
+def dock_load_proposal(pocket: Pocket, mlp: Mlp):
+    _check(load_library().dock_load_proposal(pocket.handle, mlp.handle), "dock_load_proposal")
+
+
+def dock_emit_profiles(pocket: Pocket, ligs, orient, x_out, t_out, mask_out, r_bump=2.0,
+                       passes=1):
+    """Plain sweep (S = 256) writing per-step features, landscapes and masks
+    into device tensors of total_rot*passes*n_orient rows."""
+    lib = load_library()
+    dl, keep = _host_ligands(ligs)
+    orient = _c(orient, np.float32).reshape(-1, 12)
+    prm = make_params(r_bump=r_bump, passes=passes)
+    _check(lib.dock_emit_profiles(pocket.handle, ctypes.byref(dl), _np_ptr(orient), orient.shape[0],
+                                  ctypes.byref(prm), _tptr(x_out), _tptr(t_out), _tptr(mask_out)),
+           "dock_emit_profiles")

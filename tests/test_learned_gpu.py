@@ -1,0 +1,194 @@
+"""Learned proposal on the GPU: MLP kernels against the FP64 reference, the
+profile emitter against the reference's profiles and features, and the
+learned sweep's own guarantees (fallback everywhere = plain sweep; every
+chosen angle valid and the pose consistent with the reference replay)."""
+import numpy as np
+import pytest
+
+import oracle
+import oracle.mlp as om
+from oracle.features import features as ref_features, landscape as ref_landscape
+from paper_1901_06229_amd import dock, learned, synth
+from tests.checker import check_item, item_steps, tol_of
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    torch.cuda.set_device(0)
+    return torch
+
+
+def _to_bf16_bits(torch, a):
+    t = torch.tensor(np.asarray(a, np.float32)).to(torch.bfloat16)
+    return t.view(torch.int16).cuda()
+
+
+def _bits_to_f64(torch, t):
+    return t.view(torch.bfloat16).to(torch.float32).cpu().numpy().astype(np.float64)
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30))
+
+
+def test_mlp_forward_and_gradient_match_reference():
+    torch = _torch()
+    rng = np.random.default_rng(0)
+    theta = learned.init_params(3).astype(np.float64) + rng.normal(scale=0.02, size=om.N_PARAMS)
+    theta32 = theta.astype(np.float32)
+    M = 192
+    x = rng.normal(size=(M, 64))
+    t = np.maximum(rng.normal(size=(M, 256)) - 1.0, -4.0)
+    net = dock.Mlp(theta32)
+    xb, tb = _to_bf16_bits(torch, x), _to_bf16_bits(torch, t)
+    y = torch.empty(M, 256, device="cuda")
+    net.forward(xb, y)
+    torch.cuda.synchronize()
+    y_ref, _ = om.forward(theta32.astype(np.float64), _bits_to_f64(torch, xb), bf16=True)
+    print("forward rel err", _rel(y.cpu().numpy(), y_ref))
+    assert _rel(y.cpu().numpy().astype(np.float64), y_ref) < 1e-2
+    g = torch.empty(om.N_PARAMS, device="cuda")
+    loss = net.loss_grad(xb, tb, grad_out=g)
+    l_ref, g_ref = om.loss_and_grad(theta32.astype(np.float64), _bits_to_f64(torch, xb),
+                                    _bits_to_f64(torch, tb), bf16=True)
+    assert abs(loss - l_ref) / l_ref < 1e-3
+    gg = g.cpu().numpy().astype(np.float64)
+    at = 0
+    for (o, i) in om.SIZES:
+        for size in (o * i, o):
+            e = _rel(gg[at:at + size], g_ref[at:at + size])
+            print("grad block", at, size, e)
+            assert e < 1e-2
+            at += size
+
+
+def test_mlp_adam_step_matches_reference():
+    torch = _torch()
+    rng = np.random.default_rng(1)
+    theta = learned.init_params(4)
+    net = dock.Mlp(theta)
+    M = 128
+    xb = _to_bf16_bits(torch, rng.normal(size=(M, 64)))
+    tb = _to_bf16_bits(torch, rng.normal(size=(M, 256)))
+    p = theta.astype(np.float64)
+    m = np.zeros_like(p)
+    v = np.zeros_like(p)
+    g = torch.empty(om.N_PARAMS, device="cuda")
+    for step in range(1, 4):
+        net.loss_grad(xb, tb, grad_out=g, want_loss=False)
+        net.adam(lr=1e-3)
+        gd = g.cpu().numpy().astype(np.float64)
+        p, m, v = om.adam_step(p, m, v, gd, step)
+    got = net.get_params().astype(np.float64)
+    assert np.abs(got - p).max() < 1e-5
+
+
+def test_emitted_profiles_match_reference():
+    torch = _torch()
+    pocket = synth.pocket(learned.LEARN_CONFIG)
+    h = dock.dock_init_pocket(pocket.grid, pocket.origin, pocket.spacing)
+    ligs = synth.ligands(learned.LIGAND_RECIPE, count=6, seed=4, stream=synth.STREAM_TRAIN)
+    orient = synth.orientations(learned.LEARN_CONFIG, 8)
+    rows = int(ligs.rot_offset[-1]) * 8
+    x = torch.empty(rows, 64, dtype=torch.int16, device="cuda")
+    t = torch.empty(rows, 256, dtype=torch.int16, device="cuda")
+    mk = torch.empty(rows, 8, dtype=torch.int32, device="cuda")
+    dock.dock_emit_profiles(h, ligs, orient, x, t, mk)
+    res = dock.dock_batch(h, ligs, orient, 256, want_all=True)
+    xs, ts = _bits_to_f64(torch, x), _bits_to_f64(torch, t)
+    mask = mk.cpu().numpy().view(np.uint32)
+    n_feat = n_feat_ok = n_t = n_t_ok = n_v = n_v_ok = 0
+    for l in range(ligs.n_ligands):
+        lig = ligs.ligand(l)
+        R = len(lig["rot_axis"])
+        for o in range(8):
+            k = item_steps(ligs, l, o, 8, 1, res["all_angle_idx"])
+            tr = oracle.trace_item(pocket, lig, orient[o], 256, forced_k=k)
+            # poses before each step along the same trajectory
+            X = lig["xyz"].astype(np.float64) @ orient[o][:9].reshape(3, 3).astype(np.float64).T
+            for r in range(R):
+                row = (int(ligs.rot_offset[l]) * 8 + o * R) + r
+                f_ref = ref_features(pocket, X, lig, r)
+                n_feat += 64
+                n_feat_ok += int(np.sum(np.abs(xs[row] - f_ref) <= 2 ** -7 * np.maximum(np.abs(f_ref), 1e-3) + 1e-6))
+                t_ref = ref_landscape(tr.prof_s[r])
+                n_t += 256
+                n_t_ok += int(np.sum(np.abs(ts[row] - t_ref) <= 2 ** -7 * np.abs(t_ref) + 2e-5 * (1 + abs(tr.prof_s[r].max()))))
+                bits = np.array([(mask[row, kk // 32] >> (kk % 32)) & 1 for kk in range(256)], bool)
+                ok_v = (tr.prof_flags[r] & oracle.FLAG_VALID) > 0
+                amb = (tr.prof_flags[r] & oracle.FLAG_VAMB) > 0
+                n_v += 256
+                n_v_ok += int(np.sum((bits == ok_v) | amb))
+                kk = int(k[r])
+                if kk > 0:
+                    from tests.helpers import step_pose
+                    X = step_pose(X, lig, r, kk, 256)
+    print("features", n_feat_ok, "/", n_feat, "targets", n_t_ok, "/", n_t, "validity", n_v_ok, "/", n_v)
+    assert n_v_ok == n_v
+    assert n_feat_ok >= 0.995 * n_feat
+    assert n_t_ok >= 0.99 * n_t
+    h.close()
+
+
+def _proposal_pocket(seed=5):
+    pocket = synth.pocket(learned.LEARN_CONFIG)
+    h = dock.dock_init_pocket(pocket.grid, pocket.origin, pocket.spacing)
+    net = dock.Mlp(learned.init_params(seed))
+    dock.dock_load_proposal(h, net)
+    return pocket, h, net
+
+
+def test_learned_mode_with_fallback_everywhere_is_the_plain_sweep():
+    _torch()
+    pocket, h, net = _proposal_pocket()
+    ligs = synth.ligands(learned.LIGAND_RECIPE, count=30, seed=4, stream=synth.STREAM_EVAL)
+    orient = synth.orientations(learned.LEARN_CONFIG)
+    plain = dock.dock_batch(h, ligs, orient, 256, want_all=True)
+    lrn = dock.dock_batch(h, ligs, orient, 256, mode=dock.DOCK_MODE_LEARNED, top_k=16,
+                          margin=3.0e38, want_all=True)
+    for k in ("best_score", "best_orient", "angle_idx", "xyz", "all_scores", "all_angle_idx"):
+        assert np.array_equal(plain[k], lrn[k]), k
+    # steps with at most top_k valid angles nominate all of them (exact without
+    # falling back); every other step falls back
+    assert (lrn["n_fallback"] <= 8 * np.diff(ligs.rot_offset)).all()
+    assert lrn["n_fallback"].sum() > 0
+    h.close()
+
+
+def test_learned_choices_are_valid_and_replayable():
+    _torch()
+    pocket, h, net = _proposal_pocket()
+    ligs = synth.ligands(learned.LIGAND_RECIPE, count=12, seed=4, stream=synth.STREAM_EVAL)
+    orient = synth.orientations(learned.LEARN_CONFIG)
+    res = dock.dock_batch(h, ligs, orient, 256, mode=dock.DOCK_MODE_LEARNED, top_k=16,
+                          margin=-1.0, want_all=True)
+    assert (res["n_fallback"] == 0).all()
+    bad = []
+    for l in range(ligs.n_ligands):
+        lig = ligs.ligand(l)
+        for o in range(8):
+            k = item_steps(ligs, l, o, 8, 1, res["all_angle_idx"])
+            tr = oracle.trace_item(pocket, lig, orient[o], 256, forced_k=k)
+            for s, kk in enumerate(k):
+                f = tr.prof_flags[s][int(kk)] if kk >= 0 else 0
+                if kk < 0 or not (f & (oracle.FLAG_VALID | oracle.FLAG_VAMB)):
+                    bad.append((l, o, s, int(kk)))
+            sc = float(res["all_scores"][l, o])
+            assert abs(sc - tr.score) <= tol_of(tr.score) or tr.score_lo - 1e-3 <= sc <= tr.score_hi + 1e-3
+        ob = int(res["best_orient"][l])
+        a0, a1 = ligs.atom_offset[l], ligs.atom_offset[l + 1]
+        k = item_steps(ligs, l, ob, 8, 1, res["all_angle_idx"])
+        tr = oracle.trace_item(pocket, lig, orient[ob], 256, forced_k=k)
+        assert np.abs(res["xyz"][a0:a1] - tr.xyz).max() < 1e-4
+    assert not bad, bad[:10]
+    h.close()
+
+
+def test_training_reduces_loss():
+    torch = _torch()
+    net, hist = learned.train(n_ligands=3000, epochs=3, batch=1024, log=print)
+    print(hist)
+    assert hist["val_loss"][-1] < hist["val_loss"][0] or hist["val_loss"][-1] < 0.9 * hist["train_loss"][0]
+    assert np.isfinite(hist["val_loss"]).all()
