@@ -89,6 +89,112 @@ def cpu_baseline(pocket, ligs, orient, S, budget_s=15.0):
                       f"FP64, {threads} threads, {t_used:.1f} s"}
 
 
+def device_batch(ligs, orient, want_all=False):
+    """CSR batch, orientations and result buffers as device tensors."""
+    import torch
+    from paper_1901_06229_amd import dock
+    dev = torch.device("cuda:0")
+    d = dict(n_ligands=ligs.n_ligands, total_atoms=int(ligs.atom_offset[-1]),
+             total_rot=int(ligs.rot_offset[-1]), total_move=int(ligs.move_offset[-1]))
+    for k, dt in (("atom_offset", torch.int32), ("xyz", torch.float32), ("rot_offset", torch.int32),
+                  ("rot_axis", torch.int32), ("move_offset", torch.int32), ("move_atoms", torch.int16)):
+        d[k] = torch.from_numpy(np.ascontiguousarray(getattr(ligs, k))).to(dev, dt)
+    L, NA, NR = ligs.n_ligands, d["total_atoms"], d["total_rot"]
+    out = dict(best_score=torch.empty(L, device=dev),
+               best_orient=torch.empty(L, dtype=torch.int32, device=dev),
+               angle_idx=torch.empty(max(NR, 1), dtype=torch.int16, device=dev),
+               xyz=torch.empty(max(NA, 1), 3, device=dev),
+               status=torch.empty(L, dtype=torch.int32, device=dev),
+               n_fallback=torch.empty(L, dtype=torch.int32, device=dev))
+    return d, torch.from_numpy(np.ascontiguousarray(orient)).to(dev), out
+
+
+def time_steps(h, d, od, S, out, prm, ws, stream, steps, warmup):
+    """Wall time per dock_batch_async step (inputs resident), synchronised."""
+    import torch
+    from paper_1901_06229_amd import dock
+    for _ in range(warmup):
+        dock.dock_batch_async(h, d, od, S, out, prm, workspace=ws, stream=stream)
+    stream.synchronize()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        dock.dock_batch_async(h, d, od, S, out, prm, workspace=ws, stream=stream)
+    stream.synchronize()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def learned_comparison(n_eval=10_000, n_val=2_000, n_train=156_250, epochs=10, top_k=16,
+                       steps=5, proposal=None):
+    """Plain vs learned proposal on the learned-proposal workload (64^3 pocket,
+    32-atom 4-rotamer ligands, 8 orientations, 256 steps), same inputs."""
+    import torch
+    from paper_1901_06229_amd import dock, learned, synth
+    t0 = time.perf_counter()
+    if proposal:
+        net = dock.Mlp(learned.load_params(proposal))
+        hist = {"loaded": proposal}
+    else:
+        net, hist = learned.train(n_ligands=n_train, epochs=epochs, log=log)
+    t_train = time.perf_counter() - t0
+    pocket = synth.pocket(learned.LEARN_CONFIG)
+    h = dock.dock_init_pocket(pocket.grid, pocket.origin, pocket.spacing)
+    dock.dock_load_proposal(h, net)
+    orient = synth.orientations(learned.LEARN_CONFIG)
+    stream = torch.cuda.Stream()
+    res = {}
+    for name, first, count in (("val", n_eval, n_val), ("eval", 0, n_eval)):
+        ligs = synth.ligands(learned.LIGAND_RECIPE, count=count, first=first,
+                             seed=synth.config_seed(learned.LEARN_CONFIG), stream=synth.STREAM_EVAL)
+        d, od, out = device_batch(ligs, orient)
+        ws = torch.empty(dock.dock_workspace_size(count, d["total_rot"], 8, 256), dtype=torch.uint8,
+                         device="cuda")
+        res[name] = (ligs, d, od, out, ws)
+
+    def run(name, mode, margin, n_steps):
+        ligs, d, od, out, ws = res[name]
+        prm = dock.make_params(mode=mode, top_k=top_k, margin=margin, max_atoms=32, max_rot=4)
+        sec = time_steps(h, d, od, 256, out, prm, ws, stream, n_steps, 1)
+        return sec, out["best_score"].cpu().numpy().copy(), int(out["n_fallback"].sum().item())
+
+    def loss(sp, sl):
+        return float(np.mean((sp - sl) / np.maximum(np.abs(sp), 1.0)))
+
+    # threshold on the validation ligands: fastest margin with <= 0.5 % mean loss
+    _, sp_val, _ = run("val", dock.DOCK_MODE_PLAIN, 0.0, 1)
+    candidates = []
+    for tau in (-1.0, 0.02, 0.05, 0.1, 0.2, 0.4, 0.8, 3.0e38):
+        sec, sl, nfb = run("val", dock.DOCK_MODE_LEARNED, tau, 2)
+        candidates.append((tau, sec, loss(sp_val, sl), nfb / (n_val * 8 * 4)))
+        log(f"val tau {tau:g}: {sec * 1e3:.3f} ms, loss {candidates[-1][2]:.5f}, "
+            f"fallback {candidates[-1][3]:.3f}")
+    ok = [c for c in candidates if c[2] <= 0.005]
+    tau = min(ok, key=lambda c: c[1])[0] if ok else 3.0e38
+    sec_p, sp, _ = run("eval", dock.DOCK_MODE_PLAIN, 0.0, steps)
+    sec_l, sl, nfb = run("eval", dock.DOCK_MODE_LEARNED, tau, steps)
+    net0 = dock.Mlp(learned.init_params(12345))
+    dock.dock_load_proposal(h, net0)
+    _, sl0, _ = run("eval", dock.DOCK_MODE_LEARNED, -1.0, 1)
+    dock.dock_load_proposal(h, net)
+    _, sl_t, _ = run("eval", dock.DOCK_MODE_LEARNED, -1.0, 1)
+    h.close()
+    return {
+        "workload": "learned proposal: 64^3 pocket @0.5A, 10000 held-out ligands (32 atoms, "
+                    "4 rotamers), 8 orientations, 256 steps",
+        "plain_ligands_per_s": round(n_eval / sec_p, 1),
+        "learned_ligands_per_s": round(n_eval / sec_l, 1),
+        "speedup": round(sec_p / sec_l, 3),
+        "top_k": top_k, "margin_tau": tau if tau < 1e30 else "inf (full fallback)",
+        "score_loss_mean": loss(sp, sl), "fallback_rate": nfb / (n_eval * 8 * 4),
+        "no_fallback_loss_trained": loss(sp, sl_t), "no_fallback_loss_untrained": loss(sp, sl0),
+        "validation": [{"tau": c[0] if c[0] < 1e30 else "inf", "ms": round(c[1] * 1e3, 3),
+                        "loss": round(c[2], 5), "fallback": round(c[3], 3)} for c in candidates],
+        "training": {k: v for k, v in hist.items() if k not in ("train_loss", "val_loss")}
+        | {"final_val_mse": hist.get("val_loss", [None])[-1], "seconds": round(t_train, 2)},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -100,6 +206,8 @@ def main():
     ap.add_argument("--bump", choices=("pruned", "direct"), default="pruned",
                     help="pruned: test only pairs that can clash; direct: every pair")
     ap.add_argument("--waves", type=int, default=4, help="waves per block of the sweep")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-proposal comparison")
+    ap.add_argument("--proposal", default=None, help="directory of trained proposal weights")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -182,6 +290,9 @@ def main():
                      "dense lane-ops per angle: 8 per cross pair + 45 per moving atom",
                      "pair_angle_tests": pair_tests[-1]},
     }
+    if not args.no_learned:
+        log("learned proposal: training on the GPU and comparing with the plain sweep")
+        line["learned"] = learned_comparison(proposal=args.proposal)
     if not args.no_cpu_baseline:
         log("timing the FP64 reference on a sample")
         line["cpu_baseline"] = cpu_baseline(pocket, ligs, orient, S)

@@ -334,8 +334,7 @@ int enqueue_batch(dock_pocket *p, const dock_ligands *ligs, const float *orient,
     const int steps = (prm->max_rot > 0 ? prm->max_rot : DOCK_MAX_ROT) * prm->passes;
     const int rows = (int)((L * O + 63) / 64 * 64);
     for (int s = 0; s < steps; ++s) {
-      e = mlp_forward(p->lw_feat, rows, p->prop_wb, p->prop_w, p->lw_z[0], p->lw_a[0], p->lw_z[1],
-                      p->lw_a[1], p->lw_z[2], p->lw_a[2], p->lw_z[3], st);
+      e = mlp_infer(p->lw_feat, rows, p->prop_wb, p->prop_w, p->lw_z[3], st);
       if (e == hipSuccess) e = enqueue_learned_step(LA, s, p->n_cu, st);
       if (e != hipSuccess) return hip_fail(e, "learned step");
     }

@@ -67,18 +67,10 @@ __device__ __forceinline__ void write_step_inputs(const LearnedArgs &A, const Wa
                                                   const RotState &RS, int item, int lane) {
   const GridView G = A.sw.grid;
   A.feat[(size_t)item * 64 + lane] = f32_to_bf16(rotamer_feature(W, RS, G, lane));
-  float cc[4], ss[4];
-  uint32_t bump = 0;
+  rotamer_bump_mask(W, RS, A.sw.r2, A.sw.r2 + kPruneMargin, 256, lane);
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
-    const float2 cs = A.sw.cs[t * kWave + lane];
-    cc[t] = cs.x;
-    ss[t] = cs.y;
-  }
-  rotamer_bumps<4>(W, RS, A.sw.r2, A.sw.r2 + kPruneMargin, cc, ss, bump, lane);
-#pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    const uint64_t vm = __ballot(!((bump >> t) & 1u));
+    const uint64_t vm = __ballot(!step_bumps(W, t * kWave + lane));
     if (lane == 0) A.valid[(size_t)item * 4 + t] = vm;
   }
 }
@@ -170,21 +162,11 @@ __global__ void __launch_bounds__(kWave) learned_step_kernel(LearnedArgs A, int 
     const bool fallback = any_valid && margin < A.margin;
     uint64_t best = 0ull;
     if (fallback) {  // the plain step over every valid angle
-      float cc[4], ss[4], score[4];
+      uint32_t bump = 0;
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const float2 cs = A.sw.cs[t * kWave + lane];
-        cc[t] = cs.x;
-        ss[t] = cs.y;
-      }
-      rotamer_scores<4>(W, RS, G, GS, grsrc, cc, ss, score, lane);
-      if (lane == 0) score[0] = s0;
-#pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const int k = t * kWave + lane;
-        const uint64_t kk = (vm[t] >> lane) & 1ull ? best_key(score[t], (uint32_t)k) : 0ull;
-        best = kk > best ? kk : best;
-      }
+      for (int t = 0; t < 4; ++t)
+        if (!((vm[t] >> lane) & 1ull)) bump |= 1u << t;
+      best = best_valid_step<4>(W, RS, G, GS, grsrc, A.sw.cs, bump, 0, s0, lane);
       if (lane == 0) atomicAdd(A.n_fallback + I.l, 1);
     } else if (any_valid) {  // nominated bins plus the current pose
       const bool zero_valid = vm[0] & 1ull;

@@ -135,6 +135,86 @@ hipError_t gemm_bf16(const GemmArgs &g, bool ta, bool tb, int epi, int M, int N,
   return hipErrorInvalidValue;
 }
 
+// ---------------------------------------------------------------- fused inference
+// Forward pass of 64 rows per block through all four layers.  Activations
+// stay in LDS (BF16, 64 x 256); each wave owns 64 output columns (2 x 2
+// tiles of 32 x 32) and reads its weight rows straight from global memory
+// (L2-resident, stored [out][in] so the 8 k-values of an MFMA operand are
+// contiguous).  Arithmetic and rounding points are those of the tiled path:
+// FP32 accumulation, bias, GELU, BF16 activations; FP32 output.
+constexpr int kInfRows = 64;
+constexpr int kActPad = 8;
+
+__global__ void __launch_bounds__(256) mlp_infer_kernel(const uint16_t *x, const uint16_t *wb,
+                                                        const float *bias_src, float *y) {
+  __shared__ __attribute__((aligned(16))) uint16_t sH[kInfRows][256 + kActPad];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const size_t row0 = (size_t)blockIdx.x * kInfRows;
+  // input rows: 64 x 64 BF16
+  for (int e = tid; e < kInfRows * 8; e += 256) {
+    const int r = e >> 3, c = (e & 7) * 8;
+    *(uint4 *)&sH[r][c] = *(const uint4 *)(x + (row0 + r) * 64 + c);
+  }
+  __syncthreads();
+  const int kin[4] = {64, 256, 256, 256};
+  const int64_t woff[4] = {kMlpW1, kMlpW2, kMlpW3, kMlpW4};
+  const int64_t boff[4] = {kMlpB1, kMlpB2, kMlpB3, kMlpB4};
+  const int col0 = wv * 64;
+#pragma unroll 1
+  for (int l = 0; l < 4; ++l) {
+    f32x16 acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int j = 0; j < 16; ++j) acc[a][b][j] = 0.0f;
+    const uint16_t *W = wb + woff[l];
+    const int K = kin[l];
+#pragma unroll 2
+    for (int k0 = 0; k0 < K; k0 += 16) {
+      const int kk = k0 + (lane >> 5) * 8;
+      bf16x8 bo[2], ao[2];
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+        bo[b] = *(const bf16x8 *)(W + (size_t)(col0 + b * 32 + (lane & 31)) * K + kk);
+#pragma unroll
+      for (int a = 0; a < 2; ++a) ao[a] = *(const bf16x8 *)&sH[a * 32 + (lane & 31)][kk];
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+          acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ao[a], bo[b], acc[a][b], 0, 0, 0);
+    }
+    __syncthreads();  // every wave is done reading this layer's input
+    const float *bias = bias_src + boff[l];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        const int col = col0 + b * 32 + (lane & 31);
+        const float bc = bias[col];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+          const int row = a * 32 + (j >> 2) * 8 + (lane >> 5) * 4 + (j & 3);
+          const float v = acc[a][b][j] + bc;
+          if (l < 3)
+            sH[row][col] = f2bf(gelu_f(v));
+          else
+            y[(row0 + row) * 256 + col] = v;
+        }
+      }
+    __syncthreads();
+  }
+}
+
+hipError_t mlp_infer(const uint16_t *x, int M, const uint16_t *wb, const float *bias_src, float *y,
+                     hipStream_t st) {
+  if (M % kInfRows) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(mlp_infer_kernel, dim3(M / kInfRows), dim3(256), 0, st, x, wb, bias_src, y);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- small kernels
 __global__ void f32_to_bf16_kernel(const float *x, uint16_t *y, int64_t n) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;

@@ -199,10 +199,7 @@ int dock_mlp_forward(dock_mlp *n, const uint16_t *x_bf16, int M, float *y, void 
   int rc = ensure_rows(n, M);
   if (rc) return rc;
   hipStream_t st = (hipStream_t)stream;
-  hipError_t e = mlp_forward(x_bf16, M, n->wb, n->w, n->z1, n->a1, n->z2, n->a2, n->z3, n->a3,
-                             n->y, st);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(y, n->y, sizeof(float) * (size_t)M * 256, hipMemcpyDeviceToDevice, st);
+  hipError_t e = mlp_infer(x_bf16, M, n->wb, n->w, y, st);
   return e == hipSuccess ? DOCK_OK : abi_fail(DOCK_E_DEVICE, "mlp forward: %s", hipGetErrorString(e));
 }
 

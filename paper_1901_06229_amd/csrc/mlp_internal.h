@@ -40,6 +40,11 @@ hipError_t launch_adam(float *w, float *m, float *v, const float *g, uint16_t *w
                        float lr, float b1, float b2, float eps, float c1, float c2,
                        hipStream_t st);
 
+// Fused forward pass (all layers in one kernel, activations in LDS) of M
+// rows, M a multiple of 64; y = [M][256] FP32.
+hipError_t mlp_infer(const uint16_t *x, int M, const uint16_t *wb, const float *bias_src, float *y,
+                     hipStream_t st);
+
 // Forward pass of M rows (M a multiple of 64) with BF16 weights wb and FP32
 // biases taken from the packed layout; z1..z3 / a1..a3 / y are caller
 // buffers of M x 256.

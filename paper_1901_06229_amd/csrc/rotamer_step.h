@@ -33,9 +33,12 @@ __host__ __device__ inline int wave_head_bytes(int nmax) {
   return (b + 15) / 16 * 16;
 }
 
+constexpr int kMaskWords = 128;  // invalid-angle bitmask of up to 4096 steps
+
 __host__ __device__ inline int wave_lds_bytes(int nmax) {
-  // then the pair list: coefficients (float4) and packed atom pairs (int32)
-  return wave_head_bytes(nmax) + kPairCap * (16 + 4);
+  // then the pair list -- coefficients (float4) and packed atom pairs (int32),
+  // reused afterwards for the compacted valid angles -- and the bitmask
+  return wave_head_bytes(nmax) + kPairCap * (16 + 4) + kMaskWords * 4;
 }
 
 struct WaveLds {
@@ -47,6 +50,8 @@ struct WaveLds {
   uint8_t *mov;  // moving flags
   float4 *P;     // kept pairs: 2A, 2B, D' - r_bump^2
   int *PI;       // kept pairs: i << 16 | j
+  int16_t *CK;   // compacted valid angle steps (aliases P, used after the bump test)
+  uint32_t *BM;  // bit k set: angle step k bumps
   __device__ WaveLds(char *base, int nmax) {
     X = (float4 *)base;
     C = X + nmax;
@@ -56,6 +61,8 @@ struct WaveLds {
     mov = (uint8_t *)(M + nmax);
     P = (float4 *)(base + wave_head_bytes(nmax));
     PI = (int *)(P + kPairCap);
+    CK = (int16_t *)P;
+    BM = (uint32_t *)(PI + kPairCap);
   }
 };
 
@@ -117,11 +124,29 @@ __device__ __forceinline__ float rotamer_s0(const WaveLds &W, const RotState &R)
   return s;
 }
 
-template <int TG>
-__device__ __forceinline__ void test_kept_pairs(const WaveLds &W, const RotState &R, float r2,
-                                                int cnt, const float (&cc)[TG],
-                                                const float (&ss)[TG], uint32_t &bump,
-                                                int lane) {
+// Mark the angle steps k in [lo, lo + len) (indices mod S) in the bitmask.
+__device__ __forceinline__ void mark_steps(uint32_t *BM, int lo, int len, int S) {
+  while (len > 0) {
+    const int b = lo & 31;
+    int cnt = 32 - b;
+    cnt = cnt < len ? cnt : len;
+    cnt = cnt < S - lo ? cnt : S - lo;
+    const uint32_t bits = (cnt == 32 ? 0xFFFFFFFFu : ((1u << cnt) - 1u)) << b;
+    atomicOr(&BM[lo >> 5], bits);
+    len -= cnt;
+    lo += cnt;
+    if (lo >= S) lo = 0;
+  }
+}
+
+// Clash arcs of the kept pairs PI[0, cnt).  A pair bumps at angle theta iff
+// cos(theta) 2A + sin(theta) 2B > D' - r^2, i.e. cos(theta - beta) > c with
+// R = |(2A, 2B)|, beta = atan2(2B, 2A), c = (D' - r^2) / R: an open arc of
+// half-width acos(c) around beta.  Each lane takes one pair and marks the
+// angle steps inside its arc.
+__device__ __forceinline__ void mark_kept_pairs(const WaveLds &W, const RotState &R, float r2,
+                                                int cnt, int S, int lane) {
+  const float steps_per_rad = (float)S * 0.15915494309189535f;  // S / (2 pi)
   for (int e = lane; e < cnt; e += kWave) {
     const int ij = W.PI[e];
     const float4 ci = W.C[ij >> 16], cj = W.C[ij & 0xFFFF];
@@ -133,27 +158,38 @@ __device__ __forceinline__ void test_kept_pairs(const WaveLds &W, const RotState
     const float b_ = fmaf(R.u.x, cx, fmaf(R.u.y, cy, R.u.z * cz));
     const float rho2i = fmaf(ci.x, ci.x, fmaf(ci.y, ci.y, ci.z * ci.z));
     const float rho2j = fmaf(cj.x, cj.x, fmaf(cj.y, cj.y, cj.z * cj.z));
-    W.P[e] = make_float4(2.0f * a_, 2.0f * b_, fmaf(dz, dz, rho2i + rho2j) - r2, 0.0f);
+    const float A2 = 2.0f * a_, B2 = 2.0f * b_;
+    const float D = fmaf(dz, dz, rho2i + rho2j) - r2;
+    const float Rr = sqrtf(fmaf(A2, A2, B2 * B2));
+    if (!(Rr > D)) continue;  // never closer than r_bump
+    if (-Rr > D) {            // closer than r_bump at every angle
+      mark_steps(W.BM, 0, S, S);
+      continue;
+    }
+    const float half = acosf(fminf(fmaxf(D / Rr, -1.0f), 1.0f));
+    const float beta = atan2f(B2, A2);
+    const int klo = (int)floorf((beta - half) * steps_per_rad) + 1;
+    const int khi = (int)ceilf((beta + half) * steps_per_rad) - 1;
+    const int len = khi - klo + 1;
+    if (len <= 0) continue;
+    if (len >= S) {
+      mark_steps(W.BM, 0, S, S);
+      continue;
+    }
+    int lo = klo % S;
+    if (lo < 0) lo += S;
+    mark_steps(W.BM, lo, len, S);
   }
-  wave_lds_sync();
-  for (int e = 0; e < cnt; ++e) {
-    const float4 pr = W.P[e];
-#pragma unroll
-    for (int t = 0; t < TG; ++t)
-      if (fmaf(cc[t], pr.x, ss[t] * pr.y) > pr.z) bump |= 1u << t;
-  }
-  wave_lds_sync();
 }
 
-// Bump test of the lane's TG angle slots.  Lanes sweep the flattened cross
-// pairs (i in M, j in Q), keep those whose lower bound does not clear r_bump
-// and compact them into the LDS list, which every lane then tests.  Returns
+// Invalid angle steps of the rotamer, for all S steps, into W.BM.  Lanes
+// sweep the flattened cross pairs (i in M, j in Q), keep those whose lower
+// bound does not clear r_bump, and mark each kept pair's clash arc.  Returns
 // the number of kept pairs.
-template <int TG>
-__device__ __forceinline__ int rotamer_bumps(const WaveLds &W, const RotState &R, float r2,
-                                             float thr, const float (&cc)[TG],
-                                             const float (&ss)[TG], uint32_t &bump, int lane) {
+__device__ __forceinline__ int rotamer_bump_mask(const WaveLds &W, const RotState &R, float r2,
+                                                 float thr, int S, int lane) {
   const uint64_t below = lanes_below_mask(lane);
+  for (int w = lane; w < (S + 31) / 32; w += kWave) W.BM[w] = 0u;
   const int total = R.m * R.q;
   const float inv_q = R.q > 0 ? 1.0f / (float)R.q : 0.0f;
   int np = 0, kept = 0;
@@ -183,14 +219,21 @@ __device__ __forceinline__ int rotamer_bumps(const WaveLds &W, const RotState &R
     np += __popcll(mask);
     if (np > kPairCap - kWave) {
       wave_lds_sync();
-      test_kept_pairs<TG>(W, R, r2, np, cc, ss, bump, lane);
+      mark_kept_pairs(W, R, r2, np, S, lane);
       kept += np;
       np = 0;
+      wave_lds_sync();
     }
   }
   wave_lds_sync();
-  test_kept_pairs<TG>(W, R, r2, np, cc, ss, bump, lane);
+  mark_kept_pairs(W, R, r2, np, S, lane);
+  wave_lds_sync();
   return kept + np;
+}
+
+// Bump bit of angle step k (k < S) from the mask.
+__device__ __forceinline__ bool step_bumps(const WaveLds &W, int k) {
+  return (W.BM[k >> 5] >> (k & 31)) & 1u;
 }
 
 // Scores of the lane's TG angle slots: static score plus the voxel values
@@ -240,6 +283,79 @@ __device__ __forceinline__ void rotamer_scores(const WaveLds &W, const RotState 
       for (int t = 0; t < TG; ++t) score[t] += val[t];
     }
   }
+}
+
+// Best (score, -k) key over the valid steps compacted in W.CK[0, nvalid),
+// TC tiles of 64 lanes; angle step 0, if valid, is compacted first and takes
+// the exact score s0 of the current pose.
+template <int TC>
+__device__ __forceinline__ uint64_t score_compacted(const WaveLds &W, const RotState &R,
+                                                    const GridView &G, const GridScaled &GS,
+                                                    __amdgpu_buffer_rsrc_t grsrc,
+                                                    const float2 *cs_table, int nvalid,
+                                                    float s0, int lane) {
+  float cc[TC], ss[TC], score[TC];
+  int kk[TC];
+#pragma unroll
+  for (int t = 0; t < TC; ++t) {
+    const int j = t * kWave + lane;
+    kk[t] = j < nvalid ? W.CK[j] : -1;
+    const float2 cs = cs_table[kk[t] > 0 ? kk[t] : 0];
+    cc[t] = cs.x;
+    ss[t] = cs.y;
+  }
+  rotamer_scores<TC>(W, R, G, GS, grsrc, cc, ss, score, lane);
+  uint64_t best = 0ull;
+#pragma unroll
+  for (int t = 0; t < TC; ++t) {
+    if (kk[t] == 0) score[t] = s0;
+    const uint64_t key = kk[t] >= 0 ? best_key(score[t], (uint32_t)kk[t]) : 0ull;
+    best = key > best ? key : best;
+  }
+  return best;
+}
+
+// Scores only the valid steps among the lane's TG slots (tile t holds step
+// (t0 + t) * 64 + lane): they are compacted into as few 64-lane tiles as
+// possible first.  Returns the lane's best key (wave reduction is the
+// caller's).
+template <int TG>
+__device__ __forceinline__ uint64_t best_valid_step(const WaveLds &W, const RotState &R,
+                                                    const GridView &G, const GridScaled &GS,
+                                                    __amdgpu_buffer_rsrc_t grsrc,
+                                                    const float2 *cs_table, uint32_t bump, int t0,
+                                                    float s0, int lane) {
+  const uint64_t below = lanes_below_mask(lane);
+  int nvalid = 0;
+#pragma unroll
+  for (int t = 0; t < TG; ++t) {
+    const bool v = !((bump >> t) & 1u);
+    const uint64_t m = __ballot(v);
+    if (v) W.CK[nvalid + __popcll(m & below)] = (int16_t)((t0 + t) * kWave + lane);
+    nvalid += __popcll(m);
+  }
+  wave_lds_sync();
+  uint64_t best = 0ull;
+  if (nvalid > 0) {
+    const int tc = (nvalid + kWave - 1) / kWave;
+    if (tc == 1) best = score_compacted<1>(W, R, G, GS, grsrc, cs_table, nvalid, s0, lane);
+    if constexpr (TG >= 2)
+      if (tc == 2) best = score_compacted<2>(W, R, G, GS, grsrc, cs_table, nvalid, s0, lane);
+    if constexpr (TG >= 3)
+      if (tc == 3) best = score_compacted<3>(W, R, G, GS, grsrc, cs_table, nvalid, s0, lane);
+    if constexpr (TG >= 4)
+      if (tc == 4) best = score_compacted<4>(W, R, G, GS, grsrc, cs_table, nvalid, s0, lane);
+    if constexpr (TG >= 5)
+      if (tc == 5) best = score_compacted<5>(W, R, G, GS, grsrc, cs_table, nvalid, s0, lane);
+    if constexpr (TG >= 6)
+      if (tc == 6) best = score_compacted<6>(W, R, G, GS, grsrc, cs_table, nvalid, s0, lane);
+    if constexpr (TG >= 7)
+      if (tc == 7) best = score_compacted<7>(W, R, G, GS, grsrc, cs_table, nvalid, s0, lane);
+    if constexpr (TG >= 8)
+      if (tc == 8) best = score_compacted<8>(W, R, G, GS, grsrc, cs_table, nvalid, s0, lane);
+  }
+  wave_lds_sync();
+  return best;
 }
 
 // Rotate the moving atoms of the pose in LDS by the angle (c, s).

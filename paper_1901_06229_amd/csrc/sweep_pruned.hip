@@ -79,26 +79,33 @@ __global__ void __launch_bounds__(WAVES *kWave)
         const float s0 = rotamer_s0(W, RS);
         if (emit) A.emit_x[(kbase + step) * 64 + lane] = f32_to_bf16(rotamer_feature(W, RS, G, lane));
 
+        // invalid steps of the rotamer, for all S steps at once
+        pair_tests += (uint64_t)rotamer_bump_mask(W, RS, r2, thr, S, lane);
+
         uint64_t best = 0ull;
         for (int t0 = 0; t0 < T; t0 += TG) {
-          float cc[TG], ss[TG], score[TG];
           uint32_t bump = 0;
 #pragma unroll
           for (int t = 0; t < TG; ++t) {
             const int k = (t0 + t) * kWave + lane;
-            const bool act = (t0 + t < T) && k < S;
-            const float2 cs = A.cs[act ? k : 0];
+            if (t0 + t >= T || k >= S || step_bumps(W, k)) bump |= 1u << t;
+          }
+          if (!emit) {
+            const uint64_t key =
+                best_valid_step<TG>(W, RS, G, GS, grsrc, A.cs, bump, t0, s0, lane);
+            best = key > best ? key : best;
+            continue;
+          }
+          // profile emission scores every step, valid or not
+          float cc[TG], ss[TG], score[TG];
+#pragma unroll
+          for (int t = 0; t < TG; ++t) {
+            const int k = (t0 + t) * kWave + lane;
+            const float2 cs = A.cs[(t0 + t < T && k < S) ? k : 0];
             cc[t] = cs.x;
             ss[t] = cs.y;
-            score[t] = RS.cst;
-            if (!act) bump |= 1u << t;
           }
-          const int S_grp = min(S, (t0 + TG) * kWave) - t0 * kWave;
-          pair_tests += (uint64_t)rotamer_bumps<TG>(W, RS, r2, thr, cc, ss, bump, lane) *
-                        (uint64_t)S_grp;
-          const uint32_t full = (TG >= 32) ? 0xFFFFFFFFu : ((1u << TG) - 1u);
-          if (emit || __ballot(bump != full) != 0ull)
-            rotamer_scores<TG>(W, RS, G, GS, grsrc, cc, ss, score, lane);
+          rotamer_scores<TG>(W, RS, G, GS, grsrc, cc, ss, score, lane);
           if (t0 == 0 && lane == 0) score[0] = s0;
 #pragma unroll
           for (int t = 0; t < TG; ++t) {
@@ -106,20 +113,17 @@ __global__ void __launch_bounds__(WAVES *kWave)
             const uint64_t key = (bump >> t) & 1u ? 0ull : best_key(score[t], (uint32_t)k);
             best = key > best ? key : best;
           }
-          if (emit) {  // score landscape over every angle, and the validity mask
-            float smax = score[0];
+          float smax = score[0];
 #pragma unroll
-            for (int t = 1; t < TG; ++t) smax = fmaxf(smax, score[t]);
-            smax = wave_max_f(smax);
-            uint16_t *trow = A.emit_t + (kbase + step) * 256;
+          for (int t = 1; t < TG; ++t) smax = fmaxf(smax, score[t]);
+          smax = wave_max_f(smax);
+          uint16_t *trow = A.emit_t + (kbase + step) * 256;
 #pragma unroll
-            for (int t = 0; t < TG; ++t) {
-              trow[(t0 + t) * kWave + lane] = f32_to_bf16(fmaxf(score[t] - smax, -4.0f));
-              const uint64_t vm = __ballot(!((bump >> t) & 1u));
-              if (lane < 2)
-                A.emit_mask[(kbase + step) * 8 + (t0 + t) * 2 + lane] =
-                    (uint32_t)(vm >> (32 * lane));
-            }
+          for (int t = 0; t < TG; ++t) {
+            trow[(t0 + t) * kWave + lane] = f32_to_bf16(fmaxf(score[t] - smax, -4.0f));
+            const uint64_t vm = __ballot(!((bump >> t) & 1u));
+            if (lane < 2)
+              A.emit_mask[(kbase + step) * 8 + (t0 + t) * 2 + lane] = (uint32_t)(vm >> (32 * lane));
           }
         }
         best = wave_max_u64(best);
