@@ -27,15 +27,25 @@ METRIC = "ligands/sec on 1 MI355X (plain vs learned proposal at ≤0.5% score lo
 
 # MI355X: 256 CUs x 64 lanes x 2.4 GHz, one FP32 VALU lane-operation per lane per clock
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
-# Lane-operation counts (FP32 VALU instructions per lane) of the sweep's units:
+# Lane-operation counts (VALU instructions per lane) of the sweep's units,
+# taken from the loop bodies of the compiled gfx950 kernels:
 #   direct kernel, per angle: 8 per cross pair (3 sub, mul, 2 fma, cmp, or),
 #     23 per Rodrigues rotation, 22 per voxel lookup and add
-#   pruned kernel: 25 per candidate cross pair per rotamer (bound test and the
-#     pair's harmonic coefficients), 4 per executed (pair, angle) test
-#     (fma, mul, cmp, or), 26 per (moving atom, angle) evaluation
-#     (6 fma rotation + 20 voxel index, gather and add)
+#   pruned kernel, per rotamer step:
+#     OPS_CAND per candidate cross pair (m_r q_r of them): cylinder bound
+#       (2 sub, mul, fma, cmp) and the ballot append of a kept pair;
+#     OPS_ARC per kept pair: harmonic coefficients, acos / atan2 of the clash
+#       arc, its step range and the bitmask marking;
+#     OPS_EVAL per (moving atom, non-bumping angle) evaluation: 6 FMA
+#       rotation, 3 clamps, 3 conversions, 2 24-bit multiply-adds, shift and
+#       the score add (the gather itself is a memory instruction).
 OPS_PAIR, OPS_ROT, OPS_VOX = 8, 23, 22
-OPS_CAND, OPS_TEST, OPS_EVAL = 25, 4, 26
+OPS_CAND, OPS_ARC, OPS_EVAL = 17, 133, 16
+
+# Sources of the sweep kernel: the HBM traffic measured by the FETCH_SIZE /
+# WRITE_SIZE counters is reported only while these are unchanged.
+KERNEL_SOURCES = ("sweep_pruned.hip", "rotamer_step.h", "sweep_common.h", "dock_internal.h")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_pruned_c2_traffic.md")
 
 WORKLOADS = {
     1: "C1: 64^3 pocket @0.5A, 1 ligand (32 atoms, 4 rotamers), 8 orientations, 64 steps",
@@ -62,12 +72,61 @@ def batch_counts(ligs):
     return float((m * q).sum()), float(m.sum())
 
 
-def algorithmic_ops(ligs, n_orient, S, bump, pair_tests):
-    """Lane-operations of one whole batch (see the unit costs above)."""
+def dense_ops(ligs, n_orient, S):
+    """Lane-operations of the unpruned sweep: every cross pair and every
+    moving atom at every angle (the direct kernel's work)."""
     mq, msum = batch_counts(ligs)
+    return (OPS_PAIR * mq + (OPS_ROT + OPS_VOX) * msum) * S * n_orient
+
+
+def algorithmic_ops(ligs, n_orient, S, bump, kept_pairs, evals):
+    """Lane-operations of one whole batch (see the unit costs above); the
+    pruned kernel's kept pairs and evaluations are its own counts."""
     if bump == "direct":
-        return (OPS_PAIR * mq + (OPS_ROT + OPS_VOX) * msum) * S * n_orient
-    return (OPS_CAND * mq + OPS_EVAL * msum * S) * n_orient + OPS_TEST * pair_tests
+        return dense_ops(ligs, n_orient, S)
+    mq, _ = batch_counts(ligs)
+    return OPS_CAND * mq * n_orient + OPS_ARC * kept_pairs + OPS_EVAL * evals
+
+
+def kernel_sources_digest() -> str:
+    """SHA-256 of the sweep kernel's code: the sources with comments removed
+    and whitespace collapsed, so editing a comment keeps the digest."""
+    import hashlib
+    import re
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1901_06229_amd", "csrc", name)) as f:
+            code = f.read()
+        code = re.sub(r"/\*.*?\*/", " ", code, flags=re.S)
+        code = re.sub(r"//[^\n]*", " ", code)
+        h.update(" ".join(code.split()).encode())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per sweep launch from the committed counter summary, if it
+    was taken on the current kernel sources (else None)."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            fields = dict(l.split(":", 1) for l in f.read().splitlines() if l.startswith(("traffic_", "sources_")))
+    except OSError:
+        return None
+    if fields.get("sources_sha256", "").strip() != kernel_sources_digest():
+        return None
+    return float(fields["traffic_bytes_per_launch"])
+
+
+def copy_calibration():
+    """A plain 1 GiB device-to-device copy, three times: the reference the
+    FETCH_SIZE / WRITE_SIZE counters are scaled by."""
+    import torch
+    n = 1 << 28
+    src = torch.ones(n, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print("copied 1 GiB x 3", flush=True)
 
 
 def cpu_baseline(pocket, ligs, orient, S, budget_s=15.0):
@@ -206,13 +265,21 @@ def main():
     ap.add_argument("--bump", choices=("pruned", "direct"), default="pruned",
                     help="pruned: test only pairs that can clash; direct: every pair")
     ap.add_argument("--waves", type=int, default=4, help="waves per block of the sweep")
+    ap.add_argument("--claim", type=int, default=32,
+                    help="most items a wave takes per work-queue atomic")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-proposal comparison")
     ap.add_argument("--proposal", default=None, help="directory of trained proposal weights")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run the 1 GiB copy that calibrates the HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(the batch shards by ligand with no exchange; see DESIGN.md)", file=sys.stderr)
         sys.exit(2)
+
+    if args.copy_calibration:
+        copy_calibration()
+        return
 
     import torch
     from paper_1901_06229_amd import dock, synth
@@ -243,16 +310,16 @@ def main():
     max_atoms = int(np.diff(ligs.atom_offset).max())
     flags = dock.DOCK_FLAG_TIME_SWEEP | (dock.DOCK_FLAG_DIRECT_BUMP if args.bump == "direct" else 0)
     prm = dock.make_params(r_bump=synth.R_BUMP, max_atoms=max_atoms, flags=flags)
-    dock.dock_set_launch(h, args.waves)
+    dock.dock_set_launch(h, args.waves, 0, args.claim)
     stream = torch.cuda.Stream()
     torch.cuda.synchronize()
 
-    pair_tests = []
+    work = []
 
     def step():
         dock.dock_batch_async(h, d, orient_d, S, out, prm, workspace=ws, stream=stream)
         ms = dock.dock_last_sweep_ms(h)
-        pair_tests.append(dock.dock_last_sweep_pairs(h))
+        work.append(dock.dock_last_sweep_work(h))
         return ms
 
     for w in range(args.warmup):
@@ -269,26 +336,40 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     value = args.steps * L / elapsed
-    ops = algorithmic_ops(ligs, O, S, args.bump, pair_tests[-1])
+    kept_pairs, evals = work[-1]
+    ops = algorithmic_ops(ligs, O, S, args.bump, kept_pairs, evals)
     mean_s = float(np.mean(sweep_ms)) / 1e3
     achieved = ops / mean_s / 1e12
+    mq, msum = batch_counts(ligs)
     line = {
         "metric": METRIC, "value": round(value, 2), "unit": "ligands/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * elapsed / args.steps, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic", "mode": "plain", "bump": args.bump,
+        "launch": {"waves_per_block": args.waves, "items_per_claim": args.claim},
         "config": {"workload": WORKLOADS[cfg] if L == preset["n_ligands"] else
                    WORKLOADS[cfg] + f" (ligands overridden to {L})",
                    "n_ligands": L, "n_orient": O, "angle_steps": S, "r_bump": synth.R_BUMP},
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 2),
-                     "unit": "TOP/s", "frac": round(achieved / VALU_PEAK_TOPS, 4), "traffic": None,
+                     "unit": "TOP/s", "frac": round(achieved / VALU_PEAK_TOPS, 4),
+                     "traffic": measured_traffic() if (cfg == 2 and args.bump == "pruned"
+                                                       and L == preset["n_ligands"]) else None,
                      "kernel": "sweep_pruned_kernel" if args.bump == "pruned" else "sweep_kernel",
                      "kernel_ms": round(1e3 * mean_s, 3),
-                     "work": ("lane-ops: 25 per candidate pair per rotamer + 4 per executed "
-                              "(pair, angle) test + 26 per (moving atom, angle)")
+                     "work": (f"lane-ops: {OPS_CAND} per candidate pair per rotamer step + "
+                              f"{OPS_ARC} per kept pair (clash arc) + {OPS_EVAL} per (moving atom, "
+                              "non-bumping angle) evaluation")
                      if args.bump == "pruned" else
                      "dense lane-ops per angle: 8 per cross pair + 45 per moving atom",
-                     "pair_angle_tests": pair_tests[-1]},
+                     "candidate_pairs": int(mq * O), "kept_pairs": kept_pairs,
+                     "atom_angle_evals": evals,
+                     "valid_angle_frac": round(evals / (msum * O * S), 4) if msum else None,
+                     "dense_equivalent": {
+                         "unit": "TOP/s",
+                         "value": round(dense_ops(ligs, O, S) / mean_s / 1e12, 2),
+                         "note": "lane-ops the unpruned sweep would execute (every pair and "
+                                 "atom at every angle) per second of this kernel; not a "
+                                 "fraction of peak"}},
     }
     if not args.no_learned:
         log("learned proposal: training on the GPU and comparing with the plain sweep")

@@ -175,16 +175,23 @@ size_t dock_workspace_size(int32_t n_ligands, int64_t total_rot, int n_orient,
  * DOCK_E_INVAL (NULL), DOCK_E_STATE (no timed call yet), DOCK_E_DEVICE. */
 int dock_last_sweep_ms(dock_pocket *p, float *ms);
 
-/* Number of (cross pair, angle) bump tests the sweep kernel executed in the
- * last call with DOCK_FLAG_TIME_SWEEP (pruned mode: only the pairs that can
- * clash; direct mode: not counted, 0).  Waits for that call's sweep. */
-int dock_last_sweep_pairs(dock_pocket *p, uint64_t *pair_angle_tests);
+/* Work counters of the sweep kernel in the last call with
+ * DOCK_FLAG_TIME_SWEEP, for roofline accounting: kept_pairs = cross pairs
+ * whose clash arc was computed (those the cylinder bound could not clear),
+ * summed over rotamer steps and items; atom_angle_evals = (moving atom,
+ * angle) evaluations scored, i.e. sum over rotamer steps of m_r times the
+ * number of non-bumping angles (every angle when emitting profiles).  Both
+ * are 0 in direct-bump and learned mode.  Waits for that call's sweep.
+ * Errors: DOCK_E_INVAL (NULL), DOCK_E_STATE (no timed call yet),
+ * DOCK_E_DEVICE. */
+int dock_last_sweep_work(dock_pocket *p, uint64_t *kept_pairs, uint64_t *atom_angle_evals);
 
 /* Launch mapping of the sweep kernel for calls on this handle (the knobs the
  * autotuner turns): waves_per_block in {1, 2, 4}, each wave working on its
  * own (ligand, orientation) items; blocks_per_cu >= 0 caps resident blocks
- * per compute unit (0: occupancy limit); items_per_claim in [1, 64] is how
- * many consecutive items a wave takes from the work queue per atomic.
+ * per compute unit (0: occupancy limit); items_per_claim in [1, 64] caps how
+ * many consecutive items a wave takes from the work queue per atomic (a claim
+ * is a share of the items left, so it shrinks to 1 towards the end).
  * Results are bitwise identical under every mapping.  Errors: DOCK_E_INVAL. */
 int dock_set_launch(dock_pocket *p, int waves_per_block, int blocks_per_cu,
                     int items_per_claim);

@@ -38,8 +38,8 @@ struct dock_pocket {
   size_t sync_ws_bytes = 0;
   hipEvent_t ev_sweep[3] = {nullptr, nullptr, nullptr};  // sweep start/end, counter copied
   bool timed = false;
-  unsigned long long *h_pairs = nullptr;  // pinned copy of the pair-test count
-  LaunchPlan plan{4, 0, 1};
+  unsigned long long *h_work = nullptr;  // pinned copy of the sweep's two work counters
+  LaunchPlan plan{4, 0, 32};
   // last captured launch sequence of dock_batch_async (DOCK_FLAG_GRAPH)
   std::vector<unsigned char> graph_key;
   hipGraph_t graph = nullptr;
@@ -287,7 +287,7 @@ int enqueue_batch(dock_pocket *p, const dock_ligands *ligs, const float *orient,
   A.n_items = (int32_t)(L * O);
   A.claim = p->plan.items_per_claim;
   const bool timed = (prm->flags & DOCK_FLAG_TIME_SWEEP) != 0;
-  A.pair_tests = timed ? (unsigned long long *)(A.small + 4) : nullptr;
+  A.work = timed ? (unsigned long long *)(A.small + 4) : nullptr;
   A.keys = (unsigned long long *)(base + w.keys);
   A.kstar = (int16_t *)(base + w.kstar);
   A.all_scores = out->all_scores;
@@ -340,7 +340,7 @@ int enqueue_batch(dock_pocket *p, const dock_ligands *ligs, const float *orient,
     }
     if (timed) {
       if ((e = hipEventRecord(p->ev_sweep[1], st)) != hipSuccess) return hip_fail(e, "hipEventRecord");
-      e = hipMemcpyAsync(p->h_pairs, A.small + 4, sizeof(unsigned long long), hipMemcpyDeviceToHost, st);
+      e = hipMemcpyAsync(p->h_work, A.small + 4, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st);
       if (e == hipSuccess) e = hipEventRecord(p->ev_sweep[2], st);
       if (e != hipSuccess) return hip_fail(e, "timing");
       p->timed = true;
@@ -366,7 +366,7 @@ int enqueue_batch(dock_pocket *p, const dock_ligands *ligs, const float *orient,
   if (e != hipSuccess) return hip_fail(e, "sweep kernel");
   if (timed) {
     if ((e = hipEventRecord(p->ev_sweep[1], st)) != hipSuccess) return hip_fail(e, "hipEventRecord");
-    e = hipMemcpyAsync(p->h_pairs, A.small + 4, sizeof(unsigned long long), hipMemcpyDeviceToHost, st);
+    e = hipMemcpyAsync(p->h_work, A.small + 4, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st);
     if (e != hipSuccess) return hip_fail(e, "copy pair count");
     if ((e = hipEventRecord(p->ev_sweep[2], st)) != hipSuccess) return hip_fail(e, "hipEventRecord");
     p->timed = true;
@@ -402,14 +402,15 @@ const char *dock_strerror(int code) {
 
 const char *dock_last_error(void) { return g_last_error.c_str(); }
 
-int dock_last_sweep_pairs(dock_pocket *p, uint64_t *pair_angle_tests) {
+int dock_last_sweep_work(dock_pocket *p, uint64_t *kept_pairs, uint64_t *atom_angle_evals) {
   g_last_error.clear();
-  if (!p || !pair_angle_tests) return fail(DOCK_E_INVAL, "NULL argument");
+  if (!p || !kept_pairs || !atom_angle_evals) return fail(DOCK_E_INVAL, "NULL argument");
   if (!p->timed) return fail(DOCK_E_STATE, "no call with DOCK_FLAG_TIME_SWEEP yet");
   DeviceGuard g(p->device);
   hipError_t e = hipEventSynchronize(p->ev_sweep[2]);
   if (e != hipSuccess) return hip_fail(e, "sweep counters");
-  *pair_angle_tests = (uint64_t)*(volatile unsigned long long *)p->h_pairs;
+  *kept_pairs = (uint64_t)((volatile unsigned long long *)p->h_work)[0];
+  *atom_angle_evals = (uint64_t)((volatile unsigned long long *)p->h_work)[1];
   return DOCK_OK;
 }
 
@@ -499,7 +500,7 @@ int dock_autotune(dock_pocket *p, const dock_ligands *ligs, const float *orient,
   dock_params tp = *prm;
   tp.flags |= DOCK_FLAG_TIME_SWEEP;
   const int waves[] = {1, 2, 4};
-  const int claims[] = {1, 2, 8};
+  const int claims[] = {4, 16, 32, 64};
   LaunchPlan best_plan = p->plan;
   float best_ms = 0.0f;
   int n = 0;
@@ -582,7 +583,7 @@ int dock_init_pocket(const float *grid, int nx, int ny, int nz, const float orig
   if (e == hipSuccess) e = hipEventCreate(&p->ev_sweep[0]);
   if (e == hipSuccess) e = hipEventCreate(&p->ev_sweep[1]);
   if (e == hipSuccess) e = hipEventCreate(&p->ev_sweep[2]);
-  if (e == hipSuccess) e = hipHostMalloc((void **)&p->h_pairs, sizeof(unsigned long long), 0);
+  if (e == hipSuccess) e = hipHostMalloc((void **)&p->h_work, 2 * sizeof(unsigned long long), 0);
   if (e == hipSuccess) e = hipMemcpyAsync(p->d_grid, grid, bytes, hipMemcpyHostToDevice, p->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
   if (e != hipSuccess) {
@@ -607,7 +608,7 @@ void dock_free_pocket(dock_pocket *p) {
     if (p->stream) (void)hipStreamDestroy(p->stream);
     for (hipEvent_t ev : p->ev_sweep)
       if (ev) (void)hipEventDestroy(ev);
-    if (p->h_pairs) (void)hipHostFree(p->h_pairs);
+    if (p->h_work) (void)hipHostFree(p->h_work);
     if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
     if (p->graph) (void)hipGraphDestroy(p->graph);
     free_learned(p);

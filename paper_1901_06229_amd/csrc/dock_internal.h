@@ -46,7 +46,9 @@ struct SweepArgs {
   int32_t *queue;
   int32_t n_items;
   int32_t claim;                   // consecutive items a wave takes per queue atomic
-  unsigned long long *pair_tests;  // accumulated once per wave
+  // work counters, accumulated once per wave: [0] kept cross pairs (summed
+  // over rotamer steps), [1] (moving atom, angle) evaluations scored
+  unsigned long long *work;
   unsigned long long *keys;  // [n_ligands] best (score, orientation) key
   int16_t *kstar;            // [total_rot * passes * n_orient]
   float *all_scores;         // optional [n_ligands][n_orient]

@@ -55,11 +55,9 @@ __device__ __forceinline__ ItemInfo item_info(const LearnedArgs &A, int item) {
 
 __device__ __forceinline__ RotState setup_step(const LearnedArgs &A, const WaveLds &W,
                                                const ItemInfo &I, int step, int lane) {
-  const int r = step % I.R;
-  const int ms = A.sw.lig.move_offset[I.r0 + r];
-  return rotamer_setup(W, I.n, A.sw.lig.rot_axis[2 * (I.r0 + r)],
-                       A.sw.lig.rot_axis[2 * (I.r0 + r) + 1], A.sw.lig.move_atoms + ms,
-                       A.sw.lig.move_offset[I.r0 + r + 1] - ms, lane);
+  const int rot = I.r0 + step % I.R;
+  const RotTopo T = topo_finish(A.sw.lig, topo_words_load(A.sw.lig, rot, lane), lane);
+  return rotamer_setup(W, I.n, T, A.sw.lig.move_atoms, lane);
 }
 
 // Features and exact validity of the rotamer step just set up.
@@ -70,7 +68,7 @@ __device__ __forceinline__ void write_step_inputs(const LearnedArgs &A, const Wa
   rotamer_bump_mask(W, RS, A.sw.r2, A.sw.r2 + kPruneMargin, 256, lane);
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
-    const uint64_t vm = __ballot(!step_bumps(W, t * kWave + lane));
+    const uint64_t vm = tile_valid_mask(W, t, 256);
     if (lane == 0) A.valid[(size_t)item * 4 + t] = vm;
   }
 }
@@ -95,7 +93,7 @@ __device__ __forceinline__ void save_pose(const LearnedArgs &A, const WaveLds &W
 __global__ void __launch_bounds__(kWave) learned_begin_kernel(LearnedArgs A) {
   extern __shared__ float4 dyn_lds[];
   const int lane = threadIdx.x;
-  const WaveLds W((char *)dyn_lds, A.nmax);
+  const WaveLds W((char *)dyn_lds, A.nmax, false);
   for (int item = blockIdx.x; item < A.sw.n_items; item += gridDim.x) {
     const ItemInfo I = item_info(A, item);
     if (A.sw.status[I.l] != 0) continue;
@@ -114,7 +112,7 @@ __global__ void __launch_bounds__(kWave) learned_begin_kernel(LearnedArgs A) {
 __global__ void __launch_bounds__(kWave) learned_step_kernel(LearnedArgs A, int step) {
   extern __shared__ float4 dyn_lds[];
   const int lane = threadIdx.x;
-  const WaveLds W((char *)dyn_lds, A.nmax);
+  const WaveLds W((char *)dyn_lds, A.nmax, false);
   const GridView G = A.sw.grid;
   const GridScaled GS = grid_scaled(G);
   const __amdgpu_buffer_rsrc_t grsrc = grid_rsrc(G);
@@ -125,7 +123,7 @@ __global__ void __launch_bounds__(kWave) learned_step_kernel(LearnedArgs A, int 
     for (int i = lane; i < I.n; i += kWave) W.X[i] = src[i];
     wave_lds_sync();
     const RotState RS = setup_step(A, W, I, step, lane);
-    const float s0 = rotamer_s0(W, RS);
+    const float s0 = rotamer_s0(W, RS, lane);
     // predictions of this item's 256 bins, invalid ones out of the race
     const float *y = A.pred + (size_t)item * 256;
     uint64_t vm[4];
@@ -162,11 +160,8 @@ __global__ void __launch_bounds__(kWave) learned_step_kernel(LearnedArgs A, int 
     const bool fallback = any_valid && margin < A.margin;
     uint64_t best = 0ull;
     if (fallback) {  // the plain step over every valid angle
-      uint32_t bump = 0;
-#pragma unroll
-      for (int t = 0; t < 4; ++t)
-        if (!((vm[t] >> lane) & 1ull)) bump |= 1u << t;
-      best = best_valid_step<4>(W, RS, G, GS, grsrc, A.sw.cs, bump, 0, s0, lane);
+      int nvalid;
+      best = best_valid_step<4, false>(W, RS, G, GS, grsrc, A.sw.cs, vm, 0, s0, lane, nvalid);
       if (lane == 0) atomicAdd(A.n_fallback + I.l, 1);
     } else if (any_valid) {  // nominated bins plus the current pose
       const bool zero_valid = vm[0] & 1ull;
@@ -174,7 +169,7 @@ __global__ void __launch_bounds__(kWave) learned_step_kernel(LearnedArgs A, int 
       const int ang = nom >= 0 ? nom : 0;
       const float2 cs = A.sw.cs[ang];
       float cc[1] = {cs.x}, ss[1] = {cs.y}, score[1];
-      rotamer_scores<1>(W, RS, G, GS, grsrc, cc, ss, score, lane);
+      rotamer_scores<1, false>(W, RS, G, GS, grsrc, cc, ss, score, lane);
       if (ang == 0) score[0] = s0;
       best = nom >= 0 ? best_key(score[0], (uint32_t)ang) : 0ull;
     }
@@ -206,14 +201,14 @@ static unsigned grid_for(int n_items, int n_cu) {
 hipError_t enqueue_learned_begin(const LearnedArgs &A, int n_cu, hipStream_t st) {
   if (A.sw.n_items <= 0) return hipSuccess;
   hipLaunchKernelGGL(learned_begin_kernel, dim3(grid_for(A.sw.n_items, n_cu)), dim3(kWave),
-                     wave_lds_bytes(A.nmax), st, A);
+                     wave_lds_bytes(A.nmax, false), st, A);
   return hipGetLastError();
 }
 
 hipError_t enqueue_learned_step(const LearnedArgs &A, int step, int n_cu, hipStream_t st) {
   if (A.sw.n_items <= 0) return hipSuccess;
   hipLaunchKernelGGL(learned_step_kernel, dim3(grid_for(A.sw.n_items, n_cu)), dim3(kWave),
-                     wave_lds_bytes(A.nmax), st, A, step);
+                     wave_lds_bytes(A.nmax, false), st, A, step);
   return hipGetLastError();
 }
 

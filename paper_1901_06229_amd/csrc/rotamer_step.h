@@ -10,10 +10,10 @@
 //     D' - 2 (cos(theta) A + sin(theta) B), A = r_i.r_j, B = u.(r_i x r_j),
 //     D' = |r_i|^2 + |r_j|^2 + (z_i - z_j)^2, never below
 //     (|r_i| - |r_j|)^2 + (z_i - z_j)^2.  Pairs whose bound clears
-//     r_bump^2 + kPruneMargin cannot bump at any angle and are dropped; the
-//     kept pairs are tested at every angle of the lane.
-// Each lane carries TG angle slots given by their (cos, sin); the slot-to-
-// angle mapping is the caller's (tiles of consecutive steps for the sweep,
+//     r_bump^2 + kPruneMargin cannot bump at any angle and are dropped; each
+//     kept pair's clash arc is marked into a bitmask of the S steps.
+// Scoring takes TG angle slots per lane given by their (cos, sin); the slot-
+// to-angle mapping is the caller's (compacted valid steps for the sweep,
 // nominated steps for the learned proposal).
 #pragma once
 
@@ -27,18 +27,34 @@ namespace dock {
 
 constexpr int kPairCap = 128;  // LDS pair-list entries per wave
 
+// 1: candidate pairs are enumerated with the static atoms on the lanes and
+// the moving atoms broadcast in turn; 0: over the flattened (moving, static)
+// index.  Same kept pairs either way.
+#ifndef DOCK_PAIR_ILOOP
+#define DOCK_PAIR_ILOOP 1
+#endif
+
 __host__ __device__ inline int wave_head_bytes(int nmax) {
   // X, C (float4), rho (float), Q, M (int16), mov (uint8)
   const int b = nmax * 16 * 2 + nmax * 4 + nmax * 2 * 2 + nmax;
   return (b + 15) / 16 * 16;
 }
 
-constexpr int kMaskWords = 128;  // invalid-angle bitmask of up to 4096 steps
+constexpr int kMaskWords = 128;   // invalid-angle bitmask of up to 4096 steps
+constexpr int kBasisBytes = kWave * 48;  // rotation bases of 64 atoms, 3 float4 each
+constexpr int kCompactCap = 512;  // compacted steps of one tile group (TG <= 8)
 
-__host__ __device__ inline int wave_lds_bytes(int nmax) {
-  // then the pair list -- coefficients (float4) and packed atom pairs (int32),
-  // reused afterwards for the compacted valid angles -- and the bitmask
-  return wave_head_bytes(nmax) + kPairCap * (16 + 4) + kMaskWords * 4;
+// Scratch region of a wave: the kept-pair list during the bump test, then
+// (when the bases are staged in LDS) the moving atoms' rotation bases and the
+// compacted valid angles while scoring.
+__host__ __device__ constexpr int wave_scratch_bytes(bool lds_basis) {
+  return (lds_basis ? kBasisBytes : 0) + kCompactCap * 2 > kPairCap * 4
+             ? (lds_basis ? kBasisBytes : 0) + kCompactCap * 2
+             : kPairCap * 4;
+}
+
+__host__ __device__ inline int wave_lds_bytes(int nmax, bool lds_basis) {
+  return wave_head_bytes(nmax) + wave_scratch_bytes(lds_basis) + kMaskWords * 4;
 }
 
 struct WaveLds {
@@ -48,21 +64,22 @@ struct WaveLds {
   int16_t *Q;    // static cross set of the rotamer
   int16_t *M;    // moving set of the rotamer
   uint8_t *mov;  // moving flags
-  float4 *P;     // kept pairs: 2A, 2B, D' - r_bump^2
   int *PI;       // kept pairs: i << 16 | j
-  int16_t *CK;   // compacted valid angle steps (aliases P, used after the bump test)
+  float4 *B;     // rotation bases of 64 moving atoms (aliases PI, used after the bump test)
+  int16_t *CK;   // compacted valid angle steps (after B)
   uint32_t *BM;  // bit k set: angle step k bumps
-  __device__ WaveLds(char *base, int nmax) {
+  __device__ WaveLds(char *base, int nmax, bool lds_basis) {
     X = (float4 *)base;
     C = X + nmax;
     rho = (float *)(C + nmax);
     Q = (int16_t *)(rho + nmax);
     M = Q + nmax;
     mov = (uint8_t *)(M + nmax);
-    P = (float4 *)(base + wave_head_bytes(nmax));
-    PI = (int *)(P + kPairCap);
-    CK = (int16_t *)P;
-    BM = (uint32_t *)(PI + kPairCap);
+    char *scr = base + wave_head_bytes(nmax);
+    PI = (int *)scr;
+    B = (float4 *)scr;
+    CK = (int16_t *)(scr + (lds_basis ? kBasisBytes : 0));
+    BM = (uint32_t *)(scr + wave_scratch_bytes(lds_basis));
   }
 };
 
@@ -77,50 +94,91 @@ __device__ __forceinline__ uint64_t lanes_below_mask(int lane) {
   return (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 }
 
-// Moving / static sets, the static score, the axis and cylindrical coords.
-__device__ __forceinline__ RotState rotamer_setup(const WaveLds &W, int n, int ra, int rb,
-                                                  const int16_t *mlist, int m, int lane) {
+// Topology of one rotamer step in registers: the bond-axis atoms, the
+// moving list's offset and length, and (lane t < 64) moving atom number t.
+// Loaded in two parts so the sweep can fetch the next step's topology while
+// it works on the current one; both are vector loads, so the waits that
+// later vector loads need cover them as well.
+struct RotTopo {
+  int ra, rb, ms, m;
+  int mv;
+};
+
+// Lanes 0-3 read ra, rb and the moving list's bounds of rotamer rot.
+__device__ __forceinline__ int topo_words_load(const LigView &lig, int rot, int lane) {
+  int v = 0;
+  if (lane < 2)
+    v = lig.rot_axis[2 * rot + lane];
+  else if (lane < 4)
+    v = lig.move_offset[rot + lane - 2];
+  return v;
+}
+
+// Unpacks the words and loads the first 64 moving atoms.
+__device__ __forceinline__ RotTopo topo_finish(const LigView &lig, int words, int lane) {
+  RotTopo t;
+  t.ra = __builtin_amdgcn_readlane(words, 0);
+  t.rb = __builtin_amdgcn_readlane(words, 1);
+  t.ms = __builtin_amdgcn_readlane(words, 2);
+  t.m = __builtin_amdgcn_readlane(words, 3) - t.ms;
+  t.mv = lane < t.m ? (int)lig.move_atoms[t.ms + lane] : 0;
+  return t;
+}
+
+// Moving / static sets, the static score, the axis and cylindrical coords
+// of the step with topology T (moving atoms past the first 64 are read from
+// move_atoms).
+__device__ __forceinline__ RotState rotamer_setup(const WaveLds &W, int n, const RotTopo &T,
+                                                  const int16_t *move_atoms, int lane) {
   const uint64_t below = lanes_below_mask(lane);
   for (int i = lane; i < n; i += kWave) W.mov[i] = 0;
   wave_lds_sync();
-  for (int t = lane; t < m; t += kWave) {
-    const int i = mlist[t];
+  for (int t = lane; t < T.m; t += kWave) {
+    const int i = t < kWave ? T.mv : (int)move_atoms[T.ms + t];
     W.mov[i] = 1;
     W.M[t] = (int16_t)i;
   }
   wave_lds_sync();
   RotState R;
-  R.m = m;
+  R.m = T.m;
+  R.xa = W.X[T.ra];
+  R.u = bond_axis(R.xa, W.X[T.rb]);
+  // one pass over the atoms: static list, static score (per-lane partial
+  // sums in atom order, then a fixed butterfly), cylindrical coordinates
   int q = 0;
+  float cst = 0.0f;
   for (int base = 0; base < n; base += kWave) {
     const int i = base + lane;
-    const bool st = i < n && !W.mov[i] && i != ra && i != rb;
+    bool st = false;
+    if (i < n) {
+      const float4 xi = W.X[i];
+      const bool moving = W.mov[i] != 0;
+      if (!moving) cst += xi.w;
+      st = !moving && i != T.ra && i != T.rb;
+      const Cyl c = cyl_of(xi, R.xa, R.u);
+      W.C[i] = make_float4(c.rx, c.ry, c.rz, c.z);
+      W.rho[i] = sqrtf(fmaf(c.rx, c.rx, fmaf(c.ry, c.ry, c.rz * c.rz)));
+    }
     const uint64_t mask = __ballot(st);
     if (st) W.Q[q + __popcll(mask & below)] = (int16_t)i;
     q += __popcll(mask);
   }
   R.q = q;
-  // per-lane partial sums in atom order, then a fixed butterfly over the wave
-  float cst = 0.0f;
-  for (int i = lane; i < n; i += kWave)
-    if (!W.mov[i]) cst += W.X[i].w;
   R.cst = wave_sum(cst);
-  R.xa = W.X[ra];
-  R.u = bond_axis(R.xa, W.X[rb]);
-  for (int i = lane; i < n; i += kWave) {
-    const Cyl c = cyl_of(W.X[i], R.xa, R.u);
-    W.C[i] = make_float4(c.rx, c.ry, c.rz, c.z);
-    W.rho[i] = sqrtf(fmaf(c.rx, c.rx, fmaf(c.ry, c.ry, c.rz * c.rz)));
-  }
   wave_lds_sync();
   return R;
 }
 
 // Score of the current pose (angle step 0): static score plus the moving
-// atoms' own values, in atom order -- the same order the angle scores use.
-__device__ __forceinline__ float rotamer_s0(const WaveLds &W, const RotState &R) {
+// atoms' own values, added in atom order -- the order the angle scores use.
+// The values are read in parallel and added by broadcast.
+__device__ __forceinline__ float rotamer_s0(const WaveLds &W, const RotState &R, int lane) {
   float s = R.cst;
-  for (int t = 0; t < R.m; ++t) s += W.X[W.M[t]].w;
+  for (int c0 = 0; c0 < R.m; c0 += kWave) {
+    const float v = c0 + lane < R.m ? W.X[W.M[c0 + lane]].w : 0.0f;
+    const int cnt = min(kWave, R.m - c0);
+    for (int t = 0; t < cnt; ++t) s += lane_bcast(v, t);
+  }
   return s;
 }
 
@@ -190,9 +248,47 @@ __device__ __forceinline__ int rotamer_bump_mask(const WaveLds &W, const RotStat
                                                  float thr, int S, int lane) {
   const uint64_t below = lanes_below_mask(lane);
   for (int w = lane; w < (S + 31) / 32; w += kWave) W.BM[w] = 0u;
+  int np = 0, kept = 0;
+  // appends the lane's pair if act; flushes the list before it can overflow
+  auto push = [&](bool act, int packed) {
+    const uint64_t mask = __ballot(act);
+    if (act) W.PI[np + __popcll(mask & below)] = packed;
+    np += __popcll(mask);
+    if (np > kPairCap - kWave) {
+      wave_lds_sync();
+      mark_kept_pairs(W, R, r2, np, S, lane);
+      kept += np;
+      np = 0;
+      wave_lds_sync();
+    }
+  };
+#if DOCK_PAIR_ILOOP
+  // lanes hold 64 static atoms; 64 moving atoms sit in registers, one per
+  // lane, and are broadcast in turn
+  for (int ib = 0; ib < R.m; ib += kWave) {
+    const int mc = min(kWave, R.m - ib);
+    int il = 0;
+    float zl = 0.f, rl = 0.f;
+    if (lane < mc) {
+      il = W.M[ib + lane];
+      zl = W.C[il].w;
+      rl = W.rho[il];
+    }
+    for (int jb = 0; jb < R.q; jb += kWave) {
+      const bool jin = jb + lane < R.q;
+      const int j = jin ? W.Q[jb + lane] : 0;
+      const float zj = W.C[j].w, rj = W.rho[j];
+      for (int t = 0; t < mc; ++t) {
+        const float dz = lane_bcast(zl, t) - zj;
+        const float dr = lane_bcast(rl, t) - rj;
+        push(jin && fmaf(dr, dr, dz * dz) < thr,
+             (__builtin_amdgcn_readlane(il, t) << 16) | j);
+      }
+    }
+  }
+#else
   const int total = R.m * R.q;
   const float inv_q = R.q > 0 ? 1.0f / (float)R.q : 0.0f;
-  int np = 0, kept = 0;
   for (int base = 0; base < total; base += kWave) {
     const int pidx = base + lane;
     bool act = false;
@@ -214,34 +310,42 @@ __device__ __forceinline__ int rotamer_bump_mask(const WaveLds &W, const RotStat
       act = fmaf(dr, dr, dz * dz) < thr;
       packed = (i << 16) | j;
     }
-    const uint64_t mask = __ballot(act);
-    if (act) W.PI[np + __popcll(mask & below)] = packed;
-    np += __popcll(mask);
-    if (np > kPairCap - kWave) {
-      wave_lds_sync();
-      mark_kept_pairs(W, R, r2, np, S, lane);
-      kept += np;
-      np = 0;
-      wave_lds_sync();
-    }
+    push(act, packed);
   }
+#endif
   wave_lds_sync();
   mark_kept_pairs(W, R, r2, np, S, lane);
   wave_lds_sync();
   return kept + np;
 }
 
-// Bump bit of angle step k (k < S) from the mask.
-__device__ __forceinline__ bool step_bumps(const WaveLds &W, int k) {
-  return (W.BM[k >> 5] >> (k & 31)) & 1u;
+// Wave-uniform mask of the non-bumping steps of 64-step tile `tile` (bit i:
+// step 64 tile + i), zero past the S steps.  One broadcast LDS read.
+__device__ __forceinline__ uint64_t tile_valid_mask(const WaveLds &W, int tile, int S) {
+  const int first = tile * kWave;
+  if (first >= S) return 0ull;
+  const uint2 w = *(const uint2 *)(W.BM + 2 * tile);
+  // readfirstlane returns int: go through uint32_t so nothing sign-extends
+  const uint64_t bumps = ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane(w.y) << 32) |
+                         (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane(w.x);
+  const int left = S - first;
+  const uint64_t range = left >= kWave ? ~0ull : ((1ull << left) - 1ull);
+  return ~bumps & range;
+}
+
+// Number of set bits of a wave-uniform mask below the lane.
+__device__ __forceinline__ int mask_rank(uint64_t m) {
+  return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                        __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 
 // Scores of the lane's TG angle slots: static score plus the voxel values
-// of the rotated moving atoms, added in atom order.  Lanes hold the voxel-
-// space rotation basis ((p - o)/h, e/h, f/h) of up to 64 moving atoms; each
-// lane reads one atom's basis at a time and issues the gathers of all its
-// slots before using any of them.
-template <int TG>
+// of the rotated moving atoms, added in atom order.  Per chunk of 64 moving
+// atoms each lane computes one atom's voxel-space rotation basis
+// ((p - o)/h, e/h, f/h); the bases reach every lane either from LDS
+// (LB: broadcast reads, no ALU work) or by readlane from the lane that holds
+// them.  Gathers run one atom ahead of the adds.
+template <int TG, bool LB>
 __device__ __forceinline__ void rotamer_scores(const WaveLds &W, const RotState &R,
                                                const GridView &G, const GridScaled &GS,
                                                __amdgpu_buffer_rsrc_t grsrc,
@@ -266,29 +370,65 @@ __device__ __forceinline__ void rotamer_scores(const WaveLds &W, const RotState 
       b8 = bs.fz * G.inv_h;
     }
     const int cnt = min(kWave, R.m - c0);
-    for (int tt = 0; tt < cnt; ++tt) {
-      const float px = lane_bcast(b0, tt), py = lane_bcast(b1, tt), pz = lane_bcast(b2, tt);
-      const float ex = lane_bcast(b3, tt), ey = lane_bcast(b4, tt), ez = lane_bcast(b5, tt);
-      const float fx = lane_bcast(b6, tt), fy = lane_bcast(b7, tt), fz = lane_bcast(b8, tt);
+    if constexpr (LB) {
+      W.B[3 * lane] = make_float4(b0, b1, b2, b3);
+      W.B[3 * lane + 1] = make_float4(b4, b5, b6, b7);
+      W.B[3 * lane + 2] = make_float4(b8, 0.f, 0.f, 0.f);
+      wave_lds_sync();
+    }
+    // gathers of atom tt of this chunk at the lane's TG angles
+    auto gather = [&](int tt, float(&v)[TG]) {
+      float px, py, pz, ex, ey, ez, fx, fy, fz;
+      if constexpr (LB) {
+        const float4 q0 = W.B[3 * tt], q1 = W.B[3 * tt + 1];
+        px = q0.x, py = q0.y, pz = q0.z, ex = q0.w;
+        ey = q1.x, ez = q1.y, fx = q1.z, fy = q1.w;
+        fz = W.B[3 * tt + 2].x;
+      } else {
+        px = lane_bcast(b0, tt), py = lane_bcast(b1, tt), pz = lane_bcast(b2, tt);
+        ex = lane_bcast(b3, tt), ey = lane_bcast(b4, tt), ez = lane_bcast(b5, tt);
+        fx = lane_bcast(b6, tt), fy = lane_bcast(b7, tt), fz = lane_bcast(b8, tt);
+      }
       uint32_t off[TG];
 #pragma unroll
       for (int t = 0; t < TG; ++t)
         off[t] = voxel_byte_offset(GS, fmaf(ss[t], fx, fmaf(cc[t], ex, px)),
                                    fmaf(ss[t], fy, fmaf(cc[t], ey, py)),
                                    fmaf(ss[t], fz, fmaf(cc[t], ez, pz)));
-      float val[TG];
 #pragma unroll
-      for (int t = 0; t < TG; ++t) val[t] = grid_load(grsrc, off[t]);
+      for (int t = 0; t < TG; ++t) v[t] = grid_load(grsrc, off[t]);
+      __builtin_amdgcn_sched_barrier(0);  // adds stay behind these loads
+    };
+    auto accumulate = [&](const float(&v)[TG]) {
 #pragma unroll
-      for (int t = 0; t < TG; ++t) score[t] += val[t];
+      for (int t = 0; t < TG; ++t) score[t] += v[t];
+    };
+    // two register sets alternate: atom tt + 1's gathers are issued before
+    // atom tt's values are added, so no value is copied
+    float va[TG], vb[TG];
+    gather(0, va);
+    int tt = 1;
+    for (; tt + 1 < cnt; tt += 2) {
+      gather(tt, vb);
+      accumulate(va);
+      gather(tt + 1, va);
+      accumulate(vb);
     }
+    if (tt < cnt) {
+      gather(tt, vb);
+      accumulate(va);
+      accumulate(vb);
+    } else {
+      accumulate(va);
+    }
+    if constexpr (LB) wave_lds_sync();
   }
 }
 
 // Best (score, -k) key over the valid steps compacted in W.CK[0, nvalid),
 // TC tiles of 64 lanes; angle step 0, if valid, is compacted first and takes
 // the exact score s0 of the current pose.
-template <int TC>
+template <int TC, bool LB>
 __device__ __forceinline__ uint64_t score_compacted(const WaveLds &W, const RotState &R,
                                                     const GridView &G, const GridScaled &GS,
                                                     __amdgpu_buffer_rsrc_t grsrc,
@@ -304,7 +444,7 @@ __device__ __forceinline__ uint64_t score_compacted(const WaveLds &W, const RotS
     cc[t] = cs.x;
     ss[t] = cs.y;
   }
-  rotamer_scores<TC>(W, R, G, GS, grsrc, cc, ss, score, lane);
+  rotamer_scores<TC, LB>(W, R, G, GS, grsrc, cc, ss, score, lane);
   uint64_t best = 0ull;
 #pragma unroll
   for (int t = 0; t < TC; ++t) {
@@ -315,45 +455,41 @@ __device__ __forceinline__ uint64_t score_compacted(const WaveLds &W, const RotS
   return best;
 }
 
-// Scores only the valid steps among the lane's TG slots (tile t holds step
-// (t0 + t) * 64 + lane): they are compacted into as few 64-lane tiles as
-// possible first.  Returns the lane's best key (wave reduction is the
-// caller's).
-template <int TG>
+// Scores only the valid steps of tiles t0 .. t0 + TG - 1, given their wave-
+// uniform valid masks vm (bit i of vm[t]: step (t0 + t) * 64 + i): they are
+// compacted into as few 64-lane tiles as possible first.  Returns the lane's
+// best key (wave reduction is the caller's) and the number of valid steps in
+// nvalid.
+template <int TG, bool LB>
 __device__ __forceinline__ uint64_t best_valid_step(const WaveLds &W, const RotState &R,
                                                     const GridView &G, const GridScaled &GS,
                                                     __amdgpu_buffer_rsrc_t grsrc,
-                                                    const float2 *cs_table, uint32_t bump, int t0,
-                                                    float s0, int lane) {
-  const uint64_t below = lanes_below_mask(lane);
-  int nvalid = 0;
+                                                    const float2 *cs_table,
+                                                    const uint64_t (&vm)[TG], int t0, float s0,
+                                                    int lane, int &nvalid) {
+  nvalid = 0;
 #pragma unroll
   for (int t = 0; t < TG; ++t) {
-    const bool v = !((bump >> t) & 1u);
-    const uint64_t m = __ballot(v);
-    if (v) W.CK[nvalid + __popcll(m & below)] = (int16_t)((t0 + t) * kWave + lane);
-    nvalid += __popcll(m);
+    if ((vm[t] >> lane) & 1ull)
+      W.CK[nvalid + mask_rank(vm[t])] = (int16_t)((t0 + t) * kWave + lane);
+    nvalid += __popcll(vm[t]);
   }
   wave_lds_sync();
   uint64_t best = 0ull;
-  if (nvalid > 0) {
-    const int tc = (nvalid + kWave - 1) / kWave;
-    if (tc == 1) best = score_compacted<1>(W, R, G, GS, grsrc, cs_table, nvalid, s0, lane);
-    if constexpr (TG >= 2)
-      if (tc == 2) best = score_compacted<2>(W, R, G, GS, grsrc, cs_table, nvalid, s0, lane);
-    if constexpr (TG >= 3)
-      if (tc == 3) best = score_compacted<3>(W, R, G, GS, grsrc, cs_table, nvalid, s0, lane);
-    if constexpr (TG >= 4)
-      if (tc == 4) best = score_compacted<4>(W, R, G, GS, grsrc, cs_table, nvalid, s0, lane);
-    if constexpr (TG >= 5)
-      if (tc == 5) best = score_compacted<5>(W, R, G, GS, grsrc, cs_table, nvalid, s0, lane);
-    if constexpr (TG >= 6)
-      if (tc == 6) best = score_compacted<6>(W, R, G, GS, grsrc, cs_table, nvalid, s0, lane);
-    if constexpr (TG >= 7)
-      if (tc == 7) best = score_compacted<7>(W, R, G, GS, grsrc, cs_table, nvalid, s0, lane);
-    if constexpr (TG >= 8)
-      if (tc == 8) best = score_compacted<8>(W, R, G, GS, grsrc, cs_table, nvalid, s0, lane);
-  }
+  const int tc = (nvalid + kWave - 1) / kWave;
+  // one instantiation per tile count so the slot arrays stay in registers
+#define DOCK_SCORE_TC(c)                                                                  \
+  if constexpr (TG >= c)                                                                  \
+    if (tc == c) best = score_compacted<c, LB>(W, R, G, GS, grsrc, cs_table, nvalid, s0, lane);
+  DOCK_SCORE_TC(1)
+  DOCK_SCORE_TC(2)
+  DOCK_SCORE_TC(3)
+  DOCK_SCORE_TC(4)
+  DOCK_SCORE_TC(5)
+  DOCK_SCORE_TC(6)
+  DOCK_SCORE_TC(7)
+  DOCK_SCORE_TC(8)
+#undef DOCK_SCORE_TC
   wave_lds_sync();
   return best;
 }

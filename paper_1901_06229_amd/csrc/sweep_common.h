@@ -58,8 +58,41 @@ __device__ __forceinline__ uint32_t voxel_byte_offset(const GridScaled &g, float
   const uint32_t ix = (uint32_t)__builtin_amdgcn_fmed3f(tx, 0.0f, g.hx);
   const uint32_t iy = (uint32_t)__builtin_amdgcn_fmed3f(ty, 0.0f, g.hy);
   const uint32_t iz = (uint32_t)__builtin_amdgcn_fmed3f(tz, 0.0f, g.hz);
-  return __umul24(__umul24(iz, g.ny) + iy, g.nx4) + (ix << 2);
+  // Two full-rate 24-bit multiply-adds (exact: every axis has at most 4096
+  // voxels).  Written out because the compiler otherwise folds the first
+  // product and add into a 64-bit multiply-add, a multi-pass instruction.
+  uint32_t t, off;
+  asm("v_mad_u32_u24 %0, %1, %2, %3" : "=v"(t) : "v"(iz), "s"(g.ny), "v"(iy));
+  asm("v_mad_u32_u24 %0, %1, %2, %3" : "=v"(off) : "v"(t), "s"(g.nx4), "v"(ix << 2));
+  return off;
 }
+
+// Items of a persistent wave, taken from one global counter by guided
+// self-scheduling: a claim is a share of the items left (as of the wave's
+// previous claim) between 1 and cap, so the counter sees few atomics while
+// there is much work and single items balance the tail.  The counter may end
+// above n_items by at most (waves x cap); the unsigned test keeps that safe
+// for any n_items < 2^31.
+struct WorkQueue {
+  int32_t *counter;
+  int n_items, cap, share;  // share = 4 x waves in the grid
+  int cur = 0, end = 0, seen = 0;
+  __device__ WorkQueue(int32_t *c, int n, int cap_, int waves)
+      : counter(c), n_items(n), cap(cap_), share(4 * waves) {}
+  __device__ __forceinline__ bool next(int lane, int &item) {
+    if (cur >= end) {
+      const int want = max(1, min(cap, (n_items - seen) / share));
+      int base = 0;
+      if (lane == 0) base = atomicAdd(counter, want);
+      base = __builtin_amdgcn_readfirstlane(__shfl(base, 0, 64));
+      if ((uint32_t)base >= (uint32_t)n_items) return false;
+      cur = seen = base;
+      end = min(base + want, n_items);
+    }
+    item = cur++;
+    return true;
+  }
+};
 
 // Grid read through a buffer resource (32-bit offsets, reads past the end
 // return 0 instead of faulting).

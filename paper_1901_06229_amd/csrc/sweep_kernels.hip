@@ -142,18 +142,8 @@ __global__ void __launch_bounds__(WAVES *kWave)
   const int O = A.n_orient, S = A.S;
   const uint64_t lanes_below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 
-  int cur = 0, end = 0;  // items claimed by this wave, [cur, end)
-  for (;;) {
-    if (cur >= end) {
-      int base = 0;
-      if (lane == 0) base = atomicAdd(A.queue, A.claim);
-      base = __shfl(base, 0, kWave);
-      base = __builtin_amdgcn_readfirstlane(base);
-      if (base >= A.n_items) break;
-      cur = base;
-      end = min(base + A.claim, A.n_items);
-    }
-    const int item = cur++;
+  WorkQueue queue(A.queue, A.n_items, A.claim, (int)(gridDim.x * blockDim.x / kWave));
+  for (int item; queue.next(lane, item);) {
     const int slot = item / O;
     const int o = item - slot * O;
     const int l = A.order[slot];

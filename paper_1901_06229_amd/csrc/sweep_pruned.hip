@@ -1,23 +1,24 @@
 // Greedy rotamer sweep with the bump test reduced to the pairs that can clash.
 //
-// Same mapping as the direct kernel (one 64-lane wave per (ligand,
-// orientation) item, persistent grid, work stealing; lanes = angle steps),
-// but the per-rotamer work is restructured around the rotation's geometry:
+// One 64-lane wave per (ligand, orientation) item, persistent grid, items
+// taken from a cost-sorted queue by guided claims.  Per rotamer step the wave
+// handles all S angle steps at once, restructured around the rotation's
+// geometry:
 //
-//   * Every atom is written once per rotamer in cylindrical form about the
-//     bond axis (radial vector r, axial z).  A moving atom at angle theta is
+//   * Every atom is written once per step in cylindrical form about the bond
+//     axis (radial vector r, axial z).  A moving atom at angle theta is
 //     a + z u + cos(theta) r + sin(theta) (u x r): 6 FMAs per angle.
-//   * For a cross pair (i moving, j static) the squared distance at angle
-//     theta is  d^2 = D' - 2 (cos(theta) A + sin(theta) B)  with
-//     A = r_i.r_j, B = u.(r_i x r_j), D' = |r_i|^2 + |r_j|^2 + (z_i - z_j)^2,
-//     and it never drops below (|r_i| - |r_j|)^2 + (z_i - z_j)^2.  Pairs whose
-//     lower bound clears r_bump^2 (plus a margin far above FP32 rounding)
-//     can never bump and are dropped; only the rest -- a few percent of
-//     the cross pairs -- are tested, at 2 FMAs and a compare per angle.
-//   * Survivors are compacted with ballots into an LDS list that every lane
-//     (angle) walks; the scores are gathered per angle in atom order.
-// The pair test is d^2 < r_bump^2 exactly as in the direct form; only the
-// algebra that evaluates d^2 differs (FP32 rounding at the 1e-6 A level).
+//   * A cross pair (i moving, j static) has squared distance
+//     d^2 = D' - 2 (cos(theta) A + sin(theta) B) with A = r_i.r_j,
+//     B = u.(r_i x r_j), D' = |r_i|^2 + |r_j|^2 + (z_i - z_j)^2, never below
+//     (|r_i| - |r_j|)^2 + (z_i - z_j)^2.  Pairs whose bound clears r_bump^2
+//     (plus a margin far above FP32 rounding) can never bump and are dropped.
+//   * Each kept pair bumps on one open arc of angles, found in closed form
+//     and marked into a bitmask of all S steps; only the non-bumping steps
+//     are then scored, compacted into full 64-lane tiles, with the gathers
+//     added in atom order.
+// The pair test is d^2 < r_bump^2 as in the direct form; only the algebra
+// that decides it differs (FP32 rounding at the 1e-6 A level).
 #include <hip/hip_runtime.h>
 
 #include "dock_internal.h"
@@ -26,13 +27,15 @@
 
 namespace dock {
 
-template <int WAVES, int TG>
+// LB: the moving atoms' rotation bases are staged in LDS for the scoring
+// loop (chosen at launch when the extra LDS costs no occupancy).
+template <int WAVES, int TG, bool LB>
 __global__ void __launch_bounds__(WAVES *kWave)
     sweep_pruned_kernel(SweepArgs A, int nmax) {
   extern __shared__ float4 dyn_lds[];
   const int wv = threadIdx.x / kWave;
   const int lane = threadIdx.x % kWave;
-  const WaveLds W((char *)dyn_lds + (size_t)wv * wave_lds_bytes(nmax), nmax);
+  const WaveLds W((char *)dyn_lds + (size_t)wv * wave_lds_bytes(nmax, LB), nmax, LB);
   const GridView G = A.grid;
   const GridScaled GS = grid_scaled(G);
   const __amdgpu_buffer_rsrc_t grsrc = grid_rsrc(G);
@@ -41,20 +44,10 @@ __global__ void __launch_bounds__(WAVES *kWave)
   const float r2 = A.r2;
   const float thr = r2 + kPruneMargin;
   const bool emit = A.emit_x != nullptr;  // profile emission: S == 256, TG == 4
-  uint64_t pair_tests = 0;  // executed (pair, angle) tests of this wave
+  uint64_t kept_pairs = 0, evals = 0;  // work counters of this wave
 
-  int cur = 0, end = 0;  // items claimed by this wave, [cur, end)
-  for (;;) {
-    if (cur >= end) {
-      int base = 0;
-      if (lane == 0) base = atomicAdd(A.queue, A.claim);
-      base = __shfl(base, 0, kWave);
-      base = __builtin_amdgcn_readfirstlane(base);
-      if (base >= A.n_items) break;
-      cur = base;
-      end = min(base + A.claim, A.n_items);
-    }
-    const int item = cur++;
+  WorkQueue queue(A.queue, A.n_items, A.claim, (int)gridDim.x * WAVES);
+  for (int item; queue.next(lane, item);) {
     const int slot = item / O;
     const int o = item - slot * O;
     const int l = A.order[slot];
@@ -67,35 +60,38 @@ __global__ void __launch_bounds__(WAVES *kWave)
 
     const size_t kbase = ((size_t)r0 * O + (size_t)o * R) * A.passes;
     int16_t *kout = A.kstar + kbase;
+    const int steps = R * A.passes;
     int step = 0;
     int kreg = -1;  // lane s holds the choice of step s (mod 64) until written out
+    // topology of the current step; the next step's is fetched during it
+    RotTopo topo{};
+    if (steps > 0) topo = topo_finish(A.lig, topo_words_load(A.lig, r0, lane), lane);
     for (int pass = 0; pass < A.passes; ++pass) {
       for (int r = 0; r < R; ++r, ++step) {
-        const int ms = A.lig.move_offset[r0 + r];
-        const RotState RS = rotamer_setup(W, n, A.lig.rot_axis[2 * (r0 + r)],
-                                          A.lig.rot_axis[2 * (r0 + r) + 1],
-                                          A.lig.move_atoms + ms,
-                                          A.lig.move_offset[r0 + r + 1] - ms, lane);
-        const float s0 = rotamer_s0(W, RS);
+        const bool more = step + 1 < steps;
+        const int words_next = more ? topo_words_load(A.lig, r0 + (r + 1 == R ? 0 : r + 1), lane) : 0;
+        const RotState RS = rotamer_setup(W, n, topo, A.lig.move_atoms, lane);
+        const float s0 = rotamer_s0(W, RS, lane);
         if (emit) A.emit_x[(kbase + step) * 64 + lane] = f32_to_bf16(rotamer_feature(W, RS, G, lane));
 
         // invalid steps of the rotamer, for all S steps at once
-        pair_tests += (uint64_t)rotamer_bump_mask(W, RS, r2, thr, S, lane);
+        kept_pairs += (uint64_t)rotamer_bump_mask(W, RS, r2, thr, S, lane);
+        const RotTopo topo_next = more ? topo_finish(A.lig, words_next, lane) : topo;
 
         uint64_t best = 0ull;
         for (int t0 = 0; t0 < T; t0 += TG) {
-          uint32_t bump = 0;
+          uint64_t vm[TG];  // wave-uniform valid masks of the group's tiles
 #pragma unroll
-          for (int t = 0; t < TG; ++t) {
-            const int k = (t0 + t) * kWave + lane;
-            if (t0 + t >= T || k >= S || step_bumps(W, k)) bump |= 1u << t;
-          }
+          for (int t = 0; t < TG; ++t) vm[t] = tile_valid_mask(W, t0 + t, S);
           if (!emit) {
+            int nvalid;
             const uint64_t key =
-                best_valid_step<TG>(W, RS, G, GS, grsrc, A.cs, bump, t0, s0, lane);
+                best_valid_step<TG, LB>(W, RS, G, GS, grsrc, A.cs, vm, t0, s0, lane, nvalid);
             best = key > best ? key : best;
+            evals += (uint64_t)RS.m * (uint64_t)nvalid;
             continue;
           }
+          evals += (uint64_t)RS.m * (uint64_t)(TG * kWave);
           // profile emission scores every step, valid or not
           float cc[TG], ss[TG], score[TG];
 #pragma unroll
@@ -105,12 +101,12 @@ __global__ void __launch_bounds__(WAVES *kWave)
             cc[t] = cs.x;
             ss[t] = cs.y;
           }
-          rotamer_scores<TG>(W, RS, G, GS, grsrc, cc, ss, score, lane);
+          rotamer_scores<TG, LB>(W, RS, G, GS, grsrc, cc, ss, score, lane);
           if (t0 == 0 && lane == 0) score[0] = s0;
 #pragma unroll
           for (int t = 0; t < TG; ++t) {
             const int k = (t0 + t) * kWave + lane;
-            const uint64_t key = (bump >> t) & 1u ? 0ull : best_key(score[t], (uint32_t)k);
+            const uint64_t key = (vm[t] >> lane) & 1ull ? best_key(score[t], (uint32_t)k) : 0ull;
             best = key > best ? key : best;
           }
           float smax = score[0];
@@ -121,9 +117,8 @@ __global__ void __launch_bounds__(WAVES *kWave)
 #pragma unroll
           for (int t = 0; t < TG; ++t) {
             trow[(t0 + t) * kWave + lane] = f32_to_bf16(fmaxf(score[t] - smax, -4.0f));
-            const uint64_t vm = __ballot(!((bump >> t) & 1u));
             if (lane < 2)
-              A.emit_mask[(kbase + step) * 8 + (t0 + t) * 2 + lane] = (uint32_t)(vm >> (32 * lane));
+              A.emit_mask[(kbase + step) * 8 + (t0 + t) * 2 + lane] = (uint32_t)(vm[t] >> (32 * lane));
           }
         }
         best = wave_max_u64(best);
@@ -134,6 +129,7 @@ __global__ void __launch_bounds__(WAVES *kWave)
           const float2 cs = A.cs[kb];
           rotamer_apply(W, RS, G, cs.x, cs.y, lane);
         }
+        topo = topo_next;
       }
     }
     if ((step & 63) != 0 && lane < (step & 63)) kout[(step & ~63) + lane] = (int16_t)kreg;
@@ -146,27 +142,51 @@ __global__ void __launch_bounds__(WAVES *kWave)
     }
     wave_lds_sync();
   }
-  if (lane == 0 && A.pair_tests) atomicAdd(A.pair_tests, (unsigned long long)pair_tests);
+  if (lane == 0 && A.work) {
+    atomicAdd(A.work, (unsigned long long)kept_pairs);
+    atomicAdd(A.work + 1, (unsigned long long)evals);
+  }
 }
 
+// Resident blocks per CU of one instantiation (0: its LDS exceeds a block's).
+template <int WAVES, int TG, bool LB>
+static hipError_t pruned_occupancy(int nmax, int blocks_per_cu, int *bpc) {
+  *bpc = 0;
+  const size_t shmem = (size_t)WAVES * wave_lds_bytes(nmax, LB);
+  if (shmem > 65536) return hipSuccess;
+  int occ = 0;
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+      &occ, sweep_pruned_kernel<WAVES, TG, LB>, WAVES * kWave, shmem);
+  if (e != hipSuccess) return e;
+  if (occ < 1) occ = 1;
+  *bpc = blocks_per_cu > 0 && blocks_per_cu < occ ? blocks_per_cu : occ;
+  return hipSuccess;
+}
+
+template <int WAVES, int TG, bool LB>
+static hipError_t launch_pruned_lb(const SweepArgs &A, int nmax, int bpc, int n_cu,
+                                   hipStream_t st) {
+  const size_t shmem = (size_t)WAVES * wave_lds_bytes(nmax, LB);
+  const int64_t need = (A.n_items + WAVES - 1) / WAVES;
+  int64_t grid = (int64_t)(bpc > 0 ? bpc : 1) * n_cu;
+  if (grid > need) grid = need;
+  if (grid < 1) grid = 1;
+  hipLaunchKernelGGL((sweep_pruned_kernel<WAVES, TG, LB>), dim3((unsigned)grid),
+                     dim3(WAVES * kWave), shmem, st, A, nmax);
+  return hipGetLastError();
+}
+
+// The LDS-staged bases when they keep the occupancy of the register form.
 template <int WAVES, int TG>
 static hipError_t launch_pruned_t(const SweepArgs &A, int nmax, int blocks_per_cu, int n_cu,
                                   hipStream_t st) {
-  const size_t shmem = (size_t)WAVES * wave_lds_bytes(nmax);
-  if (shmem > 65536) return hipErrorInvalidValue;
-  int occ = 0;
-  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-      &occ, sweep_pruned_kernel<WAVES, TG>, WAVES * kWave, shmem);
+  int occ_reg = 0, occ_lds = 0;
+  hipError_t e = pruned_occupancy<WAVES, TG, false>(nmax, blocks_per_cu, &occ_reg);
+  if (e == hipSuccess) e = pruned_occupancy<WAVES, TG, true>(nmax, blocks_per_cu, &occ_lds);
   if (e != hipSuccess) return e;
-  if (occ < 1) occ = 1;
-  const int bpc = blocks_per_cu > 0 && blocks_per_cu < occ ? blocks_per_cu : occ;
-  const int64_t need = (A.n_items + WAVES - 1) / WAVES;
-  int64_t grid = (int64_t)bpc * n_cu;
-  if (grid > need) grid = need;
-  if (grid < 1) grid = 1;
-  hipLaunchKernelGGL((sweep_pruned_kernel<WAVES, TG>), dim3((unsigned)grid),
-                     dim3(WAVES * kWave), shmem, st, A, nmax);
-  return hipGetLastError();
+  if (occ_reg < 1 && occ_lds < 1) return hipErrorInvalidValue;
+  if (occ_lds >= occ_reg) return launch_pruned_lb<WAVES, TG, true>(A, nmax, occ_lds, n_cu, st);
+  return launch_pruned_lb<WAVES, TG, false>(A, nmax, occ_reg, n_cu, st);
 }
 
 template <int WAVES>

@@ -101,8 +101,8 @@ def load_library(path: str = None):
     lib.dock_workspace_size.restype = c.c_size_t
     lib.dock_last_sweep_ms.argtypes = [_P, c.POINTER(c.c_float)]
     lib.dock_last_sweep_ms.restype = c.c_int
-    lib.dock_last_sweep_pairs.argtypes = [_P, c.POINTER(c.c_uint64)]
-    lib.dock_last_sweep_pairs.restype = c.c_int
+    lib.dock_last_sweep_work.argtypes = [_P, c.POINTER(c.c_uint64), c.POINTER(c.c_uint64)]
+    lib.dock_last_sweep_work.restype = c.c_int
     lib.dock_set_launch.argtypes = [_P, c.c_int, c.c_int, c.c_int]
     lib.dock_set_launch.restype = c.c_int
     lib.dock_get_launch.argtypes = [_P, c.POINTER(c.c_int), c.POINTER(c.c_int), c.POINTER(c.c_int)]
@@ -249,15 +249,16 @@ def dock_last_sweep_ms(pocket: Pocket) -> float:
     return float(ms.value)
 
 
-def dock_last_sweep_pairs(pocket: Pocket) -> int:
-    v = ctypes.c_uint64()
-    _check(load_library().dock_last_sweep_pairs(pocket.handle, ctypes.byref(v)),
-           "dock_last_sweep_pairs")
-    return int(v.value)
+def dock_last_sweep_work(pocket: Pocket) -> tuple[int, int]:
+    """(kept cross pairs, (moving atom, angle) evaluations) of the last timed sweep."""
+    kp, ev = ctypes.c_uint64(), ctypes.c_uint64()
+    _check(load_library().dock_last_sweep_work(pocket.handle, ctypes.byref(kp), ctypes.byref(ev)),
+           "dock_last_sweep_work")
+    return int(kp.value), int(ev.value)
 
 
 def dock_set_launch(pocket: Pocket, waves_per_block: int, blocks_per_cu: int = 0,
-                    items_per_claim: int = 1):
+                    items_per_claim: int = 32):
     _check(load_library().dock_set_launch(pocket.handle, int(waves_per_block), int(blocks_per_cu),
                                           int(items_per_claim)), "dock_set_launch")
 

@@ -53,3 +53,20 @@ def test_null_arguments_are_rejected_on_the_host(lib):
     assert lib.dock_batch(None, None, None, 1, 1, None, None) == dock.DOCK_E_INVAL
     assert lib.dock_batch_async(None, None, None, 1, 1, None, None, None, 0, None) == dock.DOCK_E_INVAL
     lib.dock_free_pocket(None)
+
+
+def test_bench_traffic_is_reported_only_for_the_measured_kernel(tmp_path, monkeypatch):
+    """roofline.traffic comes from the committed counter summary, and only
+    while the kernel code still hashes to the digest recorded with it."""
+    import bench
+    digest = bench.kernel_sources_digest()
+    good = tmp_path / "good.md"
+    good.write_text(f"# x\n\ntraffic_bytes_per_launch: 1234\nsources_sha256: {digest}\n")
+    stale = tmp_path / "stale.md"
+    stale.write_text("traffic_bytes_per_launch: 1234\nsources_sha256: " + "0" * 64 + "\n")
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(good))
+    assert bench.measured_traffic() == 1234.0
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(stale))
+    assert bench.measured_traffic() is None
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(tmp_path / "missing.md"))
+    assert bench.measured_traffic() is None

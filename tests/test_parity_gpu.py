@@ -203,7 +203,8 @@ def test_direct_bump_mode_parity(pockets):
 
 
 def test_results_independent_of_launch_mapping(pockets):
-    """Bitwise-identical results for every waves-per-block / blocks-per-CU plan."""
+    """Bitwise-identical results for every waves-per-block / blocks-per-CU /
+    claim-cap plan (claims shrink to single items at the end of the queue)."""
     p, h = pockets(2)
     ligs = synth.ligands(2, count=150, first=2000)
     orient = synth.orientations(2, 32)
@@ -216,7 +217,7 @@ def test_results_independent_of_launch_mapping(pockets):
             continue
         for k in ("best_score", "best_orient", "angle_idx", "xyz", "all_scores", "all_angle_idx"):
             assert np.array_equal(ref[k], res[k]), (waves, bpc, claim, k)
-    dock.dock_set_launch(h, 4, 0, 1)
+    dock.dock_set_launch(h, 4, 0, 32)
 
 
 def test_autotune_picks_fastest_and_keeps_results(pockets):
@@ -226,14 +227,14 @@ def test_autotune_picks_fastest_and_keeps_results(pockets):
     before = dock.dock_batch(h, ligs, orient, 128, want_all=True)
     entries = dock.dock_autotune(h, ligs, orient, 128, sample_ligands=100, seed=7)
     print(entries)
-    assert len(entries) == 9
+    assert len(entries) == 12  # waves {1, 2, 4} x claim caps {4, 16, 32, 64}
     best = min(entries, key=lambda e: e["sweep_ms"])
     assert dock.dock_get_launch(h) == (best["waves_per_block"], best["blocks_per_cu"],
                                        best["items_per_claim"])
     after = dock.dock_batch(h, ligs, orient, 128, want_all=True)
     for k in ("best_score", "best_orient", "angle_idx", "xyz", "all_scores", "all_angle_idx"):
         assert np.array_equal(before[k], after[k]), k
-    dock.dock_set_launch(h, 4, 0, 1)
+    dock.dock_set_launch(h, 4, 0, 32)
 
 
 def _device_batch(ligs, orient, S, torch):
