@@ -27,15 +27,6 @@ __device__ __forceinline__ uint32_t nom_key(float y, int k) {
   return (float_order(y) & 0xFFFFFF00u) | (uint32_t)(255 - k);
 }
 
-__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    const uint32_t o = (uint32_t)__shfl_xor((int)v, off, kWave);
-    v = o > v ? o : v;
-  }
-  return v;
-}
-
 // Rotamer index and step bookkeeping of an item.
 struct ItemInfo {
   int l, o, n, R, r0, a0, steps;

@@ -234,8 +234,9 @@ __device__ __forceinline__ void mark_kept_pairs(const WaveLds &W, const RotState
       mark_steps(W.BM, 0, S, S);
       continue;
     }
-    int lo = klo % S;
-    if (lo < 0) lo += S;
+    // klo lies in (-S, S/2 + 1]: one wrap either way replaces an integer modulo
+    int lo = klo < 0 ? klo + S : klo;
+    lo = lo >= S ? lo - S : lo;
     mark_steps(W.BM, lo, len, S);
   }
 }
@@ -505,17 +506,6 @@ __device__ __forceinline__ void rotamer_apply(const WaveLds &W, const RotState &
     W.X[i] = make_float4(y.x, y.y, y.z, voxel_value(G, y.x, y.y, y.z));
   }
   wave_lds_sync();
-}
-
-__device__ __forceinline__ float wave_max_f(float v) {
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) v = fmaxf(v, __shfl_xor(v, off, kWave));
-  return v;
-}
-__device__ __forceinline__ float wave_min_f(float v) {
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) v = fminf(v, __shfl_xor(v, off, kWave));
-  return v;
 }
 
 // The 64 input features of the learned proposal for this rotamer step: grid

@@ -218,21 +218,58 @@ __device__ __forceinline__ float key_score(uint64_t key) {
   return order_float((uint32_t)(key >> 32));
 }
 
-__device__ __forceinline__ uint64_t wave_max_u64(uint64_t v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    uint64_t o = __shfl_xor(v, off, kWave);
-    v = o > v ? o : v;
-  }
-  return v;
+// Wave reductions with DPP lane moves (VALU, no LDS round trips).  Six
+// steps combine pairs, quads, half-rows, rows, then rows 0+1 into 1 and 2+3
+// into 3, then rows 0-1 into 3 (row_bcast); lane 63 ends with the result,
+// which readlane hands to every lane.  The order of the combinations depends
+// only on lane positions, so a floating-point sum is deterministic.  All 64
+// lanes must be active.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ uint32_t dpp_move(uint32_t identity, uint32_t v) {
+  // lanes of rows outside ROW_MASK, or without a source lane, get identity
+  return (uint32_t)__builtin_amdgcn_update_dpp((int)identity, (int)v, CTRL, ROW_MASK, 0xF, false);
 }
 
-// Sum over the 64 lanes by a fixed butterfly (every lane gets the result;
-// the order of additions depends only on lane positions).
+template <class Op>
+__device__ __forceinline__ uint32_t wave_reduce_bits(uint32_t v, uint32_t identity, Op op) {
+  v = op(v, dpp_move<0xB1, 0xF>(identity, v));   // quad_perm [1,0,3,2]
+  v = op(v, dpp_move<0x4E, 0xF>(identity, v));   // quad_perm [2,3,0,1]
+  v = op(v, dpp_move<0x141, 0xF>(identity, v));  // row_half_mirror
+  v = op(v, dpp_move<0x140, 0xF>(identity, v));  // row_mirror
+  v = op(v, dpp_move<0x142, 0xA>(identity, v));  // row_bcast:15 into rows 1, 3
+  v = op(v, dpp_move<0x143, 0xC>(identity, v));  // row_bcast:31 into rows 2, 3
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+}
+
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
+  return wave_reduce_bits(v, 0u, [](uint32_t a, uint32_t b) { return a > b ? a : b; });
+}
+
+__device__ __forceinline__ float wave_max_f(float v) {
+  return __uint_as_float(wave_reduce_bits(__float_as_uint(v), 0xFF800000u, [](uint32_t a, uint32_t b) {
+    return __float_as_uint(fmaxf(__uint_as_float(a), __uint_as_float(b)));
+  }));
+}
+
+__device__ __forceinline__ float wave_min_f(float v) {
+  return __uint_as_float(wave_reduce_bits(__float_as_uint(v), 0x7F800000u, [](uint32_t a, uint32_t b) {
+    return __float_as_uint(fminf(__uint_as_float(a), __uint_as_float(b)));
+  }));
+}
+
+// Maximum 64-bit key: the high words first, then the low words of the lanes
+// that hold the maximal high word.
+__device__ __forceinline__ uint64_t wave_max_u64(uint64_t v) {
+  const uint32_t hi = wave_max_u32((uint32_t)(v >> 32));
+  const uint32_t lo = wave_max_u32((uint32_t)(v >> 32) == hi ? (uint32_t)v : 0u);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// Sum over the 64 lanes in a fixed order; every lane gets the same value.
 __device__ __forceinline__ float wave_sum(float v) {
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) v += __shfl_xor(v, off, kWave);
-  return v;
+  return __uint_as_float(wave_reduce_bits(__float_as_uint(v), 0u, [](uint32_t a, uint32_t b) {
+    return __float_as_uint(__uint_as_float(a) + __uint_as_float(b));
+  }));
 }
 
 // Order LDS traffic between lanes of one wave (no cross-wave barrier).

@@ -93,6 +93,31 @@ def test_c5_subset_parity(pockets):
     assert rep.ok(), rep.summary()
 
 
+def test_full_c2_batch_in_bench_configuration(pockets):
+    """The C2 batch at full size (10,000 ligands x 256 orientations x 256
+    steps) under the launch bench.py times (4 waves per block, claim cap 32):
+    items sampled across the cost-sorted queue are replayed by the reference
+    one by one, and every ligand's winner is the best of its 256 orientation
+    scores with the lowest index on ties."""
+    p, h = pockets(2)
+    ligs = synth.ligands(2)
+    assert ligs.n_ligands == 10_000
+    orient = synth.orientations(2)
+    dock.dock_set_launch(h, 4, 0, 32)
+    res = _run(pockets, 2, ligs, orient, 256)[1]
+    assert (res["status"] == 0).all()
+    sc = res["all_scores"]
+    best = sc.max(axis=1)
+    assert np.array_equal(res["best_score"], best)
+    assert np.array_equal(res["best_orient"], np.argmax(sc == best[:, None], axis=1))
+    rng = np.random.default_rng(11)
+    sample = rng.choice(ligs.n_ligands, 16, replace=False)
+    rep = check_batch(p, ligs, orient, 256, res, ligands=sample,
+                      orients=rng.choice(256, 3, replace=False))
+    print(rep.summary())
+    assert rep.ok(), rep.summary()
+
+
 def test_determinism_and_order_independence(pockets):
     ligs = synth.ligands(2, count=300, first=1000)
     orient = synth.orientations(2, 64)
@@ -115,7 +140,7 @@ def test_edge_cases(pockets):
                     move_offset=np.zeros(1, np.int32), move_atoms=np.zeros(0, np.int16))
     ligs = synth.Ligands.from_parts([lig, no_rot, one_atom, lig])
     orient = synth.orientations(1, 3)
-    for S in (1, 2, 63, 64, 65, 200):
+    for S in (1, 2, 63, 64, 65, 200, dock.DOCK_MAX_STEPS):
         res = dock.dock_batch(h, ligs, orient, S, want_all=True)
         rep = check_batch(p, ligs, orient, S, res)
         assert rep.ok(), (S, rep.summary())
