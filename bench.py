@@ -264,7 +264,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--bump", choices=("pruned", "direct"), default="pruned",
                     help="pruned: test only pairs that can clash; direct: every pair")
-    ap.add_argument("--waves", type=int, default=4, help="waves per block of the sweep")
+    ap.add_argument("--waves", type=int, default=0,
+                    help="waves per block of the sweep (0: the most resident waves)")
     ap.add_argument("--claim", type=int, default=32,
                     help="most items a wave takes per work-queue atomic")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-proposal comparison")

@@ -188,7 +188,8 @@ int dock_last_sweep_work(dock_pocket *p, uint64_t *kept_pairs, uint64_t *atom_an
 
 /* Launch mapping of the sweep kernel for calls on this handle (the knobs the
  * autotuner turns): waves_per_block in {1, 2, 4}, each wave working on its
- * own (ligand, orientation) items; blocks_per_cu >= 0 caps resident blocks
+ * own (ligand, orientation) items, or 0 (the default) for the block size that
+ * keeps the most waves resident per compute unit at this batch's sizes; blocks_per_cu >= 0 caps resident blocks
  * per compute unit (0: occupancy limit); items_per_claim in [1, 64] caps how
  * many consecutive items a wave takes from the work queue per atomic (a claim
  * is a share of the items left, so it shrinks to 1 towards the end).

@@ -39,7 +39,7 @@ struct dock_pocket {
   hipEvent_t ev_sweep[3] = {nullptr, nullptr, nullptr};  // sweep start/end, counter copied
   bool timed = false;
   unsigned long long *h_work = nullptr;  // pinned copy of the sweep's two work counters
-  LaunchPlan plan{4, 0, 32};
+  LaunchPlan plan{0, 0, 32};
   // last captured launch sequence of dock_batch_async (DOCK_FLAG_GRAPH)
   std::vector<unsigned char> graph_key;
   hipGraph_t graph = nullptr;
@@ -418,8 +418,8 @@ int dock_set_launch(dock_pocket *p, int waves_per_block, int blocks_per_cu,
                     int items_per_claim) {
   g_last_error.clear();
   if (!p) return fail(DOCK_E_INVAL, "NULL pocket");
-  if (waves_per_block != 1 && waves_per_block != 2 && waves_per_block != 4)
-    return fail(DOCK_E_INVAL, "waves_per_block must be 1, 2 or 4");
+  if (waves_per_block != 0 && waves_per_block != 1 && waves_per_block != 2 && waves_per_block != 4)
+    return fail(DOCK_E_INVAL, "waves_per_block must be 0 (automatic), 1, 2 or 4");
   if (blocks_per_cu < 0) return fail(DOCK_E_INVAL, "blocks_per_cu must be >= 0");
   if (items_per_claim < 1 || items_per_claim > 64)
     return fail(DOCK_E_INVAL, "items_per_claim must be in [1, 64]");

@@ -68,7 +68,7 @@ struct FinalOut {
 };
 
 struct LaunchPlan {
-  int waves_per_block;  // 1, 2 or 4
+  int waves_per_block;  // 1, 2 or 4; 0: the one with the most resident waves
   int blocks_per_cu;    // 0 = as many as occupancy allows
   int items_per_claim;  // 1 .. 64
 };

@@ -84,7 +84,7 @@ __device__ __forceinline__ void save_pose(const LearnedArgs &A, const WaveLds &W
 __global__ void __launch_bounds__(kWave) learned_begin_kernel(LearnedArgs A) {
   extern __shared__ float4 dyn_lds[];
   const int lane = threadIdx.x;
-  const WaveLds W((char *)dyn_lds, A.nmax, false);
+  const WaveLds W((char *)dyn_lds, A.nmax, false, 4);
   for (int item = blockIdx.x; item < A.sw.n_items; item += gridDim.x) {
     const ItemInfo I = item_info(A, item);
     if (A.sw.status[I.l] != 0) continue;
@@ -103,7 +103,7 @@ __global__ void __launch_bounds__(kWave) learned_begin_kernel(LearnedArgs A) {
 __global__ void __launch_bounds__(kWave) learned_step_kernel(LearnedArgs A, int step) {
   extern __shared__ float4 dyn_lds[];
   const int lane = threadIdx.x;
-  const WaveLds W((char *)dyn_lds, A.nmax, false);
+  const WaveLds W((char *)dyn_lds, A.nmax, false, 4);
   const GridView G = A.sw.grid;
   const GridScaled GS = grid_scaled(G);
   const __amdgpu_buffer_rsrc_t grsrc = grid_rsrc(G);
@@ -192,14 +192,14 @@ static unsigned grid_for(int n_items, int n_cu) {
 hipError_t enqueue_learned_begin(const LearnedArgs &A, int n_cu, hipStream_t st) {
   if (A.sw.n_items <= 0) return hipSuccess;
   hipLaunchKernelGGL(learned_begin_kernel, dim3(grid_for(A.sw.n_items, n_cu)), dim3(kWave),
-                     wave_lds_bytes(A.nmax, false), st, A);
+                     wave_lds_bytes(A.nmax, false, 4), st, A);
   return hipGetLastError();
 }
 
 hipError_t enqueue_learned_step(const LearnedArgs &A, int step, int n_cu, hipStream_t st) {
   if (A.sw.n_items <= 0) return hipSuccess;
   hipLaunchKernelGGL(learned_step_kernel, dim3(grid_for(A.sw.n_items, n_cu)), dim3(kWave),
-                     wave_lds_bytes(A.nmax, false), st, A, step);
+                     wave_lds_bytes(A.nmax, false, 4), st, A, step);
   return hipGetLastError();
 }
 

@@ -27,61 +27,65 @@ namespace dock {
 
 constexpr int kPairCap = 128;  // LDS pair-list entries per wave
 
-// 1: candidate pairs are enumerated with the static atoms on the lanes and
-// the moving atoms broadcast in turn; 0: over the flattened (moving, static)
-// index.  Same kept pairs either way.
-#ifndef DOCK_PAIR_ILOOP
-#define DOCK_PAIR_ILOOP 1
-#endif
+// Most compacted tiles scored in one pass for a group of TG tiles: two for
+// groups of up to 4 tiles (fewer live registers, more waves resident), all of
+// them for wider groups (measured on gfx950; results are the same either way).
+template <int TG>
+constexpr int kMaxScoreTiles = TG <= 4 ? (TG < 2 ? TG : 2) : TG;
 
 __host__ __device__ inline int wave_head_bytes(int nmax) {
-  // X, C (float4), rho (float), Q, M (int16), mov (uint8)
-  const int b = nmax * 16 * 2 + nmax * 4 + nmax * 2 * 2 + nmax;
+  // X, C (float4), Q, M (int16), mov (uint8)
+  const int b = nmax * 16 * 2 + nmax * 2 * 2 + nmax;
   return (b + 15) / 16 * 16;
 }
 
 constexpr int kMaskWords = 128;   // invalid-angle bitmask of up to 4096 steps
-constexpr int kBasisBytes = kWave * 48;  // rotation bases of 64 atoms, 3 float4 each
-constexpr int kCompactCap = 512;  // compacted steps of one tile group (TG <= 8)
+constexpr int kBasisFloats = 9;   // voxel-space rotation basis of one atom
+constexpr int kBasisBytes = kWave * kBasisFloats * 4;  // 64 atoms, component-major
 
 // Scratch region of a wave: the kept-pair list during the bump test, then
 // (when the bases are staged in LDS) the moving atoms' rotation bases and the
-// compacted valid angles while scoring.
-__host__ __device__ constexpr int wave_scratch_bytes(bool lds_basis) {
-  return (lds_basis ? kBasisBytes : 0) + kCompactCap * 2 > kPairCap * 4
-             ? (lds_basis ? kBasisBytes : 0) + kCompactCap * 2
+// compacted valid angles of a group of tg tiles while scoring.
+__host__ __device__ constexpr int wave_scratch_bytes(bool lds_basis, int tg) {
+  return (lds_basis ? kBasisBytes : 0) + tg * kWave * 2 > kPairCap * 4
+             ? (lds_basis ? kBasisBytes : 0) + tg * kWave * 2
              : kPairCap * 4;
 }
 
-__host__ __device__ inline int wave_lds_bytes(int nmax, bool lds_basis) {
-  return wave_head_bytes(nmax) + wave_scratch_bytes(lds_basis) + kMaskWords * 4;
+__host__ __device__ inline int wave_lds_bytes(int nmax, bool lds_basis, int tg) {
+  return wave_head_bytes(nmax) + wave_scratch_bytes(lds_basis, tg) + kMaskWords * 4;
 }
 
 struct WaveLds {
   float4 *X;     // pose: x, y, z, voxel value
   float4 *C;     // cylindrical coordinates about the current axis: r, z
-  float *rho;    // |r|
   int16_t *Q;    // static cross set of the rotamer
   int16_t *M;    // moving set of the rotamer
   uint8_t *mov;  // moving flags
   int *PI;       // kept pairs: i << 16 | j
-  float4 *B;     // rotation bases of 64 moving atoms (aliases PI, used after the bump test)
+  float *B;      // rotation bases of 64 moving atoms, component c of atom t at
+                 // B[64 c + t] (aliases PI, used after the bump test)
   int16_t *CK;   // compacted valid angle steps (after B)
   uint32_t *BM;  // bit k set: angle step k bumps
-  __device__ WaveLds(char *base, int nmax, bool lds_basis) {
+  __device__ WaveLds(char *base, int nmax, bool lds_basis, int tg) {
     X = (float4 *)base;
     C = X + nmax;
-    rho = (float *)(C + nmax);
-    Q = (int16_t *)(rho + nmax);
+    Q = (int16_t *)(C + nmax);
     M = Q + nmax;
     mov = (uint8_t *)(M + nmax);
     char *scr = base + wave_head_bytes(nmax);
     PI = (int *)scr;
-    B = (float4 *)scr;
+    B = (float *)scr;
     CK = (int16_t *)(scr + (lds_basis ? kBasisBytes : 0));
-    BM = (uint32_t *)(scr + wave_scratch_bytes(lds_basis));
+    BM = (uint32_t *)(scr + wave_scratch_bytes(lds_basis, tg));
   }
 };
+
+// |r| of an atom's cylindrical coordinates (the same expression wherever it
+// is needed, so every use sees the same bits).
+__device__ __forceinline__ float cyl_radius(const float4 &c) {
+  return sqrtf(fmaf(c.x, c.x, fmaf(c.y, c.y, c.z * c.z)));
+}
 
 struct RotState {
   int m, q;
@@ -157,7 +161,6 @@ __device__ __forceinline__ RotState rotamer_setup(const WaveLds &W, int n, const
       st = !moving && i != T.ra && i != T.rb;
       const Cyl c = cyl_of(xi, R.xa, R.u);
       W.C[i] = make_float4(c.rx, c.ry, c.rz, c.z);
-      W.rho[i] = sqrtf(fmaf(c.rx, c.rx, fmaf(c.ry, c.ry, c.rz * c.rz)));
     }
     const uint64_t mask = __ballot(st);
     if (st) W.Q[q + __popcll(mask & below)] = (int16_t)i;
@@ -263,7 +266,6 @@ __device__ __forceinline__ int rotamer_bump_mask(const WaveLds &W, const RotStat
       wave_lds_sync();
     }
   };
-#if DOCK_PAIR_ILOOP
   // lanes hold 64 static atoms; 64 moving atoms sit in registers, one per
   // lane, and are broadcast in turn
   for (int ib = 0; ib < R.m; ib += kWave) {
@@ -272,13 +274,15 @@ __device__ __forceinline__ int rotamer_bump_mask(const WaveLds &W, const RotStat
     float zl = 0.f, rl = 0.f;
     if (lane < mc) {
       il = W.M[ib + lane];
-      zl = W.C[il].w;
-      rl = W.rho[il];
+      const float4 ci = W.C[il];
+      zl = ci.w;
+      rl = cyl_radius(ci);
     }
     for (int jb = 0; jb < R.q; jb += kWave) {
       const bool jin = jb + lane < R.q;
       const int j = jin ? W.Q[jb + lane] : 0;
-      const float zj = W.C[j].w, rj = W.rho[j];
+      const float4 cj = W.C[j];
+      const float zj = cj.w, rj = cyl_radius(cj);
       for (int t = 0; t < mc; ++t) {
         const float dz = lane_bcast(zl, t) - zj;
         const float dr = lane_bcast(rl, t) - rj;
@@ -287,33 +291,6 @@ __device__ __forceinline__ int rotamer_bump_mask(const WaveLds &W, const RotStat
       }
     }
   }
-#else
-  const int total = R.m * R.q;
-  const float inv_q = R.q > 0 ? 1.0f / (float)R.q : 0.0f;
-  for (int base = 0; base < total; base += kWave) {
-    const int pidx = base + lane;
-    bool act = false;
-    int packed = 0;
-    if (pidx < total) {
-      int ii = (int)(((float)pidx + 0.5f) * inv_q);
-      int jj = pidx - ii * R.q;
-      if (jj < 0) {
-        --ii;
-        jj += R.q;
-      }
-      if (jj >= R.q) {
-        ++ii;
-        jj -= R.q;
-      }
-      const int i = W.M[ii], j = W.Q[jj];
-      const float dz = W.C[i].w - W.C[j].w;
-      const float dr = W.rho[i] - W.rho[j];
-      act = fmaf(dr, dr, dz * dz) < thr;
-      packed = (i << 16) | j;
-    }
-    push(act, packed);
-  }
-#endif
   wave_lds_sync();
   mark_kept_pairs(W, R, r2, np, S, lane);
   wave_lds_sync();
@@ -372,19 +349,20 @@ __device__ __forceinline__ void rotamer_scores(const WaveLds &W, const RotState 
     }
     const int cnt = min(kWave, R.m - c0);
     if constexpr (LB) {
-      W.B[3 * lane] = make_float4(b0, b1, b2, b3);
-      W.B[3 * lane + 1] = make_float4(b4, b5, b6, b7);
-      W.B[3 * lane + 2] = make_float4(b8, 0.f, 0.f, 0.f);
+      float *B = W.B + lane;
+      B[0 * kWave] = b0, B[1 * kWave] = b1, B[2 * kWave] = b2;
+      B[3 * kWave] = b3, B[4 * kWave] = b4, B[5 * kWave] = b5;
+      B[6 * kWave] = b6, B[7 * kWave] = b7, B[8 * kWave] = b8;
       wave_lds_sync();
     }
     // gathers of atom tt of this chunk at the lane's TG angles
     auto gather = [&](int tt, float(&v)[TG]) {
       float px, py, pz, ex, ey, ez, fx, fy, fz;
       if constexpr (LB) {
-        const float4 q0 = W.B[3 * tt], q1 = W.B[3 * tt + 1];
-        px = q0.x, py = q0.y, pz = q0.z, ex = q0.w;
-        ey = q1.x, ez = q1.y, fx = q1.z, fy = q1.w;
-        fz = W.B[3 * tt + 2].x;
+        const float *B = W.B + tt;  // wave-uniform address: broadcast reads
+        px = B[0 * kWave], py = B[1 * kWave], pz = B[2 * kWave];
+        ex = B[3 * kWave], ey = B[4 * kWave], ez = B[5 * kWave];
+        fx = B[6 * kWave], fy = B[7 * kWave], fz = B[8 * kWave];
       } else {
         px = lane_bcast(b0, tt), py = lane_bcast(b1, tt), pz = lane_bcast(b2, tt);
         ex = lane_bcast(b3, tt), ey = lane_bcast(b4, tt), ez = lane_bcast(b5, tt);
@@ -434,12 +412,12 @@ __device__ __forceinline__ uint64_t score_compacted(const WaveLds &W, const RotS
                                                     const GridView &G, const GridScaled &GS,
                                                     __amdgpu_buffer_rsrc_t grsrc,
                                                     const float2 *cs_table, int nvalid,
-                                                    float s0, int lane) {
+                                                    float s0, int lane, int tile0) {
   float cc[TC], ss[TC], score[TC];
   int kk[TC];
 #pragma unroll
   for (int t = 0; t < TC; ++t) {
-    const int j = t * kWave + lane;
+    const int j = (tile0 + t) * kWave + lane;
     kk[t] = j < nvalid ? W.CK[j] : -1;
     const float2 cs = cs_table[kk[t] > 0 ? kk[t] : 0];
     cc[t] = cs.x;
@@ -479,18 +457,25 @@ __device__ __forceinline__ uint64_t best_valid_step(const WaveLds &W, const RotS
   uint64_t best = 0ull;
   const int tc = (nvalid + kWave - 1) / kWave;
   // one instantiation per tile count so the slot arrays stay in registers
+  constexpr int MT = kMaxScoreTiles<TG>;
+  for (int t0c = 0; t0c < tc; t0c += MT) {
+    const int left = tc - t0c;
+    uint64_t b = 0ull;
 #define DOCK_SCORE_TC(c)                                                                  \
-  if constexpr (TG >= c)                                                                  \
-    if (tc == c) best = score_compacted<c, LB>(W, R, G, GS, grsrc, cs_table, nvalid, s0, lane);
-  DOCK_SCORE_TC(1)
-  DOCK_SCORE_TC(2)
-  DOCK_SCORE_TC(3)
-  DOCK_SCORE_TC(4)
-  DOCK_SCORE_TC(5)
-  DOCK_SCORE_TC(6)
-  DOCK_SCORE_TC(7)
-  DOCK_SCORE_TC(8)
+    if constexpr (MT >= c)                                                                \
+      if (left == c || (c == MT && left > c))                                             \
+        b = score_compacted<c, LB>(W, R, G, GS, grsrc, cs_table, nvalid, s0, lane, t0c);
+    DOCK_SCORE_TC(1)
+    DOCK_SCORE_TC(2)
+    DOCK_SCORE_TC(3)
+    DOCK_SCORE_TC(4)
+    DOCK_SCORE_TC(5)
+    DOCK_SCORE_TC(6)
+    DOCK_SCORE_TC(7)
+    DOCK_SCORE_TC(8)
 #undef DOCK_SCORE_TC
+    best = b > best ? b : best;
+  }
   wave_lds_sync();
   return best;
 }
@@ -523,7 +508,7 @@ __device__ __forceinline__ float rotamer_feature(const WaveLds &W, const RotStat
     sx += ci.x;
     sy += ci.y;
     sz += ci.z;
-    rmax = fmaxf(rmax, W.rho[i]);
+    rmax = fmaxf(rmax, cyl_radius(W.C[i]));
     zmin = fminf(zmin, ci.w);
     zmax = fmaxf(zmax, ci.w);
   }

@@ -368,8 +368,9 @@ static hipError_t launch_sweep_t(const SweepArgs &A, int blocks_per_cu, int n_cu
 hipError_t enqueue_sweep(const SweepArgs &A, int maxn, const LaunchPlan &plan, int n_cu,
                          hipStream_t st) {
   if (A.n_items <= 0) return hipSuccess;
+  const int waves = plan.waves_per_block == 0 ? 4 : plan.waves_per_block;  // 0: automatic
 #define DOCK_SWEEP_CASE(N, W)                                                       \
-  if (maxn <= N && plan.waves_per_block == W)                                         \
+  if (maxn <= N && waves == W)                                                        \
     return launch_sweep_t<N, W>(A, plan.blocks_per_cu, n_cu, st);
   DOCK_SWEEP_CASE(64, 1)
   DOCK_SWEEP_CASE(64, 2)

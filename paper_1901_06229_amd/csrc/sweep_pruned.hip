@@ -28,14 +28,17 @@
 namespace dock {
 
 // LB: the moving atoms' rotation bases are staged in LDS for the scoring
-// loop (chosen at launch when the extra LDS costs no occupancy).
-template <int WAVES, int TG, bool LB>
+// loop (chosen at launch when the extra LDS costs no occupancy).  EMIT: the
+// profile-emission form (every angle scored, features and landscapes
+// written), a separate instantiation so the plain sweep does not carry its
+// registers.
+template <int WAVES, int TG, bool LB, bool EMIT>
 __global__ void __launch_bounds__(WAVES *kWave)
     sweep_pruned_kernel(SweepArgs A, int nmax) {
   extern __shared__ float4 dyn_lds[];
   const int wv = threadIdx.x / kWave;
   const int lane = threadIdx.x % kWave;
-  const WaveLds W((char *)dyn_lds + (size_t)wv * wave_lds_bytes(nmax, LB), nmax, LB);
+  const WaveLds W((char *)dyn_lds + (size_t)wv * wave_lds_bytes(nmax, LB, TG), nmax, LB, TG);
   const GridView G = A.grid;
   const GridScaled GS = grid_scaled(G);
   const __amdgpu_buffer_rsrc_t grsrc = grid_rsrc(G);
@@ -43,7 +46,7 @@ __global__ void __launch_bounds__(WAVES *kWave)
   const int T = (S + kWave - 1) / kWave;
   const float r2 = A.r2;
   const float thr = r2 + kPruneMargin;
-  const bool emit = A.emit_x != nullptr;  // profile emission: S == 256, TG == 4
+  constexpr bool emit = EMIT;  // profile emission: S == 256, TG == 4
   uint64_t kept_pairs = 0, evals = 0;  // work counters of this wave
 
   WorkQueue queue(A.queue, A.n_items, A.claim, (int)gridDim.x * WAVES);
@@ -72,7 +75,8 @@ __global__ void __launch_bounds__(WAVES *kWave)
         const int words_next = more ? topo_words_load(A.lig, r0 + (r + 1 == R ? 0 : r + 1), lane) : 0;
         const RotState RS = rotamer_setup(W, n, topo, A.lig.move_atoms, lane);
         const float s0 = rotamer_s0(W, RS, lane);
-        if (emit) A.emit_x[(kbase + step) * 64 + lane] = f32_to_bf16(rotamer_feature(W, RS, G, lane));
+        if constexpr (emit)
+          A.emit_x[(kbase + step) * 64 + lane] = f32_to_bf16(rotamer_feature(W, RS, G, lane));
 
         // invalid steps of the rotamer, for all S steps at once
         kept_pairs += (uint64_t)rotamer_bump_mask(W, RS, r2, thr, S, lane);
@@ -83,42 +87,43 @@ __global__ void __launch_bounds__(WAVES *kWave)
           uint64_t vm[TG];  // wave-uniform valid masks of the group's tiles
 #pragma unroll
           for (int t = 0; t < TG; ++t) vm[t] = tile_valid_mask(W, t0 + t, S);
-          if (!emit) {
+          if constexpr (!emit) {
             int nvalid;
             const uint64_t key =
                 best_valid_step<TG, LB>(W, RS, G, GS, grsrc, A.cs, vm, t0, s0, lane, nvalid);
             best = key > best ? key : best;
             evals += (uint64_t)RS.m * (uint64_t)nvalid;
-            continue;
-          }
-          evals += (uint64_t)RS.m * (uint64_t)(TG * kWave);
-          // profile emission scores every step, valid or not
-          float cc[TG], ss[TG], score[TG];
+          } else {
+            // profile emission scores every step, valid or not
+            evals += (uint64_t)RS.m * (uint64_t)(TG * kWave);
+            float cc[TG], ss[TG], score[TG];
 #pragma unroll
-          for (int t = 0; t < TG; ++t) {
-            const int k = (t0 + t) * kWave + lane;
-            const float2 cs = A.cs[(t0 + t < T && k < S) ? k : 0];
-            cc[t] = cs.x;
-            ss[t] = cs.y;
-          }
-          rotamer_scores<TG, LB>(W, RS, G, GS, grsrc, cc, ss, score, lane);
-          if (t0 == 0 && lane == 0) score[0] = s0;
+            for (int t = 0; t < TG; ++t) {
+              const int k = (t0 + t) * kWave + lane;
+              const float2 cs = A.cs[(t0 + t < T && k < S) ? k : 0];
+              cc[t] = cs.x;
+              ss[t] = cs.y;
+            }
+            rotamer_scores<TG, LB>(W, RS, G, GS, grsrc, cc, ss, score, lane);
+            if (t0 == 0 && lane == 0) score[0] = s0;
 #pragma unroll
-          for (int t = 0; t < TG; ++t) {
-            const int k = (t0 + t) * kWave + lane;
-            const uint64_t key = (vm[t] >> lane) & 1ull ? best_key(score[t], (uint32_t)k) : 0ull;
-            best = key > best ? key : best;
-          }
-          float smax = score[0];
+            for (int t = 0; t < TG; ++t) {
+              const int k = (t0 + t) * kWave + lane;
+              const uint64_t key = (vm[t] >> lane) & 1ull ? best_key(score[t], (uint32_t)k) : 0ull;
+              best = key > best ? key : best;
+            }
+            float smax = score[0];
 #pragma unroll
-          for (int t = 1; t < TG; ++t) smax = fmaxf(smax, score[t]);
-          smax = wave_max_f(smax);
-          uint16_t *trow = A.emit_t + (kbase + step) * 256;
+            for (int t = 1; t < TG; ++t) smax = fmaxf(smax, score[t]);
+            smax = wave_max_f(smax);
+            uint16_t *trow = A.emit_t + (kbase + step) * 256;
 #pragma unroll
-          for (int t = 0; t < TG; ++t) {
-            trow[(t0 + t) * kWave + lane] = f32_to_bf16(fmaxf(score[t] - smax, -4.0f));
-            if (lane < 2)
-              A.emit_mask[(kbase + step) * 8 + (t0 + t) * 2 + lane] = (uint32_t)(vm[t] >> (32 * lane));
+            for (int t = 0; t < TG; ++t) {
+              trow[(t0 + t) * kWave + lane] = f32_to_bf16(fmaxf(score[t] - smax, -4.0f));
+              if (lane < 2)
+                A.emit_mask[(kbase + step) * 8 + (t0 + t) * 2 + lane] =
+                    (uint32_t)(vm[t] >> (32 * lane));
+            }
           }
         }
         best = wave_max_u64(best);
@@ -149,67 +154,96 @@ __global__ void __launch_bounds__(WAVES *kWave)
 }
 
 // Resident blocks per CU of one instantiation (0: its LDS exceeds a block's).
-template <int WAVES, int TG, bool LB>
+template <int WAVES, int TG, bool LB, bool EMIT = false>
 static hipError_t pruned_occupancy(int nmax, int blocks_per_cu, int *bpc) {
   *bpc = 0;
-  const size_t shmem = (size_t)WAVES * wave_lds_bytes(nmax, LB);
+  const size_t shmem = (size_t)WAVES * wave_lds_bytes(nmax, LB, TG);
   if (shmem > 65536) return hipSuccess;
   int occ = 0;
   hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-      &occ, sweep_pruned_kernel<WAVES, TG, LB>, WAVES * kWave, shmem);
+      &occ, sweep_pruned_kernel<WAVES, TG, LB, EMIT>, WAVES * kWave, shmem);
   if (e != hipSuccess) return e;
   if (occ < 1) occ = 1;
   *bpc = blocks_per_cu > 0 && blocks_per_cu < occ ? blocks_per_cu : occ;
   return hipSuccess;
 }
 
-template <int WAVES, int TG, bool LB>
+template <int WAVES, int TG, bool LB, bool EMIT = false>
 static hipError_t launch_pruned_lb(const SweepArgs &A, int nmax, int bpc, int n_cu,
                                    hipStream_t st) {
-  const size_t shmem = (size_t)WAVES * wave_lds_bytes(nmax, LB);
+  const size_t shmem = (size_t)WAVES * wave_lds_bytes(nmax, LB, TG);
   const int64_t need = (A.n_items + WAVES - 1) / WAVES;
   int64_t grid = (int64_t)(bpc > 0 ? bpc : 1) * n_cu;
   if (grid > need) grid = need;
   if (grid < 1) grid = 1;
-  hipLaunchKernelGGL((sweep_pruned_kernel<WAVES, TG, LB>), dim3((unsigned)grid),
+  hipLaunchKernelGGL((sweep_pruned_kernel<WAVES, TG, LB, EMIT>), dim3((unsigned)grid),
                      dim3(WAVES * kWave), shmem, st, A, nmax);
   return hipGetLastError();
 }
 
-// The LDS-staged bases when they keep the occupancy of the register form.
+// Occupancy of WAVES-wave blocks: the LDS-staged bases when they keep the
+// occupancy of the register form.
 template <int WAVES, int TG>
-static hipError_t launch_pruned_t(const SweepArgs &A, int nmax, int blocks_per_cu, int n_cu,
-                                  hipStream_t st) {
-  int occ_reg = 0, occ_lds = 0;
-  hipError_t e = pruned_occupancy<WAVES, TG, false>(nmax, blocks_per_cu, &occ_reg);
-  if (e == hipSuccess) e = pruned_occupancy<WAVES, TG, true>(nmax, blocks_per_cu, &occ_lds);
-  if (e != hipSuccess) return e;
-  if (occ_reg < 1 && occ_lds < 1) return hipErrorInvalidValue;
-  if (occ_lds >= occ_reg) return launch_pruned_lb<WAVES, TG, true>(A, nmax, occ_lds, n_cu, st);
-  return launch_pruned_lb<WAVES, TG, false>(A, nmax, occ_reg, n_cu, st);
-}
+struct PrunedChoice {
+  int bpc = 0;
+  bool lds_basis = false;
+  hipError_t query(int nmax, int blocks_per_cu) {
+    int occ_reg = 0, occ_lds = 0;
+    hipError_t e = pruned_occupancy<WAVES, TG, false>(nmax, blocks_per_cu, &occ_reg);
+    if (e == hipSuccess) e = pruned_occupancy<WAVES, TG, true>(nmax, blocks_per_cu, &occ_lds);
+    lds_basis = occ_lds >= occ_reg && occ_lds > 0;
+    bpc = lds_basis ? occ_lds : occ_reg;
+    return e;
+  }
+  int waves() const { return bpc * WAVES; }
+  hipError_t launch(const SweepArgs &A, int nmax, int n_cu, hipStream_t st) const {
+    if (bpc < 1) return hipErrorInvalidValue;
+    return lds_basis ? launch_pruned_lb<WAVES, TG, true>(A, nmax, bpc, n_cu, st)
+                     : launch_pruned_lb<WAVES, TG, false>(A, nmax, bpc, n_cu, st);
+  }
+};
 
-template <int WAVES>
-static hipError_t launch_pruned_w(const SweepArgs &A, int nmax, int blocks_per_cu, int n_cu,
-                                  hipStream_t st) {
-  const int T = (A.S + kWave - 1) / kWave;
-  if (T <= 1) return launch_pruned_t<WAVES, 1>(A, nmax, blocks_per_cu, n_cu, st);
-  if (T <= 2) return launch_pruned_t<WAVES, 2>(A, nmax, blocks_per_cu, n_cu, st);
-  if (T <= 4) return launch_pruned_t<WAVES, 4>(A, nmax, blocks_per_cu, n_cu, st);
-  if (T <= 6) return launch_pruned_t<WAVES, 6>(A, nmax, blocks_per_cu, n_cu, st);
-  return launch_pruned_t<WAVES, 8>(A, nmax, blocks_per_cu, n_cu, st);
+// waves_per_block 0: the block size with the most resident waves per CU
+// (larger blocks on ties).
+template <int TG>
+static hipError_t launch_pruned_tg(const SweepArgs &A, int nmax, const LaunchPlan &plan,
+                                   int n_cu, hipStream_t st) {
+  PrunedChoice<4, TG> c4;
+  PrunedChoice<2, TG> c2;
+  PrunedChoice<1, TG> c1;
+  const int w = plan.waves_per_block;
+  hipError_t e = hipSuccess;
+  if (w == 0 || w == 4) e = c4.query(nmax, plan.blocks_per_cu);
+  if (e == hipSuccess && (w == 0 || w == 2)) e = c2.query(nmax, plan.blocks_per_cu);
+  if (e == hipSuccess && (w == 0 || w == 1)) e = c1.query(nmax, plan.blocks_per_cu);
+  if (e != hipSuccess) return e;
+  if (w == 4) return c4.launch(A, nmax, n_cu, st);
+  if (w == 2) return c2.launch(A, nmax, n_cu, st);
+  if (w == 1) return c1.launch(A, nmax, n_cu, st);
+  if (w != 0) return hipErrorInvalidValue;
+  if (c4.waves() >= c2.waves() && c4.waves() >= c1.waves()) return c4.launch(A, nmax, n_cu, st);
+  if (c2.waves() >= c1.waves()) return c2.launch(A, nmax, n_cu, st);
+  return c1.launch(A, nmax, n_cu, st);
 }
 
 hipError_t enqueue_sweep_pruned(const SweepArgs &A, int max_atoms, const LaunchPlan &plan,
                                 int n_cu, hipStream_t st) {
   if (A.n_items <= 0) return hipSuccess;
   const int nmax = (max_atoms + 15) / 16 * 16;
-  switch (plan.waves_per_block) {
-    case 1: return launch_pruned_w<1>(A, nmax, plan.blocks_per_cu, n_cu, st);
-    case 2: return launch_pruned_w<2>(A, nmax, plan.blocks_per_cu, n_cu, st);
-    case 4: return launch_pruned_w<4>(A, nmax, plan.blocks_per_cu, n_cu, st);
-    default: return hipErrorInvalidValue;
+  const int T = (A.S + kWave - 1) / kWave;
+  if (A.emit_x) {  // profile emission: S == 256 (checked by the caller)
+    if (T != 4) return hipErrorInvalidValue;
+    int bpc = 0;
+    hipError_t e = pruned_occupancy<4, 4, false, true>(nmax, plan.blocks_per_cu, &bpc);
+    if (e != hipSuccess) return e;
+    if (bpc < 1) return hipErrorInvalidValue;
+    return launch_pruned_lb<4, 4, false, true>(A, nmax, bpc, n_cu, st);
   }
+  if (T <= 1) return launch_pruned_tg<1>(A, nmax, plan, n_cu, st);
+  if (T <= 2) return launch_pruned_tg<2>(A, nmax, plan, n_cu, st);
+  if (T <= 4) return launch_pruned_tg<4>(A, nmax, plan, n_cu, st);
+  if (T <= 6) return launch_pruned_tg<6>(A, nmax, plan, n_cu, st);
+  return launch_pruned_tg<8>(A, nmax, plan, n_cu, st);
 }
 
 }  // namespace dock
