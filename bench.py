@@ -25,8 +25,11 @@ sys.path.insert(0, ROOT)
 
 METRIC = "ligands/sec on 1 MI355X (plain vs learned proposal at ≤0.5% score loss)"
 
-# MI355X: 256 CUs x 64 lanes x 2.4 GHz, one FP32 VALU lane-operation per lane per clock
-VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+# MI355X FP32 vector rate: 256 CUs x 128 lanes x 2.4 GHz = 78.6 T lane-ops/s
+# (the 157.3 TFLOP/s spec figure, an FMA counted as one lane-op instead of two
+# flops).  Plain FP32 FMA/add chains reach about 51-55 T on the part under
+# load; clamp, conversion and integer multiply-add about 34-36 T.
+VALU_PEAK_TOPS = 256 * 128 * 2.4e9 / 1e12
 # Lane-operation counts (VALU instructions per lane) of the sweep's units,
 # taken from the loop bodies of the compiled gfx950 kernels:
 #   direct kernel, per angle: 8 per cross pair (3 sub, mul, 2 fma, cmp, or),
