@@ -188,9 +188,11 @@ def time_steps(h, d, od, S, out, prm, ws, stream, steps, warmup):
 
 
 def learned_comparison(n_eval=10_000, n_val=2_000, n_train=156_250, epochs=10, top_k=16,
-                       steps=5, proposal=None):
+                       steps=5, proposal=None, fine_steps=4096):
     """Plain vs learned proposal on the learned-proposal workload (64^3 pocket,
-    32-atom 4-rotamer ligands, 8 orientations, 256 steps), same inputs."""
+    32-atom 4-rotamer ligands, 8 orientations), same inputs, at S = 256 (one
+    step per prediction bin) and at S = fine_steps (fine_steps / 256 steps per
+    bin; same network)."""
     import torch
     from paper_1901_06229_amd import dock, learned, synth
     t0 = time.perf_counter()
@@ -205,56 +207,63 @@ def learned_comparison(n_eval=10_000, n_val=2_000, n_train=156_250, epochs=10, t
     dock.dock_load_proposal(h, net)
     orient = synth.orientations(learned.LEARN_CONFIG)
     stream = torch.cuda.Stream()
-    res = {}
+    batches = {}
     for name, first, count in (("val", n_eval, n_val), ("eval", 0, n_eval)):
         ligs = synth.ligands(learned.LIGAND_RECIPE, count=count, first=first,
                              seed=synth.config_seed(learned.LEARN_CONFIG), stream=synth.STREAM_EVAL)
-        d, od, out = device_batch(ligs, orient)
-        ws = torch.empty(dock.dock_workspace_size(count, d["total_rot"], 8, 256), dtype=torch.uint8,
-                         device="cuda")
-        res[name] = (ligs, d, od, out, ws)
-
-    def run(name, mode, margin, n_steps):
-        ligs, d, od, out, ws = res[name]
-        prm = dock.make_params(mode=mode, top_k=top_k, margin=margin, max_atoms=32, max_rot=4)
-        sec = time_steps(h, d, od, 256, out, prm, ws, stream, n_steps, 1)
-        return sec, out["best_score"].cpu().numpy().copy(), int(out["n_fallback"].sum().item())
+        batches[name] = (ligs,) + device_batch(ligs, orient)
 
     def loss(sp, sl):
         return float(np.mean((sp - sl) / np.maximum(np.abs(sp), 1.0)))
 
-    # threshold on the validation ligands: fastest margin with <= 0.5 % mean loss
-    _, sp_val, _ = run("val", dock.DOCK_MODE_PLAIN, 0.0, 1)
-    candidates = []
-    for tau in (-1.0, 0.02, 0.05, 0.1, 0.2, 0.4, 0.8, 3.0e38):
-        sec, sl, nfb = run("val", dock.DOCK_MODE_LEARNED, tau, 2)
-        candidates.append((tau, sec, loss(sp_val, sl), nfb / (n_val * 8 * 4)))
-        log(f"val tau {tau:g}: {sec * 1e3:.3f} ms, loss {candidates[-1][2]:.5f}, "
-            f"fallback {candidates[-1][3]:.3f}")
-    ok = [c for c in candidates if c[2] <= 0.005]
-    tau = min(ok, key=lambda c: c[1])[0] if ok else 3.0e38
-    sec_p, sp, _ = run("eval", dock.DOCK_MODE_PLAIN, 0.0, steps)
-    sec_l, sl, nfb = run("eval", dock.DOCK_MODE_LEARNED, tau, steps)
-    net0 = dock.Mlp(learned.init_params(12345))
-    dock.dock_load_proposal(h, net0)
-    _, sl0, _ = run("eval", dock.DOCK_MODE_LEARNED, -1.0, 1)
-    dock.dock_load_proposal(h, net)
-    _, sl_t, _ = run("eval", dock.DOCK_MODE_LEARNED, -1.0, 1)
+    def compare(S):
+        ws = {name: torch.empty(dock.dock_workspace_size(b[0].n_ligands, b[1]["total_rot"], 8, S),
+                                dtype=torch.uint8, device="cuda") for name, b in batches.items()}
+
+        def run(name, mode, margin, n_steps):
+            ligs, d, od, out = batches[name]
+            prm = dock.make_params(mode=mode, top_k=top_k, margin=margin, max_atoms=32, max_rot=4)
+            sec = time_steps(h, d, od, S, out, prm, ws[name], stream, n_steps, 1)
+            return sec, out["best_score"].cpu().numpy().copy(), int(out["n_fallback"].sum().item())
+
+        # threshold on the validation ligands: fastest margin with <= 0.5 % mean loss
+        _, sp_val, _ = run("val", dock.DOCK_MODE_PLAIN, 0.0, 1)
+        candidates = []
+        for tau in (-1.0, 0.02, 0.05, 0.1, 0.2, 0.4, 0.8, 3.0e38):
+            sec, sl, nfb = run("val", dock.DOCK_MODE_LEARNED, tau, 2)
+            candidates.append((tau, sec, loss(sp_val, sl), nfb / (n_val * 8 * 4)))
+            log(f"S {S} val tau {tau:g}: {sec * 1e3:.3f} ms, loss {candidates[-1][2]:.5f}, "
+                f"fallback {candidates[-1][3]:.3f}")
+        ok = [c for c in candidates if c[2] <= 0.005]
+        tau = min(ok, key=lambda c: c[1])[0] if ok else 3.0e38
+        sec_p, sp, _ = run("eval", dock.DOCK_MODE_PLAIN, 0.0, steps)
+        sec_l, sl, nfb = run("eval", dock.DOCK_MODE_LEARNED, tau, steps)
+        net0 = dock.Mlp(learned.init_params(12345))
+        dock.dock_load_proposal(h, net0)
+        _, sl0, _ = run("eval", dock.DOCK_MODE_LEARNED, -1.0, 1)
+        dock.dock_load_proposal(h, net)
+        _, sl_t, _ = run("eval", dock.DOCK_MODE_LEARNED, -1.0, 1)
+        return {
+            "workload": f"learned proposal: 64^3 pocket @0.5A, {n_eval} held-out ligands (32 atoms, "
+                        f"4 rotamers), 8 orientations, {S} steps ({S // 256} per prediction bin)",
+            "angle_steps": S,
+            "plain_ligands_per_s": round(n_eval / sec_p, 1),
+            "learned_ligands_per_s": round(n_eval / sec_l, 1),
+            "speedup": round(sec_p / sec_l, 3),
+            "top_k": top_k, "margin_tau": tau if tau < 1e30 else "inf (full fallback)",
+            "score_loss_mean": loss(sp, sl), "fallback_rate": nfb / (n_eval * 8 * 4),
+            "no_fallback_loss_trained": loss(sp, sl_t), "no_fallback_loss_untrained": loss(sp, sl0),
+            "validation": [{"tau": c[0] if c[0] < 1e30 else "inf", "ms": round(c[1] * 1e3, 3),
+                            "loss": round(c[2], 5), "fallback": round(c[3], 3)} for c in candidates],
+        }
+
+    res = compare(256)
+    if fine_steps:
+        res["fine_steps"] = compare(fine_steps)
     h.close()
-    return {
-        "workload": "learned proposal: 64^3 pocket @0.5A, 10000 held-out ligands (32 atoms, "
-                    "4 rotamers), 8 orientations, 256 steps",
-        "plain_ligands_per_s": round(n_eval / sec_p, 1),
-        "learned_ligands_per_s": round(n_eval / sec_l, 1),
-        "speedup": round(sec_p / sec_l, 3),
-        "top_k": top_k, "margin_tau": tau if tau < 1e30 else "inf (full fallback)",
-        "score_loss_mean": loss(sp, sl), "fallback_rate": nfb / (n_eval * 8 * 4),
-        "no_fallback_loss_trained": loss(sp, sl_t), "no_fallback_loss_untrained": loss(sp, sl0),
-        "validation": [{"tau": c[0] if c[0] < 1e30 else "inf", "ms": round(c[1] * 1e3, 3),
-                        "loss": round(c[2], 5), "fallback": round(c[3], 3)} for c in candidates],
-        "training": {k: v for k, v in hist.items() if k not in ("train_loss", "val_loss")}
-        | {"final_val_mse": hist.get("val_loss", [None])[-1], "seconds": round(t_train, 2)},
-    }
+    res["training"] = {k: v for k, v in hist.items() if k not in ("train_loss", "val_loss")} | {
+        "final_val_mse": hist.get("val_loss", [None])[-1], "seconds": round(t_train, 2)}
+    return res
 
 
 def main():

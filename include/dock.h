@@ -97,7 +97,8 @@ typedef struct {
   float r_bump;      /* bump radius (A), >= 0                                   */
   int32_t passes;    /* sweeps over all rotamers (paper: num_repetitions), >= 1 */
   int32_t mode;      /* DOCK_MODE_PLAIN or DOCK_MODE_LEARNED                    */
-  int32_t top_k;     /* learned mode: bins nominated per step (1..63)          */
+  int32_t top_k;     /* learned mode: bins nominated per step (1..63); every
+                        valid step of a nominated bin is scored              */
   float margin;      /* learned mode: fall back to the full sweep when the
                         predicted best minus the (top_k+1)-th is below this   */
   uint32_t flags;    /* DOCK_FLAG_*                                             */
@@ -253,8 +254,9 @@ int dock_mlp_adam(dock_mlp *m, float lr, float beta1, float beta2, float eps, vo
 
 /* Install a trained network as the pocket's learned proposal (device copy of
  * its current weights; the network may be freed afterwards).  Needed by
- * DOCK_MODE_LEARNED, which also requires angle_steps = 256 (one output bin
- * per angle step) and 1 <= top_k <= 63. */
+ * DOCK_MODE_LEARNED, which also requires angle_steps = 256 x 2^j (256 output
+ * bins, bin b holding the S/256 steps of angles [2 pi b/256, 2 pi (b+1)/256)),
+ * 1 <= top_k <= 63 and top_k x S/256 + 1 <= 512; otherwise DOCK_E_LIMIT. */
 int dock_load_proposal(dock_pocket *p, dock_mlp *m);
 
 /* Training data for the learned proposal: run the plain sweep (S = 256) on a

@@ -49,7 +49,7 @@ struct dock_pocket {
   float *prop_w = nullptr;
   // learned-mode buffers, grown on demand
   int64_t lw_items = 0, lw_rows = 0;
-  int lw_nmax = 0;
+  int lw_nmax = 0, lw_tiles = 0;
   float4 *lw_pose = nullptr;
   uint16_t *lw_feat = nullptr;
   uint64_t *lw_valid = nullptr;
@@ -223,12 +223,13 @@ void free_learned(dock_pocket *p) {
   for (auto &z : p->lw_z) z = nullptr;
   for (auto &a : p->lw_a) a = nullptr;
   p->lw_items = p->lw_rows = 0;
-  p->lw_nmax = 0;
+  p->lw_nmax = p->lw_tiles = 0;
 }
 
-int grow_learned(dock_pocket *p, int64_t items, int nmax) {
+int grow_learned(dock_pocket *p, int64_t items, int nmax, int tiles) {
   const int64_t rows = (items + 63) / 64 * 64;
-  if (items <= p->lw_items && nmax <= p->lw_nmax && p->lw_pose) return DOCK_OK;
+  if (items <= p->lw_items && nmax <= p->lw_nmax && tiles <= p->lw_tiles && p->lw_pose)
+    return DOCK_OK;
   free_learned(p);
   hipError_t e = hipSuccess;
   auto A = [&](void **q, size_t b) {
@@ -236,7 +237,7 @@ int grow_learned(dock_pocket *p, int64_t items, int nmax) {
   };
   A((void **)&p->lw_pose, sizeof(float4) * (size_t)items * nmax);
   A((void **)&p->lw_feat, sizeof(uint16_t) * (size_t)rows * 64);
-  A((void **)&p->lw_valid, sizeof(uint64_t) * (size_t)items * 4);
+  A((void **)&p->lw_valid, sizeof(uint64_t) * (size_t)items * tiles);
   for (auto &z : p->lw_z) A((void **)&z, sizeof(float) * (size_t)rows * 256);
   for (auto &a : p->lw_a) A((void **)&a, sizeof(uint16_t) * (size_t)rows * 256);
   // padding rows of the feature matrix stay zero
@@ -249,6 +250,7 @@ int grow_learned(dock_pocket *p, int64_t items, int nmax) {
   p->lw_items = items;
   p->lw_rows = rows;
   p->lw_nmax = nmax;
+  p->lw_tiles = tiles;
   return DOCK_OK;
 }
 
@@ -262,8 +264,11 @@ int enqueue_batch(dock_pocket *p, const dock_ligands *ligs, const float *orient,
   const bool learned = prm->mode == DOCK_MODE_LEARNED;
   if (learned) {
     if (!p->prop_wb) return fail(DOCK_E_STATE, "no learned proposal loaded (dock_load_proposal)");
-    if (S != 256) return fail(DOCK_E_LIMIT, "learned mode needs angle_steps = 256 (one bin per step)");
+    if (S % 256 != 0 || ((S / 256) & (S / 256 - 1)) != 0)
+      return fail(DOCK_E_LIMIT, "learned mode needs angle_steps = 256 x a power of two (256 bins)");
     if (prm->top_k < 1 || prm->top_k > 63) return fail(DOCK_E_LIMIT, "top_k outside [1, 63]");
+    if (prm->top_k * (S / 256) + 1 > 512)
+      return fail(DOCK_E_LIMIT, "top_k x angle_steps / 256 must be below 512");
     if (prm->max_rot < 0 || prm->max_rot > DOCK_MAX_ROT) return fail(DOCK_E_LIMIT, "max_rot outside [0, 255]");
   }
   WsLayout w = ws_layout(L, ligs->total_rot, O, S, prm->passes);
@@ -302,7 +307,7 @@ int enqueue_batch(dock_pocket *p, const dock_ligands *ligs, const float *orient,
   const int maxn = maxn_bucket(max_atoms);
   if (learned) {
     const int nmax = (max_atoms + 15) / 16 * 16;
-    int rc = grow_learned(p, L * O, nmax);
+    int rc = grow_learned(p, L * O, nmax, S / 64);
     if (rc) return rc;
     int32_t *nfb = out->n_fallback;
     if (!nfb) {
@@ -324,6 +329,9 @@ int enqueue_batch(dock_pocket *p, const dock_ligands *ligs, const float *orient,
     LA.feat = p->lw_feat;
     LA.valid = p->lw_valid;
     LA.pred = p->lw_z[3];
+    LA.tiles = S / 64;
+    LA.bin_shift = 0;
+    while ((256 << LA.bin_shift) < S) ++LA.bin_shift;
     LA.top_k = prm->top_k;
     LA.margin = prm->margin;
     LA.n_fallback = nfb;

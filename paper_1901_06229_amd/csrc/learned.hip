@@ -4,15 +4,17 @@
 // large matrix products over every item's features:
 //   begin:  stage the rigid pose, set up the first rotamer, write its 64
 //           features and its exact validity mask (bump test of all angles);
-//   MLP:    predicted score landscape (256 bins) for every item;
-//   step:   nominate the top_k valid bins by prediction (plus angle 0),
-//           score them exactly, keep the best; if the predicted margin
-//           (best minus the (top_k+1)-th valid prediction) is below the
-//           threshold, score every valid angle instead (the plain sweep's
-//           step, bit for bit); apply, then set up the next rotamer and
-//           write its features and mask.
+//   MLP:    predicted score landscape over 256 bins for every item (bin b
+//           covers the S/256 steps of angles [2 pi b/256, 2 pi (b+1)/256));
+//   step:   nominate the top_k bins by prediction among the bins holding a
+//           valid step, score every valid step of those bins (plus angle 0)
+//           exactly and keep the best; if the predicted margin (best minus
+//           the (top_k+1)-th valid prediction) is below the threshold, score
+//           every valid step instead (the plain sweep's step, bit for bit);
+//           apply, then set up the next rotamer and write its features and
+//           mask.
 // Validity is never predicted: it is the same exact bump test as the plain
-// sweep, so a nominated angle is always a valid one.
+// sweep, so a chosen angle is always a valid one.
 #include <hip/hip_runtime.h>
 
 #include "dock_internal.h"
@@ -21,6 +23,10 @@
 #include "sweep_common.h"
 
 namespace dock {
+
+// Compaction capacity of the learned kernels' waves: 8 tiles = 512 steps,
+// enough for top_k nominated bins of S/256 steps plus angle 0.
+constexpr int kLearnedTiles = 8;
 
 // Orderable 32-bit key of (prediction, -bin) for the nomination rounds.
 __device__ __forceinline__ uint32_t nom_key(float y, int k) {
@@ -51,16 +57,16 @@ __device__ __forceinline__ RotState setup_step(const LearnedArgs &A, const WaveL
   return rotamer_setup(W, I.n, T, A.sw.lig.move_atoms, lane);
 }
 
-// Features and exact validity of the rotamer step just set up.
+// Features and exact validity (S bits) of the rotamer step just set up.
 __device__ __forceinline__ void write_step_inputs(const LearnedArgs &A, const WaveLds &W,
                                                   const RotState &RS, int item, int lane) {
   const GridView G = A.sw.grid;
   A.feat[(size_t)item * 64 + lane] = f32_to_bf16(rotamer_feature(W, RS, G, lane));
-  rotamer_bump_mask(W, RS, A.sw.r2, A.sw.r2 + kPruneMargin, 256, lane);
-#pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    const uint64_t vm = tile_valid_mask(W, t, 256);
-    if (lane == 0) A.valid[(size_t)item * 4 + t] = vm;
+  rotamer_bump_mask(W, RS, A.sw.r2, A.sw.r2 + kPruneMargin, A.sw.S, lane);
+  // lane t writes the valid mask of tile t (S is a multiple of 64)
+  if (lane < A.tiles) {
+    const uint64_t bumps = ((uint64_t)W.BM[2 * lane + 1] << 32) | (uint64_t)W.BM[2 * lane];
+    A.valid[(size_t)item * A.tiles + lane] = ~bumps;
   }
 }
 
@@ -84,7 +90,7 @@ __device__ __forceinline__ void save_pose(const LearnedArgs &A, const WaveLds &W
 __global__ void __launch_bounds__(kWave) learned_begin_kernel(LearnedArgs A) {
   extern __shared__ float4 dyn_lds[];
   const int lane = threadIdx.x;
-  const WaveLds W((char *)dyn_lds, A.nmax, false, 4);
+  const WaveLds W((char *)dyn_lds, A.nmax, false, kLearnedTiles);
   for (int item = blockIdx.x; item < A.sw.n_items; item += gridDim.x) {
     const ItemInfo I = item_info(A, item);
     if (A.sw.status[I.l] != 0) continue;
@@ -100,13 +106,32 @@ __global__ void __launch_bounds__(kWave) learned_begin_kernel(LearnedArgs A) {
   }
 }
 
+// Best key over the valid steps compacted in W.CK[0, nvalid), scored two
+// tiles at a time.
+__device__ __forceinline__ uint64_t score_compacted_list(const WaveLds &W, const RotState &RS,
+                                                         const GridView &G, const GridScaled &GS,
+                                                         __amdgpu_buffer_rsrc_t grsrc,
+                                                         const float2 *cs, int nvalid, float s0,
+                                                         int lane) {
+  uint64_t best = 0ull;
+  const int tc = (nvalid + kWave - 1) / kWave;
+  for (int t0 = 0; t0 < tc; t0 += 2) {
+    const uint64_t b =
+        tc - t0 >= 2 ? score_compacted<2, false>(W, RS, G, GS, grsrc, cs, nvalid, s0, lane, t0)
+                     : score_compacted<1, false>(W, RS, G, GS, grsrc, cs, nvalid, s0, lane, t0);
+    best = b > best ? b : best;
+  }
+  return best;
+}
+
 __global__ void __launch_bounds__(kWave) learned_step_kernel(LearnedArgs A, int step) {
   extern __shared__ float4 dyn_lds[];
   const int lane = threadIdx.x;
-  const WaveLds W((char *)dyn_lds, A.nmax, false, 4);
+  const WaveLds W((char *)dyn_lds, A.nmax, false, kLearnedTiles);
   const GridView G = A.sw.grid;
   const GridScaled GS = grid_scaled(G);
   const __amdgpu_buffer_rsrc_t grsrc = grid_rsrc(G);
+  const int f = 1 << A.bin_shift;  // steps per bin
   for (int item = blockIdx.x; item < A.sw.n_items; item += gridDim.x) {
     const ItemInfo I = item_info(A, item);
     if (A.sw.status[I.l] != 0 || step >= I.steps) continue;
@@ -115,17 +140,20 @@ __global__ void __launch_bounds__(kWave) learned_step_kernel(LearnedArgs A, int 
     wave_lds_sync();
     const RotState RS = setup_step(A, W, I, step, lane);
     const float s0 = rotamer_s0(W, RS, lane);
-    // predictions of this item's 256 bins, invalid ones out of the race
+    const uint64_t *valid = A.valid + (size_t)item * A.tiles;
+    // predictions of this item's 256 bins; bins without a valid step are out
+    // of the race (lane holds bins lane, 64 + lane, 128 + lane, 192 + lane)
     const float *y = A.pred + (size_t)item * 256;
-    uint64_t vm[4];
     uint32_t key[4];
     bool any_valid = false;
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-      vm[t] = A.valid[(size_t)item * 4 + t];
-      const bool v = (vm[t] >> lane) & 1ull;
-      key[t] = v ? nom_key(y[t * kWave + lane], t * kWave + lane) : 0u;
-      any_valid = any_valid || vm[t] != 0ull;
+      const int b = t * kWave + lane;
+      const int k0 = b << A.bin_shift;  // first step of the bin
+      const uint64_t w = valid[k0 >> 6];
+      const uint64_t bits = (w >> (k0 & 63)) & (f == 64 ? ~0ull : ((1ull << f) - 1ull));
+      key[t] = bits ? nom_key(y[b], b) : 0u;
+      any_valid = any_valid || __ballot(bits != 0ull) != 0ull;
     }
     // nomination rounds: the top_k valid bins, then the next one for the margin
     int nom = -1;  // lane j < top_k receives the j-th nominated bin
@@ -151,18 +179,35 @@ __global__ void __launch_bounds__(kWave) learned_step_kernel(LearnedArgs A, int 
     const bool fallback = any_valid && margin < A.margin;
     uint64_t best = 0ull;
     if (fallback) {  // the plain step over every valid angle
-      int nvalid;
-      best = best_valid_step<4, false>(W, RS, G, GS, grsrc, A.sw.cs, vm, 0, s0, lane, nvalid);
+      for (int t0 = 0; t0 < A.tiles; t0 += 4) {
+        uint64_t vm[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) vm[t] = valid[t0 + t];
+        int nvalid;
+        const uint64_t key4 =
+            best_valid_step<4, false>(W, RS, G, GS, grsrc, A.sw.cs, vm, t0, s0, lane, nvalid);
+        best = key4 > best ? key4 : best;
+      }
       if (lane == 0) atomicAdd(A.n_fallback + I.l, 1);
-    } else if (any_valid) {  // nominated bins plus the current pose
-      const bool zero_valid = vm[0] & 1ull;
-      if (lane == A.top_k && zero_valid) nom = 0;
-      const int ang = nom >= 0 ? nom : 0;
-      const float2 cs = A.sw.cs[ang];
-      float cc[1] = {cs.x}, ss[1] = {cs.y}, score[1];
-      rotamer_scores<1, false>(W, RS, G, GS, grsrc, cc, ss, score, lane);
-      if (ang == 0) score[0] = s0;
-      best = nom >= 0 ? best_key(score[0], (uint32_t)ang) : 0ull;
+    } else if (any_valid) {
+      // nominated bins as a 256-bit mask (the bump-mask words are free until
+      // the next step's inputs are written)
+      if (lane < 8) W.BM[lane] = 0u;
+      wave_lds_sync();
+      if (nom >= 0) atomicOr(&W.BM[nom >> 5], 1u << (nom & 31));
+      wave_lds_sync();
+      // valid steps of the nominated bins, plus angle 0, compacted in order
+      int nvalid = 0;
+      for (int t = 0; t < A.tiles; ++t) {
+        const int bin = (t * kWave + lane) >> A.bin_shift;
+        const bool nominated = (W.BM[bin >> 5] >> (bin & 31)) & 1u;
+        const uint64_t m = valid[t] & (__ballot(nominated) | (t == 0 ? 1ull : 0ull));
+        if ((m >> lane) & 1ull) W.CK[nvalid + mask_rank(m)] = (int16_t)(t * kWave + lane);
+        nvalid += __popcll(m);
+      }
+      wave_lds_sync();
+      best = score_compacted_list(W, RS, G, GS, grsrc, A.sw.cs, nvalid, s0, lane);
+      wave_lds_sync();
     }
     best = wave_max_u64(best);
     const int kb = best ? (int)key_index(best) : -1;
@@ -192,14 +237,14 @@ static unsigned grid_for(int n_items, int n_cu) {
 hipError_t enqueue_learned_begin(const LearnedArgs &A, int n_cu, hipStream_t st) {
   if (A.sw.n_items <= 0) return hipSuccess;
   hipLaunchKernelGGL(learned_begin_kernel, dim3(grid_for(A.sw.n_items, n_cu)), dim3(kWave),
-                     wave_lds_bytes(A.nmax, false, 4), st, A);
+                     wave_lds_bytes(A.nmax, false, kLearnedTiles), st, A);
   return hipGetLastError();
 }
 
 hipError_t enqueue_learned_step(const LearnedArgs &A, int step, int n_cu, hipStream_t st) {
   if (A.sw.n_items <= 0) return hipSuccess;
   hipLaunchKernelGGL(learned_step_kernel, dim3(grid_for(A.sw.n_items, n_cu)), dim3(kWave),
-                     wave_lds_bytes(A.nmax, false, 4), st, A, step);
+                     wave_lds_bytes(A.nmax, false, kLearnedTiles), st, A, step);
   return hipGetLastError();
 }
 

@@ -13,9 +13,11 @@ struct LearnedArgs {
   int nmax;             // LDS atoms per wave (>= largest ligand)
   float4 *pose;         // [n_items][nmax] pose between steps (x, y, z, voxel value)
   uint16_t *feat;       // [rows][64] BF16 features of each item's next step
-  uint64_t *valid;      // [n_items][4] exact validity of the 256 angle steps
+  uint64_t *valid;      // [n_items][tiles] exact validity of the S angle steps
   const float *pred;    // [rows][256] MLP output for the current step
-  int top_k;            // nominated bins per step (1 .. 63)
+  int tiles;            // S / 64
+  int bin_shift;        // log2(S / 256): steps per prediction bin = 1 << bin_shift
+  int top_k;            // nominated bins per step (1 .. 63, top_k << bin_shift < 512)
   float margin;         // fall back to the full step below this predicted margin
   int32_t *n_fallback;  // [n_ligands] steps that fell back
 };

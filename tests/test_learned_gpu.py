@@ -192,3 +192,40 @@ def test_training_reduces_loss():
     print(hist)
     assert hist["val_loss"][-1] < hist["val_loss"][0] or hist["val_loss"][-1] < 0.9 * hist["train_loss"][0]
     assert np.isfinite(hist["val_loss"]).all()
+
+
+def test_learned_mode_at_finer_steps():
+    """S = 1024 (4 steps per prediction bin): with fallback everywhere the
+    result is the plain sweep bit for bit; without fallback every chosen
+    angle is valid and the poses replay against the reference; sizes outside
+    the documented limits are rejected."""
+    _torch()
+    pocket, h, net = _proposal_pocket()
+    ligs = synth.ligands(learned.LIGAND_RECIPE, count=10, seed=4, stream=synth.STREAM_EVAL)
+    orient = synth.orientations(learned.LEARN_CONFIG)
+    S = 1024
+    plain = dock.dock_batch(h, ligs, orient, S, want_all=True)
+    lrn = dock.dock_batch(h, ligs, orient, S, mode=dock.DOCK_MODE_LEARNED, top_k=16,
+                          margin=3.0e38, want_all=True)
+    for k in ("best_score", "best_orient", "angle_idx", "xyz", "all_scores", "all_angle_idx"):
+        assert np.array_equal(plain[k], lrn[k]), k
+    res = dock.dock_batch(h, ligs, orient, S, mode=dock.DOCK_MODE_LEARNED, top_k=8,
+                          margin=-1.0, want_all=True)
+    assert (res["n_fallback"] == 0).all()
+    bad = []
+    for l in range(ligs.n_ligands):
+        lig = ligs.ligand(l)
+        for o in (0, 5):
+            k = item_steps(ligs, l, o, 8, 1, res["all_angle_idx"])
+            tr = oracle.trace_item(pocket, lig, orient[o], S, forced_k=k)
+            for s, kk in enumerate(k):
+                f = tr.prof_flags[s][int(kk)] if kk >= 0 else 0
+                if kk < 0 or not (f & (oracle.FLAG_VALID | oracle.FLAG_VAMB)):
+                    bad.append((l, o, s, int(kk)))
+            sc = float(res["all_scores"][l, o])
+            assert abs(sc - tr.score) <= tol_of(tr.score) or tr.score_lo - 1e-3 <= sc <= tr.score_hi + 1e-3
+    assert not bad, bad[:10]
+    for S_bad, top_k in ((384, 8), (4096, 63)):
+        with pytest.raises(dock.DockError):
+            dock.dock_batch(h, ligs, orient, S_bad, mode=dock.DOCK_MODE_LEARNED, top_k=top_k)
+    h.close()
