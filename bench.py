@@ -132,8 +132,9 @@ def copy_calibration():
     print("copied 1 GiB x 3", flush=True)
 
 
-def cpu_baseline(pocket, ligs, orient, S, budget_s=15.0):
-    """The FP64 reference on a bounded sample of the same workload."""
+def cpu_baseline(pocket, ligs, orient, S, budget_s=20.0):
+    """The FP64 reference on a bounded sample of the same workload: the first
+    ligands, doubling the count until one run takes at least budget_s / 2."""
     import oracle
     threads = min(16, os.cpu_count() or 1)
     sample = 8
@@ -143,7 +144,7 @@ def cpu_baseline(pocket, ligs, orient, S, budget_s=15.0):
         t0 = time.perf_counter()
         oracle.dock_batch(pocket, sub, orient, S, n_threads=threads)
         t_used = time.perf_counter() - t0
-        if t_used > budget_s / 4 or sample * 2 > ligs.n_ligands:
+        if t_used >= budget_s / 2 or sample * 2 > ligs.n_ligands:
             break
         sample *= 2
     return {"value": sample / t_used, "unit": "ligands/s", "cores": threads, "kind": "oracle",
