@@ -288,7 +288,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(the batch shards by ligand with no exchange; see DESIGN.md)", file=sys.stderr)
+              "(a batch would shard by ligand, with no exchange between GPUs)", file=sys.stderr)
         sys.exit(2)
 
     if args.copy_calibration:
