@@ -29,8 +29,13 @@
  *     no caller pointer after they return; asynchronous calls keep them until
  *     the stream has passed the enqueued work.
  *   - A dock_pocket owns its device copy of the grid until dock_free_pocket.
- *     One handle may be shared across threads; concurrent calls on one
- *     handle must use distinct streams (each call uses its own workspace).
+ *     One handle may be shared across threads: calls are enqueued under the
+ *     handle's lock, and synchronous calls return only when done.  Work that
+ *     overlaps in time on one handle must be plain-mode dock_batch_async
+ *     calls on distinct streams, each with its own workspace.  Learned-mode
+ *     calls, calls that pass no workspace and calls with
+ *     DOCK_FLAG_TIME_SWEEP use buffers or events the handle owns and must
+ *     not overlap with another such call on the same handle.
  */
 #ifndef DOCK_H
 #define DOCK_H
