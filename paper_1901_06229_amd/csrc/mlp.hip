@@ -30,12 +30,28 @@ __device__ __forceinline__ uint16_t f2bf(float f) {
 }
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
+// erf by Abramowitz & Stegun 7.1.26: 1 - (a1 t + ... + a5 t^5) exp(-x^2),
+// t = 1 / (1 + p |x|), odd in x; absolute error below 1.5e-7, far below the
+// BF16 resolution of the activations it feeds.  Branch-free: one reciprocal
+// and one exponential.
+__device__ __forceinline__ float erf_as(float x) {
+  const float ax = fabsf(x);
+  const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, ax, 1.0f));
+  float p = fmaf(1.061405429f, t, -1.453152027f);
+  p = fmaf(p, t, 1.421413741f);
+  p = fmaf(p, t, -0.284496736f);
+  p = fmaf(p, t, 0.254829592f);
+  p *= t;
+  const float r = fmaf(-p, __expf(-ax * ax), 1.0f);
+  return copysignf(r, x);
+}
+
 __device__ __forceinline__ float gelu_f(float z) {
-  return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f));
+  return 0.5f * z * (1.0f + erf_as(z * 0.70710678118654752f));
 }
 __device__ __forceinline__ float gelu_grad_f(float z) {
-  return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) +
-         z * expf(-0.5f * z * z) * 0.39894228040143268f;
+  return 0.5f * (1.0f + erf_as(z * 0.70710678118654752f)) +
+         z * __expf(-0.5f * z * z) * 0.39894228040143268f;
 }
 
 constexpr int kTile = 64;  // output tile edge
@@ -145,8 +161,10 @@ hipError_t gemm_bf16(const GemmArgs &g, bool ta, bool tb, int epi, int M, int N,
 constexpr int kInfRows = 64;
 constexpr int kActPad = 8;
 
-__global__ void __launch_bounds__(256) mlp_infer_kernel(const uint16_t *x, const uint16_t *wb,
-                                                        const float *bias_src, float *y) {
+// Two blocks per CU (two waves per SIMD, within 256 registers and no spills):
+// one block's GELU epilogue overlaps the other's matrix products.
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+    mlp_infer_kernel(const uint16_t *x, const uint16_t *wb, const float *bias_src, float *y) {
   __shared__ __attribute__((aligned(16))) uint16_t sH[kInfRows][256 + kActPad];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const size_t row0 = (size_t)blockIdx.x * kInfRows;
@@ -170,14 +188,19 @@ __global__ void __launch_bounds__(256) mlp_infer_kernel(const uint16_t *x, const
 #pragma unroll
         for (int j = 0; j < 16; ++j) acc[a][b][j] = 0.0f;
     const uint16_t *W = wb + woff[l];
-    const int K = kin[l];
-#pragma unroll 2
-    for (int k0 = 0; k0 < K; k0 += 16) {
+    const int K = kin[l];  // 64 or 256: a multiple of 4 k-steps of 16
+    // Weight operands come from global memory (L2): they are fetched four
+    // k-steps ahead into four rotating register sets, so the MFMAs of a step
+    // do not wait for its loads.
+    auto load_w = [&](int k0, bf16x8(&bo)[2]) {
       const int kk = k0 + (lane >> 5) * 8;
-      bf16x8 bo[2], ao[2];
 #pragma unroll
       for (int b = 0; b < 2; ++b)
         bo[b] = *(const bf16x8 *)(W + (size_t)(col0 + b * 32 + (lane & 31)) * K + kk);
+    };
+    auto step = [&](int k0, const bf16x8(&bo)[2]) {
+      const int kk = k0 + (lane >> 5) * 8;
+      bf16x8 ao[2];
 #pragma unroll
       for (int a = 0; a < 2; ++a) ao[a] = *(const bf16x8 *)&sH[a * 32 + (lane & 31)][kk];
 #pragma unroll
@@ -185,6 +208,23 @@ __global__ void __launch_bounds__(256) mlp_infer_kernel(const uint16_t *x, const
 #pragma unroll
         for (int b = 0; b < 2; ++b)
           acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ao[a], bo[b], acc[a][b], 0, 0, 0);
+    };
+    bf16x8 w0[2], w1[2], w2[2], w3[2];
+    load_w(0, w0);
+    load_w(16, w1);
+    load_w(32, w2);
+    load_w(48, w3);
+#pragma unroll 1
+    for (int k0 = 0; k0 < K; k0 += 64) {
+      const bool more = k0 + 64 < K;
+      step(k0, w0);
+      if (more) load_w(k0 + 64, w0);
+      step(k0 + 16, w1);
+      if (more) load_w(k0 + 80, w1);
+      step(k0 + 32, w2);
+      if (more) load_w(k0 + 96, w2);
+      step(k0 + 48, w3);
+      if (more) load_w(k0 + 112, w3);
     }
     __syncthreads();  // every wave is done reading this layer's input
     const float *bias = bias_src + boff[l];
