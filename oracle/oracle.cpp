@@ -28,6 +28,16 @@
 //     better;
 //   * ties: lowest angle index, lowest orientation index; no valid angle ->
 //     no move, recorded as -1.
+// Optional rigid alignment before the sweep (paper §3.1, first phase: the
+// ligand as a rigid body is turned to the orientation that fits the pocket
+// best, the score evaluated at every rotation; §4.1: rotation and scoring
+// fused, a reduction to the best orientation, then one rotation of the
+// ligand).  Readings:
+//   * the candidate set is a caller-given list of rotation matrices R_a;
+//   * each is applied about the centroid c of the starting pose,
+//     Y_i = c + R_a (X_i - c), every atom moving (a rigid body keeps its
+//     internal distances, so no bump test applies);
+//   * score as above; the lowest index among the best scores wins.
 #include <atomic>
 #include <cmath>
 #include <cstdint>
@@ -126,6 +136,9 @@ struct Ligand {
 // Optional per-step record (profile and ambiguity information).
 struct Trace {
   const int16_t *forced_k;  // follow these choices instead of the argmax
+  int forced_a;             // alignment to follow instead of the argmax (-1: none)
+  double *align_s, *align_lo, *align_hi;  // [n_align]
+  uint8_t *align_flags;                   // bit2 score ambiguous
   double delta;
   double *prof_s, *prof_lo, *prof_hi;  // [steps * S]
   uint8_t *prof_flags;                 // bit0 valid, bit1 validity ambiguous,
@@ -133,10 +146,65 @@ struct Trace {
   double *final_lo, *final_hi;
 };
 
-// One restart: orientation, then the greedy sweep.  Returns the final score.
+// Rigid alignment of pose X (n atoms) over the rotation set: every candidate
+// scored, the best (lowest index on ties) applied about the centroid.
+// Returns this reference's own argmax; the pose follows tr->forced_a if set.
+int align_pose(const Pocket &P, std::vector<double> &X, int n, const float *align_rot,
+               int n_align, Trace *tr) {
+  double c[3] = {0.0, 0.0, 0.0};
+  for (int i = 0; i < n; ++i)
+    for (int d = 0; d < 3; ++d) c[d] += X[3 * i + d];
+  for (int d = 0; d < 3; ++d) c[d] /= (double)n;
+  auto place = [&](int a, int i, double y[3]) {
+    const float *Rm = align_rot + 9 * (size_t)a;
+    for (int d = 0; d < 3; ++d) {
+      double acc = c[d];
+      for (int e = 0; e < 3; ++e) acc += (double)Rm[3 * d + e] * (X[3 * i + e] - c[e]);
+      y[d] = acc;
+    }
+  };
+  int best_a = -1;
+  double best_s = 0.0;
+  for (int a = 0; a < n_align; ++a) {
+    double score = 0.0, lo = 0.0, hi = 0.0;
+    bool samb = false;
+    for (int i = 0; i < n; ++i) {
+      double y[3];
+      place(a, i, y);
+      score += voxel_value(P, y);
+      if (tr) {
+        double vl, vh;
+        bool am;
+        voxel_interval(P, y, tr->delta, &vl, &vh, &am);
+        lo += vl;
+        hi += vh;
+        samb = samb || am;
+      }
+    }
+    if (tr && tr->align_s) {
+      tr->align_s[a] = score;
+      tr->align_lo[a] = lo;
+      tr->align_hi[a] = hi;
+      tr->align_flags[a] = (uint8_t)(samb ? 4 : 0);
+    }
+    if (best_a < 0 || score > best_s) {
+      best_a = a;
+      best_s = score;
+    }
+  }
+  const int follow = (tr && tr->forced_a >= 0) ? tr->forced_a : best_a;
+  std::vector<double> Y((size_t)n * 3);
+  for (int i = 0; i < n; ++i) place(follow, i, &Y[3 * i]);
+  X.swap(Y);
+  return best_a;
+}
+
+// One restart: orientation, optional rigid alignment, then the greedy sweep.
+// Returns the final score.
 double run_item(const Pocket &P, const Ligand &L, const float *orient, int S,
                 double r_bump, int passes, int16_t *k_out, double *xyz_out,
-                Trace *tr) {
+                Trace *tr, const float *align_rot = nullptr, int n_align = 0,
+                int16_t *a_out = nullptr) {
   const int n = L.n;
   std::vector<double> X((size_t)n * 3), Y((size_t)n * 3);
   // rigid starting pose: X = R X_ref + t
@@ -147,6 +215,10 @@ double run_item(const Pocket &P, const Ligand &L, const float *orient, int S,
         acc += (double)orient[3 * d + e] * (double)L.xyz[3 * i + e];
       X[3 * i + d] = acc;
     }
+  if (n_align > 0) {
+    const int a = align_pose(P, X, n, align_rot, n_align, tr);
+    if (a_out) *a_out = (int16_t)a;
+  }
   std::vector<char> moving(n), onaxis(n);
   const double r2 = r_bump * r_bump;
   int step = 0;
@@ -298,18 +370,25 @@ int oracle_trace_item(const float *grid, int nx, int ny, int nz,
                       double delta, int16_t *k_star, double *xyz_out,
                       double *final_score, double *final_lo, double *final_hi,
                       double *prof_s, double *prof_lo, double *prof_hi,
-                      uint8_t *prof_flags) {
-  if (n < 1 || R < 0 || S < 1 || passes < 1) return -1;
+                      uint8_t *prof_flags, const float *align_rot, int n_align,
+                      int forced_a, int16_t *a_star, double *align_s, double *align_lo,
+                      double *align_hi, uint8_t *align_flags) {
+  if (n < 1 || R < 0 || S < 1 || passes < 1 || n_align < 0) return -1;
+  if (n_align > 0 && (!align_rot || forced_a >= n_align)) return -1;
   Pocket P = make_pocket(grid, nx, ny, nz, origin, spacing);
   Ligand L{n, R, xyz, rot_axis, move_offset, move_atoms};
-  Trace tr{forced_k, delta, prof_s, prof_lo, prof_hi, prof_flags, final_lo, final_hi};
-  *final_score = run_item(P, L, orient, S, r_bump, passes, k_star, xyz_out, &tr);
+  Trace tr{forced_k, forced_a, align_s, align_lo, align_hi, align_flags, delta,
+           prof_s, prof_lo, prof_hi, prof_flags, final_lo, final_hi};
+  *final_score = run_item(P, L, orient, S, r_bump, passes, k_star, xyz_out, &tr,
+                          align_rot, n_align, a_star);
   return 0;
 }
 
 // Whole batch: every ligand x every orientation, best orientation per ligand.
 // angle_idx: [total_rot * passes]; ligand l's entries start at
-// rot_offset[l] * passes.  all_scores may be NULL.
+// rot_offset[l] * passes.  all_scores may be NULL.  With n_align > 0 every
+// restart is aligned first; best_align[l] (may be NULL) receives the
+// alignment of the best orientation, all_align[l][o] (may be NULL) every one.
 int oracle_dock_batch(const float *grid, int nx, int ny, int nz,
                       const float *origin, float spacing, int n_ligands,
                       const int32_t *atom_offset, const float *xyz,
@@ -318,8 +397,10 @@ int oracle_dock_batch(const float *grid, int nx, int ny, int nz,
                       const float *orient, int n_orient, int S, double r_bump,
                       int passes, double *best_score, int32_t *best_orient,
                       int16_t *angle_idx, double *xyz_out, double *all_scores,
-                      int n_threads) {
-  if (n_ligands < 0 || n_orient < 1 || S < 1 || passes < 1) return -1;
+                      int n_threads, const float *align_rot, int n_align,
+                      int16_t *best_align, int16_t *all_align) {
+  if (n_ligands < 0 || n_orient < 1 || S < 1 || passes < 1 || n_align < 0) return -1;
+  if (n_align > 0 && !align_rot) return -1;
   Pocket P = make_pocket(grid, nx, ny, nz, origin, spacing);
   std::atomic<int> next{0};
   auto work = [&]() {
@@ -340,13 +421,17 @@ int oracle_dock_batch(const float *grid, int nx, int ny, int nz,
       xbuf.resize((size_t)n * 3);
       xbest.resize((size_t)n * 3);
       int bo = -1;
+      int16_t ba = -1;
       double bs = 0.0;
       for (int o = 0; o < n_orient; ++o) {
+        int16_t a = -1;
         double s = run_item(P, L, orient + 12 * (size_t)o, S, r_bump, passes,
-                            kbuf.data(), xbuf.data(), nullptr);
+                            kbuf.data(), xbuf.data(), nullptr, align_rot, n_align, &a);
         if (all_scores) all_scores[(size_t)l * n_orient + o] = s;
+        if (all_align) all_align[(size_t)l * n_orient + o] = a;
         if (bo < 0 || s > bs) {
           bo = o;
+          ba = a;
           bs = s;
           kbest.swap(kbuf);
           xbest.swap(xbuf);
@@ -354,6 +439,7 @@ int oracle_dock_batch(const float *grid, int nx, int ny, int nz,
       }
       best_score[l] = bs;
       best_orient[l] = bo;
+      if (best_align) best_align[l] = ba;
       if (angle_idx)
         std::memcpy(angle_idx + (size_t)r0 * passes, kbest.data(),
                     sizeof(int16_t) * R * passes);

@@ -37,6 +37,7 @@ PRESETS = {
 
 # generator streams
 STREAM_POCKET, STREAM_LIGANDS, STREAM_ORIENT, STREAM_TRAIN, STREAM_EVAL = 0, 1, 2, 3, 4
+STREAM_ALIGN = 5
 
 _lib = None
 
@@ -206,4 +207,16 @@ def orientations(config: int, n: int | None = None, seed: int | None = None,
     s = config_seed(config) if seed is None else seed
     out = np.empty((n, 12), np.float32)
     lib.synth_orientations(s, stream, first, n, _ptr(out))
+    return out
+
+
+def align_rotations(config: int, n: int, seed: int | None = None) -> np.ndarray:
+    """[n, 3, 3] float32 rotation set for the rigid alignment search: the
+    identity first (so an aligned restart never scores below its starting
+    pose), then n - 1 uniform random rotations from their own stream."""
+    out = np.empty((n, 3, 3), np.float32)
+    if n > 0:
+        out[0] = np.eye(3, dtype=np.float32)
+    if n > 1:
+        out[1:] = orientations(config, n - 1, seed=seed, stream=STREAM_ALIGN)[:, :9].reshape(-1, 3, 3)
     return out
