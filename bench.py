@@ -44,6 +44,11 @@ VALU_PEAK_TOPS = 256 * 128 * 2.4e9 / 1e12
 #       the score add (the gather itself is a memory instruction).
 OPS_PAIR, OPS_ROT, OPS_VOX = 8, 23, 22
 OPS_CAND, OPS_ARC, OPS_EVAL = 17, 133, 16
+# Rigid alignment, per (item, rotation, atom): 9 FMA rotation, 3 clamps,
+# 3 conversions, shift, 2 24-bit multiply-adds and the score add (the gather
+# is a memory instruction).
+OPS_ALIGN = 19
+ALIGN_ROTATIONS = 64
 
 # Sources of the sweep kernel: the HBM traffic measured by the FETCH_SIZE /
 # WRITE_SIZE counters is reported only while these are unchanged.
@@ -267,6 +272,51 @@ def learned_comparison(n_eval=10_000, n_val=2_000, n_train=156_250, epochs=10, t
     return res
 
 
+def align_leg(cfg, h, ligs, d, orient_d, S, out, stream, steps, warmup, max_atoms, n_align):
+    """The same batch with a rigid alignment search before the sweep (paper
+    §3.1, first phase): n_align rotations per (ligand, orientation) restart."""
+    import torch
+    from paper_1901_06229_amd import dock, synth
+    L, O = ligs.n_ligands, orient_d.shape[0]
+    rots = torch.from_numpy(synth.align_rotations(cfg, n_align)).cuda()
+    ws = torch.empty(dock.dock_workspace_size(L, d["total_rot"], O, S, n_align=n_align),
+                     dtype=torch.uint8, device="cuda:0")
+    prm = dock.make_params(r_bump=synth.R_BUMP, max_atoms=max_atoms, flags=dock.DOCK_FLAG_TIME_SWEEP,
+                           align=rots)
+
+    def step():
+        dock.dock_batch_async(h, d, orient_d, S, out, prm, workspace=ws, stream=stream)
+        return dock.dock_last_align_ms(h), dock.dock_last_sweep_ms(h)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    times = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        times.append(step())
+    stream.synchronize()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    align_s = float(np.mean([t[0] for t in times])) / 1e3
+    evals = float(n_align) * O * float(ligs.atom_offset[-1])
+    achieved = OPS_ALIGN * evals / align_s / 1e12
+    return {
+        "workload": f"{WORKLOADS[cfg].split(':')[0]} batch with a rigid alignment search of {n_align} "
+                    "rotations (identity first) per restart before the sweep",
+        "n_align": n_align,
+        "ligands_per_s": round(steps * L / elapsed, 2),
+        "ms_per_step": round(1e3 * elapsed / steps, 3),
+        "sweep_ms": round(float(np.mean([t[1] for t in times])), 3),
+        "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 2),
+                     "unit": "TOP/s", "frac": round(achieved / VALU_PEAK_TOPS, 4), "traffic": None,
+                     "kernel": "align_kernel", "kernel_ms": round(1e3 * align_s, 3),
+                     "work": f"lane-ops: {OPS_ALIGN} per (restart, rotation, atom) rotate-and-score",
+                     "rotation_atom_evals": int(evals),
+                     "gathers_per_s": round(evals / align_s, 1)},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -282,6 +332,8 @@ def main():
     ap.add_argument("--claim", type=int, default=32,
                     help="most items a wave takes per work-queue atomic")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-proposal comparison")
+    ap.add_argument("--align", type=int, default=ALIGN_ROTATIONS,
+                    help="rotations of the rigid-alignment leg (0: skip it)")
     ap.add_argument("--proposal", default=None, help="directory of trained proposal weights")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run the 1 GiB copy that calibrates the HBM byte counters")
@@ -385,6 +437,10 @@ def main():
                                  "atom at every angle) per second of this kernel; not a "
                                  "fraction of peak"}},
     }
+    if args.align > 0:
+        log(f"rigid alignment: {args.align} rotations per restart before the sweep")
+        line["align"] = align_leg(cfg, h, ligs, d, orient_d, S, out, stream, args.steps, args.warmup,
+                                  max_atoms, args.align)
     if not args.no_learned:
         log("learned proposal: training on the GPU and comparing with the plain sweep")
         line["learned"] = learned_comparison(proposal=args.proposal)

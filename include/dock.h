@@ -8,6 +8,11 @@
  *
  * What one (ligand, orientation) item computes:
  *   1. X = R_o X_ref + t_o                             (rigid starting pose)
+ *      optional rigid alignment (paper §3.1, first phase; §4.1: rotation and
+ *      scoring fused, reduced to the best, the ligand rotated once): with a
+ *      rotation set R_0 .. R_{A-1}, c = mean of X,
+ *        s_a = sum over atoms of grid[...] at c + R_a (X_i - c),
+ *        a* = lowest a maximising s_a,  X <- c + R_a* (X - c)
  *   2. for pass in [0, passes), for rotamer r in input order:
  *        u = (X_b - X_a)/|X_b - X_a|
  *        for k in [0, S): theta_k = 2 pi k / S; Y = X with the moving atoms
@@ -57,6 +62,7 @@ extern "C" {
 
 #define DOCK_MAX_ATOMS 256    /* atoms per ligand                 */
 #define DOCK_MAX_ROT 255      /* rotamers per ligand              */
+#define DOCK_MAX_ALIGN 4096   /* rotations in an alignment set    */
 #define DOCK_MAX_STEPS 4096   /* angle steps S                    */
 #define DOCK_MAX_PASSES 16    /* refinement passes (num_repetitions) */
 
@@ -109,6 +115,12 @@ typedef struct {
   uint32_t flags;    /* DOCK_FLAG_*                                             */
   int32_t max_atoms; /* async calls: upper bound on atoms per ligand (0: 256)   */
   int32_t max_rot;   /* async learned calls: upper bound on rotamers (0: 255)   */
+  int32_t n_align;   /* rotations in the alignment set, 0 .. DOCK_MAX_ALIGN;
+                        0 = no alignment (the sweep starts from R_o X_ref + t_o) */
+  const float *align_rot; /* [n_align][9] row-major rotation matrices (host
+                        memory for dock_batch, device memory for
+                        dock_batch_async); dock_batch rejects non-finite or
+                        non-orthonormal ones (|R R^T - I| > 1e-3)            */
 } dock_params;
 
 /* Outputs.  Sizes follow from the inputs.
@@ -125,7 +137,12 @@ typedef struct {
  *   status[n_ligands]           optional (NULL): 0 or a DOCK_E_* code per
  *                               ligand (async calls validate on the device)
  *   n_fallback[n_ligands]       optional (NULL): learned mode, steps that
- *                               fell back to the full sweep               */
+ *                               fell back to the full sweep
+ *   align_idx[n_ligands]        optional (NULL): rotation chosen by the
+ *                               alignment of the best orientation (-1 if
+ *                               n_align = 0 or the ligand was rejected)
+ *   all_align_idx[n_ligands][n_orient]  optional (NULL): every item's
+ *                               rotation; written only when n_align > 0     */
 typedef struct {
   float *best_score;
   int32_t *best_orient;
@@ -135,6 +152,8 @@ typedef struct {
   int16_t *all_angle_idx;
   int32_t *status;
   int32_t *n_fallback;
+  int16_t *align_idx;
+  int16_t *all_align_idx;
 } dock_results;
 
 /* Stage a pocket grid on the current HIP device (paper Listing 1: the pocket
@@ -172,14 +191,20 @@ int dock_batch_async(dock_pocket *p, const dock_ligands *ligs,
                      const dock_params *prm, dock_results *out,
                      void *workspace, size_t workspace_bytes, void *stream);
 
-/* Bytes of device workspace dock_batch_async needs for these sizes. */
+/* Bytes of device workspace dock_batch_async needs for these sizes (n_align
+ * as in dock_params: alignment adds 50 bytes per item). */
 size_t dock_workspace_size(int32_t n_ligands, int64_t total_rot, int n_orient,
-                           int angle_steps, int passes);
+                           int angle_steps, int passes, int n_align);
 
 /* Duration in ms of the sweep kernel of the last call on this handle that
  * set DOCK_FLAG_TIME_SWEEP (waits for that kernel to finish).  Errors:
  * DOCK_E_INVAL (NULL), DOCK_E_STATE (no timed call yet), DOCK_E_DEVICE. */
 int dock_last_sweep_ms(dock_pocket *p, float *ms);
+
+/* Duration in ms of the alignment kernels of the last call on this handle
+ * that set DOCK_FLAG_TIME_SWEEP and n_align > 0 (waits for them).  Errors:
+ * DOCK_E_INVAL (NULL), DOCK_E_STATE (no such call yet), DOCK_E_DEVICE. */
+int dock_last_align_ms(dock_pocket *p, float *ms);
 
 /* Work counters of the sweep kernel in the last call with
  * DOCK_FLAG_TIME_SWEEP, for roofline accounting: kept_pairs = cross pairs

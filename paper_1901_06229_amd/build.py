@@ -11,7 +11,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB_PATH = os.path.join(PKG, "libdock.so")
 
-SOURCES = ["sweep_kernels.hip", "sweep_pruned.hip", "learned.hip", "mlp.hip", "mlp_abi.hip",
+SOURCES = ["sweep_kernels.hip", "sweep_pruned.hip", "align.hip", "learned.hip", "mlp.hip", "mlp_abi.hip",
            "dock_abi.hip"]
 
 HIP_FLAGS = [

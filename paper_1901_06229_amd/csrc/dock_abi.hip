@@ -38,6 +38,8 @@ struct dock_pocket {
   size_t sync_ws_bytes = 0;
   hipEvent_t ev_sweep[3] = {nullptr, nullptr, nullptr};  // sweep start/end, counter copied
   bool timed = false;
+  hipEvent_t ev_align[2] = {nullptr, nullptr};  // alignment start/end
+  bool align_timed = false;
   unsigned long long *h_work = nullptr;  // pinned copy of the sweep's two work counters
   LaunchPlan plan{0, 0, 32};
   // last captured launch sequence of dock_batch_async (DOCK_FLAG_GRAPH)
@@ -110,10 +112,10 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct WsLayout {
-  size_t small, keys, order, bucket, status, kstar, cs, total;
+  size_t small, keys, order, bucket, status, kstar, cs, item_orient, item_align, total;
 };
 
-WsLayout ws_layout(int64_t L, int64_t total_rot, int O, int S, int passes) {
+WsLayout ws_layout(int64_t L, int64_t total_rot, int O, int S, int passes, int n_align) {
   WsLayout w;
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -128,6 +130,9 @@ WsLayout ws_layout(int64_t L, int64_t total_rot, int O, int S, int passes) {
   w.status = take(sizeof(int32_t) * (size_t)L);
   w.kstar = take(sizeof(int16_t) * (size_t)total_rot * (size_t)passes * (size_t)O);
   w.cs = take(sizeof(float2) * (size_t)S);
+  // alignment: one rigid transform and one rotation index per item
+  w.item_orient = n_align > 0 ? take(sizeof(float) * 12 * (size_t)L * (size_t)O) : 0;
+  w.item_align = n_align > 0 ? take(sizeof(int16_t) * (size_t)L * (size_t)O) : 0;
   w.total = off;
   return w;
 }
@@ -158,6 +163,26 @@ int check_params(const dock_params *prm, int n_orient, int S) {
     return fail(DOCK_E_INVAL, "unknown mode %d", prm->mode);
   if (prm->max_atoms < 0 || prm->max_atoms > DOCK_MAX_ATOMS)
     return fail(DOCK_E_LIMIT, "max_atoms %d outside [0, %d]", prm->max_atoms, DOCK_MAX_ATOMS);
+  if (prm->n_align < 0 || prm->n_align > DOCK_MAX_ALIGN)
+    return fail(DOCK_E_LIMIT, "n_align %d outside [0, %d]", prm->n_align, DOCK_MAX_ALIGN);
+  if (prm->n_align > 0 && !prm->align_rot) return fail(DOCK_E_INVAL, "align_rot is NULL");
+  return DOCK_OK;
+}
+
+// Host check of an alignment set: finite, orthonormal rows within 1e-3.
+int check_rotations_host(const float *rot, int n) {
+  for (int a = 0; a < n; ++a) {
+    const float *m = rot + 9 * (size_t)a;
+    for (int k = 0; k < 9; ++k)
+      if (!std::isfinite(m[k])) return fail(DOCK_E_INVAL, "alignment rotation %d is not finite", a);
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        double d = (double)m[3 * i] * m[3 * j] + (double)m[3 * i + 1] * m[3 * j + 1] +
+                   (double)m[3 * i + 2] * m[3 * j + 2];
+        if (std::fabs(d - (i == j ? 1.0 : 0.0)) > 1e-3)
+          return fail(DOCK_E_INVAL, "alignment matrix %d is not orthonormal", a);
+      }
+  }
   return DOCK_OK;
 }
 
@@ -271,7 +296,7 @@ int enqueue_batch(dock_pocket *p, const dock_ligands *ligs, const float *orient,
       return fail(DOCK_E_LIMIT, "top_k x angle_steps / 256 must be below 512");
     if (prm->max_rot < 0 || prm->max_rot > DOCK_MAX_ROT) return fail(DOCK_E_LIMIT, "max_rot outside [0, 255]");
   }
-  WsLayout w = ws_layout(L, ligs->total_rot, O, S, prm->passes);
+  WsLayout w = ws_layout(L, ligs->total_rot, O, S, prm->passes, prm->n_align);
   if (ws_bytes < w.total) return fail(DOCK_E_INVAL, "workspace too small: %zu < %zu", ws_bytes, w.total);
   char *base = (char *)ws;
   SweepArgs A{};
@@ -281,6 +306,7 @@ int enqueue_batch(dock_pocket *p, const dock_ligands *ligs, const float *orient,
                   ligs->move_offset, ligs->move_atoms};
   A.orient = orient;
   A.n_orient = O;
+  A.orient_stride = 0;
   A.S = S;
   A.passes = prm->passes;
   A.r2 = prm->r_bump * prm->r_bump;
@@ -305,6 +331,34 @@ int enqueue_batch(dock_pocket *p, const dock_ligands *ligs, const float *orient,
                                  A.small + 1, st);
   if (e != hipSuccess) return hip_fail(e, "prepare kernels");
   const int maxn = maxn_bucket(max_atoms);
+  // rigid alignment: per-item transforms replace the shared orientation table
+  const int16_t *item_align = nullptr;
+  if (prm->n_align > 0 && L > 0) {
+    AlignArgs AA{};
+    AA.grid = p->view;
+    AA.lig = A.lig;
+    AA.orient = orient;
+    AA.n_orient = O;
+    AA.rot = prm->align_rot;
+    AA.n_align = prm->n_align;
+    AA.status = A.status;
+    AA.item_orient = (float *)(base + w.item_orient);
+    AA.item_align = (int16_t *)(base + w.item_align);
+    if (timed && (e = hipEventRecord(p->ev_align[0], st)) != hipSuccess)
+      return hip_fail(e, "hipEventRecord");
+    if ((e = enqueue_align(AA, maxn, st)) != hipSuccess) return hip_fail(e, "alignment kernel");
+    if (timed) {
+      if ((e = hipEventRecord(p->ev_align[1], st)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+      p->align_timed = true;
+    }
+    if (out->all_align_idx &&
+        (e = hipMemcpyAsync(out->all_align_idx, AA.item_align, sizeof(int16_t) * (size_t)L * O,
+                            hipMemcpyDeviceToDevice, st)) != hipSuccess)
+      return hip_fail(e, "copy all_align_idx");
+    A.orient = AA.item_orient;
+    A.orient_stride = O;
+    item_align = AA.item_align;
+  }
   if (learned) {
     const int nmax = (max_atoms + 15) / 16 * 16;
     int rc = grow_learned(p, L * O, nmax, S / 64);
@@ -353,7 +407,8 @@ int enqueue_batch(dock_pocket *p, const dock_ligands *ligs, const float *orient,
       if (e != hipSuccess) return hip_fail(e, "timing");
       p->timed = true;
     }
-    FinalOut F{out->best_score, out->best_orient, out->angle_idx, out->xyz_out};
+    FinalOut F{out->best_score, out->best_orient, out->angle_idx, out->xyz_out, out->align_idx,
+               item_align};
     e = enqueue_finalize(A, F, maxn, kSweepPruned, st);
     if (e != hipSuccess) return hip_fail(e, "finalize kernel");
     if (out->all_angle_idx && ligs->total_rot > 0) {
@@ -379,7 +434,8 @@ int enqueue_batch(dock_pocket *p, const dock_ligands *ligs, const float *orient,
     if ((e = hipEventRecord(p->ev_sweep[2], st)) != hipSuccess) return hip_fail(e, "hipEventRecord");
     p->timed = true;
   }
-  FinalOut F{out->best_score, out->best_orient, out->angle_idx, out->xyz_out};
+  FinalOut F{out->best_score, out->best_orient, out->angle_idx, out->xyz_out, out->align_idx,
+             item_align};
   e = enqueue_finalize(A, F, maxn, mode, st);
   if (e != hipSuccess) return hip_fail(e, "finalize kernel");
   if (out->all_angle_idx && ligs->total_rot > 0) {
@@ -551,9 +607,21 @@ int dock_last_sweep_ms(dock_pocket *p, float *ms) {
 }
 
 size_t dock_workspace_size(int32_t n_ligands, int64_t total_rot, int n_orient, int angle_steps,
-                           int passes) {
-  if (n_ligands < 0 || total_rot < 0 || n_orient < 1 || angle_steps < 1 || passes < 1) return 0;
-  return ws_layout(n_ligands, total_rot, n_orient, angle_steps, passes).total;
+                           int passes, int n_align) {
+  if (n_ligands < 0 || total_rot < 0 || n_orient < 1 || angle_steps < 1 || passes < 1 ||
+      n_align < 0)
+    return 0;
+  return ws_layout(n_ligands, total_rot, n_orient, angle_steps, passes, n_align).total;
+}
+
+int dock_last_align_ms(dock_pocket *p, float *ms) {
+  g_last_error.clear();
+  if (!p || !ms) return fail(DOCK_E_INVAL, "NULL argument");
+  if (!p->align_timed) return fail(DOCK_E_STATE, "no aligned call with DOCK_FLAG_TIME_SWEEP yet");
+  DeviceGuard g(p->device);
+  hipError_t e = hipEventSynchronize(p->ev_align[1]);
+  if (e == hipSuccess) e = hipEventElapsedTime(ms, p->ev_align[0], p->ev_align[1]);
+  return e == hipSuccess ? DOCK_OK : hip_fail(e, "alignment timing");
 }
 
 int dock_init_pocket(const float *grid, int nx, int ny, int nz, const float origin[3],
@@ -591,6 +659,8 @@ int dock_init_pocket(const float *grid, int nx, int ny, int nz, const float orig
   if (e == hipSuccess) e = hipEventCreate(&p->ev_sweep[0]);
   if (e == hipSuccess) e = hipEventCreate(&p->ev_sweep[1]);
   if (e == hipSuccess) e = hipEventCreate(&p->ev_sweep[2]);
+  if (e == hipSuccess) e = hipEventCreate(&p->ev_align[0]);
+  if (e == hipSuccess) e = hipEventCreate(&p->ev_align[1]);
   if (e == hipSuccess) e = hipHostMalloc((void **)&p->h_work, 2 * sizeof(unsigned long long), 0);
   if (e == hipSuccess) e = hipMemcpyAsync(p->d_grid, grid, bytes, hipMemcpyHostToDevice, p->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
@@ -615,6 +685,8 @@ void dock_free_pocket(dock_pocket *p) {
     if (p->sync_ws) (void)hipFree(p->sync_ws);
     if (p->stream) (void)hipStreamDestroy(p->stream);
     for (hipEvent_t ev : p->ev_sweep)
+      if (ev) (void)hipEventDestroy(ev);
+    for (hipEvent_t ev : p->ev_align)
       if (ev) (void)hipEventDestroy(ev);
     if (p->h_work) (void)hipHostFree(p->h_work);
     if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
@@ -648,7 +720,7 @@ int dock_batch_async(dock_pocket *p, const dock_ligands *ligs, const float *orie
   std::lock_guard<std::mutex> lk(p->mu);
   if (!workspace) {
     size_t need = dock_workspace_size(ligs->n_ligands, ligs->total_rot, n_orient, angle_steps,
-                                      prm->passes);
+                                      prm->passes, prm->n_align);
     rc = grow(&p->ws, &p->ws_bytes, need);
     if (rc) return rc;
     workspace = p->ws;
@@ -717,6 +789,8 @@ static int run_sync(dock_pocket *p, const dock_ligands *ligs, const float *orien
   const int passes = prm->passes;
   for (int a = 0; a < n_orient * 12; ++a)
     if (!std::isfinite(orient[a])) return fail(DOCK_E_INVAL, "orientation table is not finite");
+  const int NAL = prm->n_align;
+  if (NAL > 0 && (rc = check_rotations_host(prm->align_rot, NAL)) != DOCK_OK) return rc;
   for (int64_t a = 0; a < NA * 3; ++a)
     if (!std::isfinite(ligs->xyz[a])) return fail(DOCK_E_INVAL, "coordinates are not finite");
   if (L == 0) return DOCK_OK;
@@ -734,12 +808,13 @@ static int run_sync(dock_pocket *p, const dock_ligands *ligs, const float *orien
                o_ai = take(2 * NR * passes), o_xo = take(12 * NA),
                o_as = out->all_scores ? take(4 * L * n_orient) : 0,
                o_aai = out->all_angle_idx ? take(2 * NR * passes * n_orient) : 0,
-               o_st = take(4 * L), o_fb = take(4 * L);
+               o_st = take(4 * L), o_fb = take(4 * L), o_rot = take(36 * (size_t)NAL),
+               o_ali = take(2 * L), o_aal = out->all_align_idx ? take(2 * L * n_orient) : 0;
   std::lock_guard<std::mutex> lk(p->mu);
   DeviceGuard g(p->device);
   rc = grow(&p->io, &p->io_bytes, off);
   if (rc) return rc;
-  const size_t need_ws = dock_workspace_size((int32_t)L, NR, n_orient, angle_steps, passes);
+  const size_t need_ws = dock_workspace_size((int32_t)L, NR, n_orient, angle_steps, passes, NAL);
   rc = grow(&p->sync_ws, &p->sync_ws_bytes, need_ws);
   if (rc) return rc;
   char *d = (char *)p->io;
@@ -757,6 +832,7 @@ static int run_sync(dock_pocket *p, const dock_ligands *ligs, const float *orien
   }
   if (NM > 0) h2d(o_mv, ligs->move_atoms, 2 * NM);
   h2d(o_or, orient, 48 * (size_t)n_orient);
+  if (NAL > 0) h2d(o_rot, prm->align_rot, 36 * (size_t)NAL);
   if (e != hipSuccess) return hip_fail(e, "batch upload");
   dock_ligands dl = *ligs;
   dl.atom_offset = (const int32_t *)(d + o_ao);
@@ -774,9 +850,12 @@ static int run_sync(dock_pocket *p, const dock_ligands *ligs, const float *orien
   dr.all_angle_idx = out->all_angle_idx ? (int16_t *)(d + o_aai) : nullptr;
   dr.status = (int32_t *)(d + o_st);
   dr.n_fallback = (int32_t *)(d + o_fb);
+  dr.align_idx = out->align_idx ? (int16_t *)(d + o_ali) : nullptr;
+  dr.all_align_idx = out->all_align_idx && NAL > 0 ? (int16_t *)(d + o_aal) : nullptr;
   dock_params pr = *prm;
   pr.max_atoms = max_n;
   pr.max_rot = max_r;
+  pr.align_rot = NAL > 0 ? (const float *)(d + o_rot) : nullptr;
   rc = enqueue_batch(p, &dl, (const float *)(d + o_or), n_orient, angle_steps, &pr, &dr,
                      p->sync_ws, p->sync_ws_bytes, st, emit_x, emit_t, emit_mask);
   if (rc) return rc;
@@ -791,6 +870,8 @@ static int run_sync(dock_pocket *p, const dock_ligands *ligs, const float *orien
   if (out->all_scores) d2h(out->all_scores, o_as, 4 * L * n_orient);
   if (out->all_angle_idx && NR > 0) d2h(out->all_angle_idx, o_aai, 2 * NR * passes * n_orient);
   d2h(out->status, o_st, 4 * L);
+  d2h(out->align_idx, o_ali, 2 * L);
+  if (NAL > 0) d2h(out->all_align_idx, o_aal, 2 * L * n_orient);
   if (prm->mode == DOCK_MODE_LEARNED) d2h(out->n_fallback, o_fb, 4 * L);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) return hip_fail(e, "batch run");
@@ -814,6 +895,7 @@ int dock_emit_profiles(dock_pocket *p, const dock_ligands *ligs, const float *or
   if (!p || !ligs || !orient || !prm || !x_out || !t_out || !mask_out)
     return fail(DOCK_E_INVAL, "NULL argument");
   if (prm->mode != DOCK_MODE_PLAIN) return fail(DOCK_E_INVAL, "profiles come from the plain sweep");
+  if (prm->n_align != 0) return fail(DOCK_E_INVAL, "profiles are emitted without alignment");
   dock_results none{};
   return run_sync(p, ligs, orient, n_orient, 256, prm, &none, x_out, t_out, mask_out);
 }

@@ -34,8 +34,9 @@ struct LigView {
 struct SweepArgs {
   GridView grid;
   LigView lig;
-  const float *orient;  // [n_orient][12]
+  const float *orient;  // [n_orient][12], or [n_ligands][n_orient][12] per item
   int n_orient;
+  int orient_stride;    // transforms per ligand in orient: 0 (one shared table) or n_orient
   int S;
   int passes;
   float r2;             // r_bump^2
@@ -65,6 +66,23 @@ struct FinalOut {
   int32_t *best_orient;
   int16_t *angle_idx;
   float *xyz_out;
+  int16_t *align_idx;          // optional [n_ligands]: alignment of the best orientation
+  const int16_t *item_align;   // [n_ligands][n_orient] when aligned, else NULL
+};
+
+// Rigid alignment search: every (ligand, orientation) item's starting pose is
+// scored under each rotation of the set (about the pose centroid) and the
+// best one is folded into a per-item rigid transform for the sweep.
+struct AlignArgs {
+  GridView grid;
+  LigView lig;
+  const float *orient;     // [n_orient][12]
+  int n_orient;
+  const float *rot;        // [n_align][9] row-major rotations
+  int n_align;
+  const int32_t *status;   // [n_ligands]; items of ligands with status != 0 are skipped
+  float *item_orient;      // out [n_ligands][n_orient][12]
+  int16_t *item_align;     // out [n_ligands][n_orient] chosen rotation (-1: skipped)
 };
 
 struct LaunchPlan {
@@ -83,5 +101,6 @@ hipError_t enqueue_sweep_pruned(const SweepArgs &A, int max_atoms, const LaunchP
                                 int n_cu, hipStream_t st);
 hipError_t enqueue_finalize(const SweepArgs &A, const FinalOut &F, int maxn, SweepMode mode,
                             hipStream_t st);
+hipError_t enqueue_align(const AlignArgs &A, int maxn, hipStream_t st);
 
 }  // namespace dock

@@ -94,7 +94,8 @@ __global__ void __launch_bounds__(kWave) learned_begin_kernel(LearnedArgs A) {
   for (int item = blockIdx.x; item < A.sw.n_items; item += gridDim.x) {
     const ItemInfo I = item_info(A, item);
     if (A.sw.status[I.l] != 0) continue;
-    stage_pose(W, A.sw.grid, A.sw.lig.xyz + 3 * (size_t)I.a0, I.n, A.sw.orient + 12 * I.o, lane);
+    stage_pose(W, A.sw.grid, A.sw.lig.xyz + 3 * (size_t)I.a0, I.n,
+               A.sw.orient + 12 * ((size_t)I.l * A.sw.orient_stride + I.o), lane);
     if (I.steps == 0) {
       finish_item(A, W, I, lane);
     } else {

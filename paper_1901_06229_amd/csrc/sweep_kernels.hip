@@ -152,7 +152,7 @@ __global__ void __launch_bounds__(WAVES *kWave)
     const int n = A.lig.atom_offset[l + 1] - a0;
     const int r0 = A.lig.rot_offset[l];
     const int R = A.lig.rot_offset[l + 1] - r0;
-    const float *T = A.orient + 12 * o;
+    const float *T = A.orient + 12 * ((size_t)l * A.orient_stride + o);
 
     for (int i = lane; i < n; i += kWave) {
       const float *p = A.lig.xyz + 3 * (size_t)(a0 + i);
@@ -257,13 +257,14 @@ __global__ void __launch_bounds__(kWave) finalize_kernel(SweepArgs A, FinalOut F
     if (lane == 0) {
       F.best_orient[l] = -1;
       F.best_score[l] = __int_as_float(0x7fc00000);
+      if (F.align_idx) F.align_idx[l] = -1;
     }
     return;
   }
   const int n = A.lig.atom_offset[l + 1] - a0;
   const int R = A.lig.rot_offset[l + 1] - r0;
   const int o = (int)key_index(key);
-  const float *T = A.orient + 12 * o;
+  const float *T = A.orient + 12 * ((size_t)l * A.orient_stride + o);
   for (int i = lane; i < n; i += kWave) {
     const float *p = A.lig.xyz + 3 * (size_t)(a0 + i);
     float3 x = orient_point(T, p[0], p[1], p[2]);
@@ -308,6 +309,7 @@ __global__ void __launch_bounds__(kWave) finalize_kernel(SweepArgs A, FinalOut F
   if (lane == 0) {
     F.best_orient[l] = o;
     F.best_score[l] = key_score(key);
+    if (F.align_idx) F.align_idx[l] = F.item_align ? F.item_align[(size_t)l * O + o] : (int16_t)-1;
   }
 }
 

@@ -59,7 +59,7 @@ __global__ void __launch_bounds__(WAVES *kWave)
     const int n = A.lig.atom_offset[l + 1] - a0;
     const int r0 = A.lig.rot_offset[l];
     const int R = A.lig.rot_offset[l + 1] - r0;
-    stage_pose(W, G, A.lig.xyz + 3 * (size_t)a0, n, A.orient + 12 * o, lane);
+    stage_pose(W, G, A.lig.xyz + 3 * (size_t)a0, n, A.orient + 12 * ((size_t)l * A.orient_stride + o), lane);
 
     const size_t kbase = ((size_t)r0 * O + (size_t)o * R) * A.passes;
     int16_t *kout = A.kstar + kbase;

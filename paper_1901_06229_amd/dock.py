@@ -35,12 +35,14 @@ class dock_ligands(ctypes.Structure):
 class dock_params(ctypes.Structure):
     _fields_ = [("r_bump", ctypes.c_float), ("passes", ctypes.c_int32), ("mode", ctypes.c_int32),
                 ("top_k", ctypes.c_int32), ("margin", ctypes.c_float), ("flags", ctypes.c_uint32),
-                ("max_atoms", ctypes.c_int32), ("max_rot", ctypes.c_int32)]
+                ("max_atoms", ctypes.c_int32), ("max_rot", ctypes.c_int32),
+                ("n_align", ctypes.c_int32), ("align_rot", _P)]
 
 
 class dock_results(ctypes.Structure):
     _fields_ = [("best_score", _P), ("best_orient", _P), ("angle_idx", _P), ("xyz_out", _P),
-                ("all_scores", _P), ("all_angle_idx", _P), ("status", _P), ("n_fallback", _P)]
+                ("all_scores", _P), ("all_angle_idx", _P), ("status", _P), ("n_fallback", _P),
+                ("align_idx", _P), ("all_align_idx", _P)]
 
 
 class dock_tune_entry(ctypes.Structure):
@@ -97,9 +99,11 @@ def load_library(path: str = None):
                                      c.POINTER(dock_params), c.POINTER(dock_results), _P,
                                      c.c_size_t, _P]
     lib.dock_batch_async.restype = c.c_int
-    lib.dock_workspace_size.argtypes = [c.c_int32, c.c_int64, c.c_int, c.c_int, c.c_int]
+    lib.dock_workspace_size.argtypes = [c.c_int32, c.c_int64, c.c_int, c.c_int, c.c_int, c.c_int]
     lib.dock_workspace_size.restype = c.c_size_t
     lib.dock_last_sweep_ms.argtypes = [_P, c.POINTER(c.c_float)]
+    lib.dock_last_align_ms.restype = c.c_int
+    lib.dock_last_align_ms.argtypes = [_P, c.POINTER(c.c_float)]
     lib.dock_last_sweep_ms.restype = c.c_int
     lib.dock_last_sweep_work.argtypes = [_P, c.POINTER(c.c_uint64), c.POINTER(c.c_uint64)]
     lib.dock_last_sweep_work.restype = c.c_int
@@ -191,16 +195,31 @@ def dock_free_pocket(p: Pocket):
     p.close()
 
 
+def _any_ptr(a):
+    if a is None:
+        return None
+    if hasattr(a, "data_ptr"):
+        return ctypes.c_void_p(a.data_ptr())
+    return _np_ptr(a)
+
+
 def make_params(r_bump=2.0, passes=1, mode=DOCK_MODE_PLAIN, top_k=16, margin=0.0, flags=0,
-                max_atoms=0, max_rot=0) -> dock_params:
+                max_atoms=0, max_rot=0, align=None) -> dock_params:
+    """align: optional [A, 3, 3] float32 rotation set (a contiguous numpy array for
+    dock_batch, a device tensor for dock_batch_async); the caller keeps it alive."""
+    n_align = 0 if align is None else int(align.shape[0])
     return dock_params(float(r_bump), int(passes), int(mode), int(top_k), float(margin),
-                       int(flags), int(max_atoms), int(max_rot))
+                       int(flags), int(max_atoms), int(max_rot), n_align, _any_ptr(align))
 
 
 def dock_batch(pocket: Pocket, ligs, orient, angle_steps: int, r_bump: float = 2.0,
                passes: int = 1, mode: int = DOCK_MODE_PLAIN, top_k: int = 16,
-               margin: float = 0.0, flags: int = 0, want_all: bool = False) -> dict:
-    """Synchronous batch on host arrays (``ligs``: any object with the CSR fields)."""
+               margin: float = 0.0, flags: int = 0, want_all: bool = False, align=None) -> dict:
+    """Synchronous batch on host arrays (``ligs``: any object with the CSR fields).
+
+    align: optional [A, 3, 3] rotation set; every restart is first aligned
+    rigidly to its best rotation (``align_idx`` per ligand, ``all_align_idx``
+    per item with want_all)."""
     lib = load_library()
     ao = _c(ligs.atom_offset, np.int32)
     xyz = _c(ligs.xyz, np.float32)
@@ -222,11 +241,17 @@ def dock_batch(pocket: Pocket, ligs, orient, angle_steps: int, r_bump: float = 2
         out["all_angle_idx"] = np.empty(max(NR * passes * O, 1), np.int16)
     if mode == DOCK_MODE_LEARNED:
         out["n_fallback"] = np.empty(max(L, 1), np.int32)
+    if align is not None:
+        align = _c(align, np.float32).reshape(-1, 3, 3)
+        out["align_idx"] = np.empty(max(L, 1), np.int16)
+        if want_all:
+            out["all_align_idx"] = np.empty((max(L, 1), O), np.int16)
     dr = dock_results(_np_ptr(out["best_score"]), _np_ptr(out["best_orient"]),
                       _np_ptr(out["angle_idx"]), _np_ptr(out["xyz"]),
                       _np_ptr(out.get("all_scores")), _np_ptr(out.get("all_angle_idx")),
-                      _np_ptr(out["status"]), _np_ptr(out.get("n_fallback")))
-    prm = make_params(r_bump, passes, mode, top_k, margin, flags)
+                      _np_ptr(out["status"]), _np_ptr(out.get("n_fallback")),
+                      _np_ptr(out.get("align_idx")), _np_ptr(out.get("all_align_idx")))
+    prm = make_params(r_bump, passes, mode, top_k, margin, flags, align=align)
     _check(lib.dock_batch(pocket.handle, ctypes.byref(dl), _np_ptr(orient), O, int(angle_steps),
                           ctypes.byref(prm), ctypes.byref(dr)), "dock_batch")
     out["angle_idx"] = out["angle_idx"][:NR * passes]
@@ -234,18 +259,28 @@ def dock_batch(pocket: Pocket, ligs, orient, angle_steps: int, r_bump: float = 2
     out["status"] = out["status"][:L]
     if want_all:
         out["all_angle_idx"] = out["all_angle_idx"][:NR * passes * O]
+    if align is not None:
+        out["align_idx"] = out["align_idx"][:L]
+        if want_all:
+            out["all_align_idx"] = out["all_align_idx"][:L]
     return out
 
 
 def dock_workspace_size(n_ligands: int, total_rot: int, n_orient: int, angle_steps: int,
-                        passes: int = 1) -> int:
+                        passes: int = 1, n_align: int = 0) -> int:
     return int(load_library().dock_workspace_size(n_ligands, total_rot, n_orient, angle_steps,
-                                                  passes))
+                                                  passes, n_align))
 
 
 def dock_last_sweep_ms(pocket: Pocket) -> float:
     ms = ctypes.c_float()
     _check(load_library().dock_last_sweep_ms(pocket.handle, ctypes.byref(ms)), "dock_last_sweep_ms")
+    return float(ms.value)
+
+
+def dock_last_align_ms(pocket: Pocket) -> float:
+    ms = ctypes.c_float()
+    _check(load_library().dock_last_align_ms(pocket.handle, ctypes.byref(ms)), "dock_last_align_ms")
     return float(ms.value)
 
 
@@ -310,7 +345,7 @@ def dock_batch_async(pocket: Pocket, dev: dict, orient_dev, angle_steps: int, ou
     dev: atom_offset, xyz, rot_offset, rot_axis, move_offset, move_atoms (device
     tensors) and the python ints n_ligands, total_atoms, total_rot, total_move.
     out: best_score, best_orient, angle_idx, xyz (device tensors) and optional
-    all_scores, all_angle_idx, status, n_fallback.
+    all_scores, all_angle_idx, status, n_fallback, align_idx, all_align_idx.
     """
     lib = load_library()
     dl = dock_ligands(int(dev["n_ligands"]), int(dev["total_atoms"]), int(dev["total_rot"]),
@@ -320,7 +355,8 @@ def dock_batch_async(pocket: Pocket, dev: dict, orient_dev, angle_steps: int, ou
     dr = dock_results(_tptr(out["best_score"]), _tptr(out["best_orient"]),
                       _tptr(out.get("angle_idx")), _tptr(out["xyz"]),
                       _tptr(out.get("all_scores")), _tptr(out.get("all_angle_idx")),
-                      _tptr(out.get("status")), _tptr(out.get("n_fallback")))
+                      _tptr(out.get("status")), _tptr(out.get("n_fallback")),
+                      _tptr(out.get("align_idx")), _tptr(out.get("all_align_idx")))
     n_orient = int(orient_dev.shape[0])
     ws_ptr = _tptr(workspace)
     ws_bytes = 0 if workspace is None else workspace.numel() * workspace.element_size()

@@ -74,10 +74,34 @@ def classify_step(tr, s: int, kg: int) -> str | None:
     return None
 
 
-def check_item(pocket, lig, orient, S, r_bump, passes, gpu_k, gpu_score, gpu_xyz=None):
-    """Replay one item along the GPU's choices; returns (counts, failures, dx, rel)."""
-    tr = oracle.trace_item(pocket, lig, orient, S, r_bump, passes, forced_k=gpu_k)
+def classify_align(tr, ag: int) -> str | None:
+    """The GPU's alignment choice against the reference's candidate scores."""
+    ao = int(tr.a_star)
+    if ag == ao:
+        return "exact"
+    if ag < 0 or ag >= len(tr.align_s):
+        return None
+    tol = tol_of(tr.align_s[ao])
+    if tr.align_s[ao] - tr.align_s[ag] <= tol:
+        return "tie"
+    if tr.align_hi[ag] + tol >= tr.align_lo[ao]:
+        return "ambiguous"
+    return None
+
+
+def check_item(pocket, lig, orient, S, r_bump, passes, gpu_k, gpu_score, gpu_xyz=None,
+               align=None, gpu_a=-1):
+    """Replay one item along the GPU's choices (its alignment first, if a
+    rotation set is given); returns (counts, failures, dx, rel)."""
+    tr = oracle.trace_item(pocket, lig, orient, S, r_bump, passes, forced_k=gpu_k, align=align,
+                           forced_a=int(gpu_a) if align is not None else -1)
     counts, fails = Counter(), []
+    if align is not None:
+        c = classify_align(tr, int(gpu_a))
+        if c is None:
+            fails.append(("align", int(gpu_a), int(tr.a_star)))
+        else:
+            counts["align_" + c] += 1
     for s, kg in enumerate(gpu_k):
         c = classify_step(tr, s, int(kg))
         if c is None:
@@ -103,12 +127,13 @@ def item_steps(ligs, l, o, O, passes, all_angle_idx):
 
 
 def check_batch(pocket, ligs, orient, S, res, r_bump=2.0, passes=1, ligands=None,
-                orients=None, threads=8) -> Report:
+                orients=None, threads=8, align=None) -> Report:
     """Check GPU results ``res`` (dock_batch output with want_all=True).
 
     ligands: ligand indices to check (default all); orients: orientation
     indices per ligand (default all) -- the winning orientation is always
-    checked, including its final coordinates.
+    checked, including its final coordinates.  align: the rotation set the
+    GPU run aligned with (its choices are in res["all_align_idx"]).
     """
     O = orient.shape[0]
     rep = Report()
@@ -128,11 +153,13 @@ def check_batch(pocket, ligs, orient, S, res, r_bump=2.0, passes=1, ligands=None
             if o == ob:
                 a0, a1 = ligs.atom_offset[l], ligs.atom_offset[l + 1]
                 xyz = res["xyz"][a0:a1]
-            jobs.append((l, o, lig, k, float(res["all_scores"][l, o]), xyz))
+            a = int(res["all_align_idx"][l, o]) if align is not None else -1
+            jobs.append((l, o, lig, k, float(res["all_scores"][l, o]), xyz, a))
 
     def run(job):
-        l, o, lig, k, sc, xyz = job
-        return (l, o) + check_item(pocket, lig, orient[o], S, r_bump, passes, k, sc, xyz)
+        l, o, lig, k, sc, xyz, a = job
+        return (l, o) + check_item(pocket, lig, orient[o], S, r_bump, passes, k, sc, xyz,
+                                   align=align, gpu_a=a)
 
     with ThreadPoolExecutor(max(1, threads)) as ex:
         for l, o, counts, fails, dx, rel in ex.map(run, jobs):
@@ -153,6 +180,8 @@ def check_batch(pocket, ligs, orient, S, res, r_bump=2.0, passes=1, ligands=None
             a = res["angle_idx"][int(ligs.rot_offset[l]) * passes:][:R * passes]
             if not np.array_equal(a, item_steps(ligs, l, ob, O, passes, res["all_angle_idx"])):
                 rep.failures.append(("angle_idx", l))
+        if align is not None and ob >= 0 and res["align_idx"][l] != res["all_align_idx"][l, ob]:
+            rep.failures.append(("align_idx", l))
     return rep
 
 

@@ -39,7 +39,10 @@ def test_strerror_and_workspace_size(lib):
     b = dock.dock_workspace_size(100, 700, 256, 512)
     assert 0 < a < b
     assert a >= 700 * 256 * 2 + 100 * 8
-    assert lib.dock_workspace_size(-1, 0, 1, 1, 1) == 0
+    assert lib.dock_workspace_size(-1, 0, 1, 1, 1, 0) == 0
+    assert lib.dock_workspace_size(1, 0, 1, 1, 1, -1) == 0
+    # alignment: a 48-byte transform and a 2-byte index per item
+    assert dock.dock_workspace_size(100, 700, 256, 256, n_align=64) - a == 50 * 100 * 256
 
 
 def test_null_arguments_are_rejected_on_the_host(lib):
