@@ -90,6 +90,18 @@ def test_identity_set_is_the_unaligned_sweep(pockets):
     assert (b["align_idx"] == 0).all() and (b["all_align_idx"] == 0).all()
 
 
+def test_translated_restarts(pockets):
+    """Restarts translated up to 9 A from the first one: their atoms leave the
+    staged cube of grid values, so lanes mix the LDS and global-memory routes."""
+    ligs = synth.ligands(2, count=16, first=900)
+    orient = synth.orientations(2, 24).copy()
+    rng = np.random.default_rng(5)
+    orient[1:, 9:] = rng.uniform(-9.0, 9.0, size=(23, 3)).astype(np.float32)
+    rots = synth.align_rotations(2, 64)
+    p, res = _run(pockets, 2, ligs, orient, 64, rots)
+    _check(p, ligs, orient, 64, res, rots)
+
+
 def test_max_size_ligand_alignment(pockets):
     """A 256-atom ligand (the largest LDS staging) with 130 rotations."""
     p, h = pockets(5)
