@@ -36,7 +36,6 @@ struct SweepArgs {
   LigView lig;
   const float *orient;  // [n_orient][12], or [n_ligands][n_orient][12] per item
   int n_orient;
-  int orient_stride;    // transforms per ligand in orient: 0 (one shared table) or n_orient
   int S;
   int passes;
   float r2;             // r_bump^2
@@ -59,6 +58,9 @@ struct SweepArgs {
   uint16_t *emit_x;
   uint16_t *emit_t;
   uint32_t *emit_mask;
+  // transforms per ligand in orient: 0 (one shared table) or n_orient (one
+  // per item); last, so the fields above keep their kernel-argument offsets
+  int orient_stride;
 };
 
 struct FinalOut {
