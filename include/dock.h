@@ -185,7 +185,10 @@ int dock_batch(dock_pocket *p, const dock_ligands *ligs, const float *orient,
  * Per-ligand input errors are found on the device: such ligands are skipped,
  * get best_orient = -1 and, if out->status is set, their DOCK_E_* code.
  * workspace: device memory of at least dock_workspace_size() bytes, or NULL
- * to let the library allocate (and cache on the handle) its own. */
+ * to let the library allocate (and cache on the handle) its own.
+ * Every array must be device-accessible (device, managed, pinned host or
+ * unified memory): a pageable host pointer is rejected with DOCK_E_INVAL
+ * before anything is enqueued. */
 int dock_batch_async(dock_pocket *p, const dock_ligands *ligs,
                      const float *orient, int n_orient, int angle_steps,
                      const dock_params *prm, dock_results *out,
@@ -269,7 +272,8 @@ void dock_mlp_free(dock_mlp *m);
 int dock_mlp_get_params(dock_mlp *m, float *host_params);
 int dock_mlp_set_params(dock_mlp *m, const float *host_params);
 
-/* y[rows][256] (FP32) = network(x[rows][64]). */
+/* y[rows][256] (FP32) = network(x[rows][64]).  x and y must be
+ * device-accessible (else DOCK_E_INVAL, nothing enqueued). */
 int dock_mlp_forward(dock_mlp *m, const uint16_t *x_bf16, int rows, float *y, void *stream);
 
 /* Loss = mean over rows x 256 of (y - t)^2 and its gradient w.r.t. the packed

@@ -17,6 +17,8 @@
 #include <vector>
 
 #include "dock.h"
+#include <utility>
+
 #include "dock_internal.h"
 #include "learned_internal.h"
 #include "mlp_internal.h"
@@ -87,6 +89,21 @@ int abi_fail(int code, const char *fmt, ...) {
   va_end(ap);
   g_last_error = buf;
   return code;
+}
+
+// DOCK_OK if p (non-NULL) is memory the device can read and write: device,
+// managed, pinned host or unified allocations.  Pageable host memory is
+// rejected here, before any launch, instead of faulting a kernel.  A failed
+// query leaves no sticky error behind for later launch checks.
+int abi_check_device(const void *p, const char *what) {
+  if (!p) return DOCK_OK;
+  hipPointerAttribute_t a{};
+  const hipError_t e = hipPointerGetAttributes(&a, p);
+  if (e != hipSuccess) (void)hipGetLastError();
+  if (e != hipSuccess || (a.type != hipMemoryTypeDevice && a.type != hipMemoryTypeManaged &&
+                          a.type != hipMemoryTypeHost && a.type != hipMemoryTypeUnified))
+    return abi_fail(DOCK_E_INVAL, "%s is not device-accessible memory", what);
+  return DOCK_OK;
 }
 }  // namespace dock
 
@@ -717,6 +734,22 @@ int dock_batch_async(dock_pocket *p, const dock_ligands *ligs, const float *orie
     return fail(DOCK_E_INVAL, "result array is NULL");
   if (ligs->total_rot > 0 && !out->angle_idx) return fail(DOCK_E_INVAL, "angle_idx is NULL");
   DeviceGuard g(p->device);
+  {
+    const bool rot = ligs->total_rot > 0, mv = ligs->total_move > 0, al = prm->n_align > 0;
+    const std::pair<const void *, const char *> ptrs[] = {
+        {ligs->atom_offset, "atom_offset"}, {ligs->xyz, "xyz"}, {ligs->rot_offset, "rot_offset"},
+        {rot ? ligs->rot_axis : nullptr, "rot_axis"}, {rot ? ligs->move_offset : nullptr, "move_offset"},
+        {mv ? ligs->move_atoms : nullptr, "move_atoms"}, {orient, "orient"},
+        {al ? prm->align_rot : nullptr, "align_rot"}, {out->best_score, "best_score"},
+        {out->best_orient, "best_orient"}, {rot ? out->angle_idx : nullptr, "angle_idx"},
+        {out->xyz_out, "xyz_out"}, {out->all_scores, "all_scores"},
+        {out->all_angle_idx, "all_angle_idx"}, {out->status, "status"},
+        {out->n_fallback, "n_fallback"}, {out->align_idx, "align_idx"},
+        {al ? out->all_align_idx : nullptr, "all_align_idx"}, {workspace, "workspace"}};
+    if (ligs->n_ligands > 0)
+      for (const auto &q : ptrs)
+        if ((rc = abi_check_device(q.first, q.second)) != DOCK_OK) return rc;
+  }
   std::lock_guard<std::mutex> lk(p->mu);
   if (!workspace) {
     size_t need = dock_workspace_size(ligs->n_ligands, ligs->total_rot, n_orient, angle_steps,
@@ -896,6 +929,13 @@ int dock_emit_profiles(dock_pocket *p, const dock_ligands *ligs, const float *or
     return fail(DOCK_E_INVAL, "NULL argument");
   if (prm->mode != DOCK_MODE_PLAIN) return fail(DOCK_E_INVAL, "profiles come from the plain sweep");
   if (prm->n_align != 0) return fail(DOCK_E_INVAL, "profiles are emitted without alignment");
+  {
+    DeviceGuard g(p->device);
+    int rc = abi_check_device(x_out, "x_out");
+    if (rc == DOCK_OK) rc = abi_check_device(t_out, "t_out");
+    if (rc == DOCK_OK) rc = abi_check_device(mask_out, "mask_out");
+    if (rc) return rc;
+  }
   dock_results none{};
   return run_sync(p, ligs, orient, n_orient, 256, prm, &none, x_out, t_out, mask_out);
 }

@@ -18,6 +18,7 @@ using namespace dock;
 
 namespace dock {
 int abi_fail(int code, const char *fmt, ...);  // dock_abi.hip (thread-local last error)
+int abi_check_device(const void *p, const char *what);  // dock_abi.hip
 }
 
 struct dock_mlp {
@@ -195,8 +196,11 @@ int dock_mlp_set_params(dock_mlp *n, const float *host_params) {
 int dock_mlp_forward(dock_mlp *n, const uint16_t *x_bf16, int M, float *y, void *stream) {
   if (!n || !x_bf16 || !y) return abi_fail(DOCK_E_INVAL, "NULL argument");
   if (M < 64 || M % 64) return abi_fail(DOCK_E_INVAL, "rows must be a positive multiple of 64");
+  int rc = abi_check_device(x_bf16, "x");
+  if (rc == DOCK_OK) rc = abi_check_device(y, "y");
+  if (rc) return rc;
   std::lock_guard<std::mutex> lk(n->mu);
-  int rc = ensure_rows(n, M);
+  rc = ensure_rows(n, M);
   if (rc) return rc;
   hipStream_t st = (hipStream_t)stream;
   hipError_t e = mlp_infer(x_bf16, M, n->wb, n->w, y, st);
@@ -207,8 +211,12 @@ int dock_mlp_loss_grad(dock_mlp *n, const uint16_t *x_bf16, const uint16_t *t_bf
                        float *grad_out, float *loss_out, void *stream) {
   if (!n || !x_bf16 || !t_bf16) return abi_fail(DOCK_E_INVAL, "NULL argument");
   if (M < 64 || M % 64) return abi_fail(DOCK_E_INVAL, "rows must be a positive multiple of 64");
+  int rc = abi_check_device(x_bf16, "x");
+  if (rc == DOCK_OK) rc = abi_check_device(t_bf16, "t");
+  if (rc == DOCK_OK) rc = abi_check_device(grad_out, "grad_out");
+  if (rc) return rc;
   std::lock_guard<std::mutex> lk(n->mu);
-  int rc = ensure_rows(n, M);
+  rc = ensure_rows(n, M);
   if (rc) return rc;
   hipStream_t st = (hipStream_t)stream;
   hipError_t e = mlp_forward(x_bf16, M, n->wb, n->w, n->z1, n->a1, n->z2, n->a2, n->z3, n->a3,

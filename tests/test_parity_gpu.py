@@ -280,6 +280,35 @@ def _device_batch(ligs, orient, S, torch):
     return d, torch.from_numpy(orient).to(dev), out
 
 
+def test_async_rejects_host_memory(pockets):
+    """Pageable host arrays passed to the device-array entry point are refused
+    on the host before anything is enqueued.  The workspace is also too small,
+    so even a missed check would stop before any launch."""
+    import torch
+    p, h = pockets(2)
+    ligs = synth.ligands(2, count=8, first=300)
+    orient = synth.orientations(2, 4)
+    d, od, out = _device_batch(ligs, orient, 32, torch)
+    tiny = torch.empty(256, dtype=torch.uint8, device="cuda:0")
+    prm = dock.make_params(max_atoms=int(np.diff(ligs.atom_offset).max()))
+    with pytest.raises(dock.DockError) as e:
+        dock.dock_batch_async(h, d, torch.from_numpy(orient), 32, out, prm, workspace=tiny)
+    assert e.value.code == dock.DOCK_E_INVAL and "orient is not device-accessible" in str(e.value)
+    host_rot = torch.from_numpy(synth.align_rotations(2, 4))
+    with pytest.raises(dock.DockError) as e:
+        dock.dock_batch_async(h, d, od, 32, out, dock.make_params(align=host_rot), workspace=tiny)
+    assert "align_rot is not device-accessible" in str(e.value)
+    bad_out = dict(out, xyz=torch.empty(int(ligs.atom_offset[-1]), 3))
+    with pytest.raises(dock.DockError) as e:
+        dock.dock_batch_async(h, d, od, 32, bad_out, prm, workspace=tiny)
+    assert "xyz_out is not device-accessible" in str(e.value)
+    # with device arrays the same call fails only on the workspace size
+    with pytest.raises(dock.DockError) as e:
+        dock.dock_batch_async(h, d, od, 32, out, prm, workspace=tiny)
+    assert "workspace too small" in str(e.value)
+    torch.cuda.synchronize()
+
+
 def test_async_and_graph_replay_match_sync(pockets):
     """dock_batch_async on device tensors, eager and as a replayed HIP graph
     (several replays with eager work and synchronisation in between), against
