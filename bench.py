@@ -331,6 +331,12 @@ def main():
                     help="waves per block of the sweep (0: the most resident waves)")
     ap.add_argument("--claim", type=int, default=32,
                     help="most items a wave takes per work-queue atomic")
+    ap.add_argument("--autotune", type=int, default=None,
+                    help="time every launch mapping on this many sampled ligands first and keep "
+                         "the fastest (default: 2000 for the uneven-batch workload, else off)")
+    ap.add_argument("--graph", action=argparse.BooleanOptionalAction, default=None,
+                    help="replay the batch's launch sequence as a captured HIP graph "
+                         "(default: on for the uneven-batch workload)")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-proposal comparison")
     ap.add_argument("--align", type=int, default=ALIGN_ROTATIONS,
                     help="rotations of the rigid-alignment leg (0: skip it)")
@@ -375,8 +381,18 @@ def main():
     ws = torch.empty(dock.dock_workspace_size(L, NR, O, S), dtype=torch.uint8, device=dev)
     max_atoms = int(np.diff(ligs.atom_offset).max())
     flags = dock.DOCK_FLAG_TIME_SWEEP | (dock.DOCK_FLAG_DIRECT_BUMP if args.bump == "direct" else 0)
+    autotune = args.autotune if args.autotune is not None else (2000 if cfg == 3 else 0)
+    graph = args.graph if args.graph is not None else cfg == 3
+    if graph:
+        flags |= dock.DOCK_FLAG_GRAPH
     prm = dock.make_params(r_bump=synth.R_BUMP, max_atoms=max_atoms, flags=flags)
     dock.dock_set_launch(h, args.waves, 0, args.claim)
+    tune = None
+    if autotune > 0:
+        log(f"autotuning the launch mapping on {autotune} sampled ligands")
+        tune = dock.dock_autotune(h, ligs, orient, S, sample_ligands=min(autotune, L), seed=1,
+                                  r_bump=synth.R_BUMP, flags=flags & dock.DOCK_FLAG_DIRECT_BUMP)
+    launch = dict(zip(("waves_per_block", "blocks_per_cu", "items_per_claim"), dock.dock_get_launch(h)))
     stream = torch.cuda.Stream()
     torch.cuda.synchronize()
 
@@ -412,7 +428,8 @@ def main():
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * elapsed / args.steps, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic", "mode": "plain", "bump": args.bump,
-        "launch": {"waves_per_block": args.waves, "items_per_claim": args.claim},
+        "launch": dict(launch, autotuned=tune is not None, graph=graph,
+                       **({"tune_entries": len(tune)} if tune else {})),
         "config": {"workload": WORKLOADS[cfg] if L == preset["n_ligands"] else
                    WORKLOADS[cfg] + f" (ligands overridden to {L})",
                    "n_ligands": L, "n_orient": O, "angle_steps": S, "r_bump": synth.R_BUMP},
@@ -422,6 +439,8 @@ def main():
                                                        and L == preset["n_ligands"]) else None,
                      "kernel": "sweep_pruned_kernel" if args.bump == "pruned" else "sweep_kernel",
                      "kernel_ms": round(1e3 * mean_s, 3),
+                     **({"timed": "around each replayed graph (preparation, sweep, finalize)"}
+                        if graph else {}),
                      "work": (f"lane-ops: {OPS_CAND} per candidate pair per rotamer step + "
                               f"{OPS_ARC} per kept pair (clash arc) + {OPS_EVAL} per (moving atom, "
                               "non-bumping angle) evaluation")

@@ -200,12 +200,15 @@ size_t dock_workspace_size(int32_t n_ligands, int64_t total_rot, int n_orient,
                            int angle_steps, int passes, int n_align);
 
 /* Duration in ms of the sweep kernel of the last call on this handle that
- * set DOCK_FLAG_TIME_SWEEP (waits for that kernel to finish).  Errors:
+ * set DOCK_FLAG_TIME_SWEEP (waits for that kernel to finish).  A call
+ * replayed as a HIP graph (DOCK_FLAG_GRAPH) is timed around the whole graph
+ * (batch preparation, alignment, sweep and finalize).  Errors:
  * DOCK_E_INVAL (NULL), DOCK_E_STATE (no timed call yet), DOCK_E_DEVICE. */
 int dock_last_sweep_ms(dock_pocket *p, float *ms);
 
 /* Duration in ms of the alignment kernels of the last call on this handle
- * that set DOCK_FLAG_TIME_SWEEP and n_align > 0 (waits for them).  Errors:
+ * that set DOCK_FLAG_TIME_SWEEP and n_align > 0, not replayed as a HIP graph
+ * (waits for them).  Errors:
  * DOCK_E_INVAL (NULL), DOCK_E_STATE (no such call yet), DOCK_E_DEVICE. */
 int dock_last_align_ms(dock_pocket *p, float *ms);
 

@@ -299,7 +299,7 @@ int grow_learned(dock_pocket *p, int64_t items, int nmax, int tiles) {
 int enqueue_batch(dock_pocket *p, const dock_ligands *ligs, const float *orient, int O, int S,
                   const dock_params *prm, const dock_results *out, void *ws, size_t ws_bytes,
                   hipStream_t st, uint16_t *emit_x = nullptr, uint16_t *emit_t = nullptr,
-                  uint32_t *emit_mask = nullptr) {
+                  uint32_t *emit_mask = nullptr, bool events = true) {
   const int64_t L = ligs->n_ligands;
   const int max_atoms = prm->max_atoms > 0 ? prm->max_atoms : DOCK_MAX_ATOMS;
   if (L * (int64_t)O >= ((int64_t)1 << 31)) return fail(DOCK_E_LIMIT, "n_ligands * n_orient >= 2^31");
@@ -335,6 +335,9 @@ int enqueue_batch(dock_pocket *p, const dock_ligands *ligs, const float *orient,
   A.n_items = (int32_t)(L * O);
   A.claim = p->plan.items_per_claim;
   const bool timed = (prm->flags & DOCK_FLAG_TIME_SWEEP) != 0;
+  // Timing events bracket the kernels only in eager calls: recorded inside a
+  // captured graph they do not, so a graph is timed around its launch.
+  const bool ev = timed && events;
   A.work = timed ? (unsigned long long *)(A.small + 4) : nullptr;
   A.keys = (unsigned long long *)(base + w.keys);
   A.kstar = (int16_t *)(base + w.kstar);
@@ -361,10 +364,10 @@ int enqueue_batch(dock_pocket *p, const dock_ligands *ligs, const float *orient,
     AA.status = A.status;
     AA.item_orient = (float *)(base + w.item_orient);
     AA.item_align = (int16_t *)(base + w.item_align);
-    if (timed && (e = hipEventRecord(p->ev_align[0], st)) != hipSuccess)
+    if (ev && (e = hipEventRecord(p->ev_align[0], st)) != hipSuccess)
       return hip_fail(e, "hipEventRecord");
     if ((e = enqueue_align(AA, maxn, st)) != hipSuccess) return hip_fail(e, "alignment kernel");
-    if (timed) {
+    if (ev) {
       if ((e = hipEventRecord(p->ev_align[1], st)) != hipSuccess) return hip_fail(e, "hipEventRecord");
       p->align_timed = true;
     }
@@ -406,7 +409,7 @@ int enqueue_batch(dock_pocket *p, const dock_ligands *ligs, const float *orient,
     LA.top_k = prm->top_k;
     LA.margin = prm->margin;
     LA.n_fallback = nfb;
-    if (timed && (e = hipEventRecord(p->ev_sweep[0], st)) != hipSuccess)
+    if (ev && (e = hipEventRecord(p->ev_sweep[0], st)) != hipSuccess)
       return hip_fail(e, "hipEventRecord");
     if ((e = enqueue_learned_begin(LA, p->n_cu, st)) != hipSuccess)
       return hip_fail(e, "learned begin kernel");
@@ -418,11 +421,12 @@ int enqueue_batch(dock_pocket *p, const dock_ligands *ligs, const float *orient,
       if (e != hipSuccess) return hip_fail(e, "learned step");
     }
     if (timed) {
-      if ((e = hipEventRecord(p->ev_sweep[1], st)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+      if (ev && (e = hipEventRecord(p->ev_sweep[1], st)) != hipSuccess)
+        return hip_fail(e, "hipEventRecord");
       e = hipMemcpyAsync(p->h_work, A.small + 4, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st);
-      if (e == hipSuccess) e = hipEventRecord(p->ev_sweep[2], st);
+      if (e == hipSuccess && ev) e = hipEventRecord(p->ev_sweep[2], st);
       if (e != hipSuccess) return hip_fail(e, "timing");
-      p->timed = true;
+      if (ev) p->timed = true;
     }
     FinalOut F{out->best_score, out->best_orient, out->angle_idx, out->xyz_out, out->align_idx,
                item_align};
@@ -436,7 +440,7 @@ int enqueue_batch(dock_pocket *p, const dock_ligands *ligs, const float *orient,
     }
     return DOCK_OK;
   }
-  if (timed && (e = hipEventRecord(p->ev_sweep[0], st)) != hipSuccess)
+  if (ev && (e = hipEventRecord(p->ev_sweep[0], st)) != hipSuccess)
     return hip_fail(e, "hipEventRecord");
   const SweepMode mode = (prm->flags & DOCK_FLAG_DIRECT_BUMP) ? kSweepDirect : kSweepPruned;
   if (mode == kSweepDirect)
@@ -445,11 +449,12 @@ int enqueue_batch(dock_pocket *p, const dock_ligands *ligs, const float *orient,
     e = enqueue_sweep_pruned(A, max_atoms, p->plan, p->n_cu, st);
   if (e != hipSuccess) return hip_fail(e, "sweep kernel");
   if (timed) {
-    if ((e = hipEventRecord(p->ev_sweep[1], st)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+    if (ev && (e = hipEventRecord(p->ev_sweep[1], st)) != hipSuccess)
+      return hip_fail(e, "hipEventRecord");
     e = hipMemcpyAsync(p->h_work, A.small + 4, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st);
     if (e != hipSuccess) return hip_fail(e, "copy pair count");
-    if ((e = hipEventRecord(p->ev_sweep[2], st)) != hipSuccess) return hip_fail(e, "hipEventRecord");
-    p->timed = true;
+    if (ev && (e = hipEventRecord(p->ev_sweep[2], st)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+    if (ev) p->timed = true;
   }
   FinalOut F{out->best_score, out->best_orient, out->angle_idx, out->xyz_out, out->align_idx,
              item_align};
@@ -788,7 +793,7 @@ int dock_batch_async(dock_pocket *p, const dock_ligands *ligs, const float *orie
     if ((e = hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed)) != hipSuccess)
       return hip_fail(e, "hipStreamBeginCapture");
     rc = enqueue_batch(p, ligs, orient, n_orient, angle_steps, prm, out, workspace,
-                       workspace_bytes, st);
+                       workspace_bytes, st, nullptr, nullptr, nullptr, false);
     hipGraph_t graph = nullptr;
     e = hipStreamEndCapture(st, &graph);
     if (rc) {
@@ -805,7 +810,16 @@ int dock_batch_async(dock_pocket *p, const dock_ligands *ligs, const float *orie
     p->graph_exec = exec;
     p->graph_key = key;
   }
+  const bool timed = (prm->flags & DOCK_FLAG_TIME_SWEEP) != 0;
+  if (timed && (e = hipEventRecord(p->ev_sweep[0], st)) != hipSuccess)
+    return hip_fail(e, "hipEventRecord");
   if ((e = hipGraphLaunch(p->graph_exec, st)) != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+  if (timed) {
+    if ((e = hipEventRecord(p->ev_sweep[1], st)) != hipSuccess ||
+        (e = hipEventRecord(p->ev_sweep[2], st)) != hipSuccess)
+      return hip_fail(e, "hipEventRecord");
+    p->timed = true;
+  }
   return DOCK_OK;
 }
 

@@ -280,6 +280,42 @@ def _device_batch(ligs, orient, S, torch):
     return d, torch.from_numpy(orient).to(dev), out
 
 
+def test_graph_replay_with_sweep_timing(pockets):
+    """The benchmark's uneven-batch mode: a replayed HIP graph that also records
+    the sweep's timing events and work counters.  Every replay matches the
+    eager call and reports its own kernel time and counters."""
+    import torch
+    p, h = pockets(2)
+    ligs = synth.ligands(3, count=300, first=100)
+    orient = synth.orientations(2, 16)
+    d, od, out = _device_batch(ligs, orient, 128, torch)
+    ws = torch.empty(dock.dock_workspace_size(ligs.n_ligands, d["total_rot"], 16, 128),
+                     dtype=torch.uint8, device="cuda:0")
+    st = torch.cuda.Stream()
+    mx = int(np.diff(ligs.atom_offset).max())
+    names = ("best_score", "best_orient", "angle_idx", "xyz", "all_scores", "all_angle_idx")
+    eager = dock.make_params(max_atoms=mx, flags=dock.DOCK_FLAG_TIME_SWEEP)
+    for _ in range(2):  # the first launch also loads the kernels' code
+        dock.dock_batch_async(h, d, od, 128, out, eager, workspace=ws, stream=st)
+    st.synchronize()
+    ref = {k: out[k].cpu().numpy() for k in names}
+    ref_work = dock.dock_last_sweep_work(h)
+    sweep_ms = dock.dock_last_sweep_ms(h)
+    gprm = dock.make_params(max_atoms=mx, flags=dock.DOCK_FLAG_TIME_SWEEP | dock.DOCK_FLAG_GRAPH)
+    for _ in range(3):
+        for k in names:
+            out[k].fill_(0)
+        torch.cuda.synchronize()
+        dock.dock_batch_async(h, d, od, 128, out, gprm, workspace=ws, stream=st)
+        ms = dock.dock_last_sweep_ms(h)
+        # the replayed graph is timed as a whole: the sweep dominates it
+        assert 0.9 * sweep_ms <= ms <= 1.5 * sweep_ms + 0.5, (ms, sweep_ms)
+        assert dock.dock_last_sweep_work(h) == ref_work
+        st.synchronize()
+        for k in names:
+            assert np.array_equal(ref[k], out[k].cpu().numpy()), k
+
+
 def test_async_rejects_host_memory(pockets):
     """Pageable host arrays passed to the device-array entry point are refused
     on the host before anything is enqueued.  The workspace is also too small,
