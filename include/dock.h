@@ -291,9 +291,11 @@ int dock_mlp_adam(dock_mlp *m, float lr, float beta1, float beta2, float eps, vo
 
 /* Install a trained network as the pocket's learned proposal (device copy of
  * its current weights; the network may be freed afterwards).  Needed by
- * DOCK_MODE_LEARNED, which also requires angle_steps = 256 x 2^j (256 output
- * bins, bin b holding the S/256 steps of angles [2 pi b/256, 2 pi (b+1)/256)),
- * 1 <= top_k <= 63 and top_k x S/256 + 1 <= 512; otherwise DOCK_E_LIMIT. */
+ * DOCK_MODE_LEARNED.  The network's 256 output bins map onto any angle_steps
+ * S: bin b holds the steps of angles in [2 pi b/256, 2 pi (b+1)/256), that is
+ * k in [ceil(b S/256), ceil((b+1) S/256)) (none for some bins when S < 256).
+ * Learned mode requires 1 <= top_k <= 63 and top_k x ceil(S/256) + 1 <= 512;
+ * otherwise DOCK_E_LIMIT. */
 int dock_load_proposal(dock_pocket *p, dock_mlp *m);
 
 /* Training data for the learned proposal: run the plain sweep (S = 256) on a

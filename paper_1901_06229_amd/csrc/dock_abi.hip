@@ -306,11 +306,9 @@ int enqueue_batch(dock_pocket *p, const dock_ligands *ligs, const float *orient,
   const bool learned = prm->mode == DOCK_MODE_LEARNED;
   if (learned) {
     if (!p->prop_wb) return fail(DOCK_E_STATE, "no learned proposal loaded (dock_load_proposal)");
-    if (S % 256 != 0 || ((S / 256) & (S / 256 - 1)) != 0)
-      return fail(DOCK_E_LIMIT, "learned mode needs angle_steps = 256 x a power of two (256 bins)");
     if (prm->top_k < 1 || prm->top_k > 63) return fail(DOCK_E_LIMIT, "top_k outside [1, 63]");
-    if (prm->top_k * (S / 256) + 1 > 512)
-      return fail(DOCK_E_LIMIT, "top_k x angle_steps / 256 must be below 512");
+    if (prm->top_k * ((S + 255) / 256) + 1 > 512)
+      return fail(DOCK_E_LIMIT, "top_k x ceil(angle_steps / 256) must be below 512");
     if (prm->max_rot < 0 || prm->max_rot > DOCK_MAX_ROT) return fail(DOCK_E_LIMIT, "max_rot outside [0, 255]");
   }
   WsLayout w = ws_layout(L, ligs->total_rot, O, S, prm->passes, prm->n_align);
@@ -381,7 +379,7 @@ int enqueue_batch(dock_pocket *p, const dock_ligands *ligs, const float *orient,
   }
   if (learned) {
     const int nmax = (max_atoms + 15) / 16 * 16;
-    int rc = grow_learned(p, L * O, nmax, S / 64);
+    int rc = grow_learned(p, L * O, nmax, (S + 63) / 64);
     if (rc) return rc;
     int32_t *nfb = out->n_fallback;
     if (!nfb) {
@@ -403,9 +401,7 @@ int enqueue_batch(dock_pocket *p, const dock_ligands *ligs, const float *orient,
     LA.feat = p->lw_feat;
     LA.valid = p->lw_valid;
     LA.pred = p->lw_z[3];
-    LA.tiles = S / 64;
-    LA.bin_shift = 0;
-    while ((256 << LA.bin_shift) < S) ++LA.bin_shift;
+    LA.tiles = (S + 63) / 64;
     LA.top_k = prm->top_k;
     LA.margin = prm->margin;
     LA.n_fallback = nfb;

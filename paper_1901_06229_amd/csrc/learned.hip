@@ -5,7 +5,9 @@
 //   begin:  stage the rigid pose, set up the first rotamer, write its 64
 //           features and its exact validity mask (bump test of all angles);
 //   MLP:    predicted score landscape over 256 bins for every item (bin b
-//           covers the S/256 steps of angles [2 pi b/256, 2 pi (b+1)/256));
+//           holds the steps k whose angle 2 pi k/S lies in
+//           [2 pi b/256, 2 pi (b+1)/256): k in [ceil(b S/256), ceil((b+1) S/256)),
+//           none, one or several depending on S);
 //   step:   nominate the top_k bins by prediction among the bins holding a
 //           valid step, score every valid step of those bins (plus angle 0)
 //           exactly and keep the best; if the predicted margin (best minus
@@ -25,7 +27,7 @@
 namespace dock {
 
 // Compaction capacity of the learned kernels' waves: 8 tiles = 512 steps,
-// enough for top_k nominated bins of S/256 steps plus angle 0.
+// enough for top_k nominated bins of up to ceil(S/256) steps plus angle 0.
 constexpr int kLearnedTiles = 8;
 
 // Orderable 32-bit key of (prediction, -bin) for the nomination rounds.
@@ -63,10 +65,12 @@ __device__ __forceinline__ void write_step_inputs(const LearnedArgs &A, const Wa
   const GridView G = A.sw.grid;
   A.feat[(size_t)item * 64 + lane] = f32_to_bf16(rotamer_feature(W, RS, G, lane));
   rotamer_bump_mask(W, RS, A.sw.r2, A.sw.r2 + kPruneMargin, A.sw.S, lane);
-  // lane t writes the valid mask of tile t (S is a multiple of 64)
+  // lane t writes the valid mask of tile t; steps from S on are not angles
   if (lane < A.tiles) {
     const uint64_t bumps = ((uint64_t)W.BM[2 * lane + 1] << 32) | (uint64_t)W.BM[2 * lane];
-    A.valid[(size_t)item * A.tiles + lane] = ~bumps;
+    const int left = A.sw.S - lane * kWave;
+    const uint64_t range = left >= kWave ? ~0ull : ((1ull << left) - 1ull);
+    A.valid[(size_t)item * A.tiles + lane] = ~bumps & range;
   }
 }
 
@@ -132,7 +136,7 @@ __global__ void __launch_bounds__(kWave) learned_step_kernel(LearnedArgs A, int 
   const GridView G = A.sw.grid;
   const GridScaled GS = grid_scaled(G);
   const __amdgpu_buffer_rsrc_t grsrc = grid_rsrc(G);
-  const int f = 1 << A.bin_shift;  // steps per bin
+  const int S = A.sw.S;
   for (int item = blockIdx.x; item < A.sw.n_items; item += gridDim.x) {
     const ItemInfo I = item_info(A, item);
     if (A.sw.status[I.l] != 0 || step >= I.steps) continue;
@@ -150,9 +154,14 @@ __global__ void __launch_bounds__(kWave) learned_step_kernel(LearnedArgs A, int 
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       const int b = t * kWave + lane;
-      const int k0 = b << A.bin_shift;  // first step of the bin
-      const uint64_t w = valid[k0 >> 6];
-      const uint64_t bits = (w >> (k0 & 63)) & (f == 64 ? ~0ull : ((1ull << f) - 1ull));
+      const int k0 = (b * S + 255) >> 8, cnt = (((b + 1) * S + 255) >> 8) - k0;  // <= 16 steps
+      uint64_t bits = 0ull;
+      if (cnt > 0) {
+        const int wi = k0 >> 6, lo = k0 & 63;
+        uint64_t w = valid[wi] >> lo;
+        if (lo + cnt > kWave) w |= valid[wi + 1] << (kWave - lo);  // the bin spans two words
+        bits = w & ((1ull << cnt) - 1ull);
+      }
       key[t] = bits ? nom_key(y[b], b) : 0u;
       any_valid = any_valid || __ballot(bits != 0ull) != 0ull;
     }
@@ -183,7 +192,7 @@ __global__ void __launch_bounds__(kWave) learned_step_kernel(LearnedArgs A, int 
       for (int t0 = 0; t0 < A.tiles; t0 += 4) {
         uint64_t vm[4];
 #pragma unroll
-        for (int t = 0; t < 4; ++t) vm[t] = valid[t0 + t];
+        for (int t = 0; t < 4; ++t) vm[t] = t0 + t < A.tiles ? valid[t0 + t] : 0ull;
         int nvalid;
         const uint64_t key4 =
             best_valid_step<4, false>(W, RS, G, GS, grsrc, A.sw.cs, vm, t0, s0, lane, nvalid);
@@ -191,17 +200,19 @@ __global__ void __launch_bounds__(kWave) learned_step_kernel(LearnedArgs A, int 
       }
       if (lane == 0) atomicAdd(A.n_fallback + I.l, 1);
     } else if (any_valid) {
-      // nominated bins as a 256-bit mask (the bump-mask words are free until
-      // the next step's inputs are written)
-      if (lane < 8) W.BM[lane] = 0u;
+      // steps of the nominated bins as an S-bit mask (the bump-mask words are
+      // free until the next step's inputs are written)
+      for (int i = lane; i < 2 * A.tiles; i += kWave) W.BM[i] = 0u;
       wave_lds_sync();
-      if (nom >= 0) atomicOr(&W.BM[nom >> 5], 1u << (nom & 31));
+      if (nom >= 0) {
+        const int k1 = ((nom + 1) * S + 255) >> 8;
+        for (int k = (nom * S + 255) >> 8; k < k1; ++k) atomicOr(&W.BM[k >> 5], 1u << (k & 31));
+      }
       wave_lds_sync();
       // valid steps of the nominated bins, plus angle 0, compacted in order
       int nvalid = 0;
       for (int t = 0; t < A.tiles; ++t) {
-        const int bin = (t * kWave + lane) >> A.bin_shift;
-        const bool nominated = (W.BM[bin >> 5] >> (bin & 31)) & 1u;
+        const bool nominated = (W.BM[2 * t + (lane >> 5)] >> (lane & 31)) & 1u;
         const uint64_t m = valid[t] & (__ballot(nominated) | (t == 0 ? 1ull : 0ull));
         if ((m >> lane) & 1ull) W.CK[nvalid + mask_rank(m)] = (int16_t)(t * kWave + lane);
         nvalid += __popcll(m);

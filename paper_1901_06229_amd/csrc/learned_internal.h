@@ -15,9 +15,8 @@ struct LearnedArgs {
   uint16_t *feat;       // [rows][64] BF16 features of each item's next step
   uint64_t *valid;      // [n_items][tiles] exact validity of the S angle steps
   const float *pred;    // [rows][256] MLP output for the current step
-  int tiles;            // S / 64
-  int bin_shift;        // log2(S / 256): steps per prediction bin = 1 << bin_shift
-  int top_k;            // nominated bins per step (1 .. 63, top_k << bin_shift < 512)
+  int tiles;            // ceil(S / 64)
+  int top_k;            // nominated bins per step (1 .. 63, top_k ceil(S / 256) < 512)
   float margin;         // fall back to the full step below this predicted margin
   int32_t *n_fallback;  // [n_ligands] steps that fell back
 };

@@ -194,16 +194,17 @@ def test_training_reduces_loss():
     assert np.isfinite(hist["val_loss"]).all()
 
 
-def test_learned_mode_at_finer_steps():
-    """S = 1024 (4 steps per prediction bin): with fallback everywhere the
-    result is the plain sweep bit for bit; without fallback every chosen
-    angle is valid and the poses replay against the reference; sizes outside
-    the documented limits are rejected."""
+@pytest.mark.parametrize("S", [1024, 360, 100])
+def test_learned_mode_at_other_step_counts(S):
+    """S = 1024 (4 steps per prediction bin), 360 (one or two, bins spanning
+    two mask words) and 100 (empty bins): with fallback everywhere the result
+    is the plain sweep bit for bit; without fallback every chosen angle is
+    valid and the poses replay against the reference; sizes outside the
+    documented limits are rejected."""
     _torch()
     pocket, h, net = _proposal_pocket()
     ligs = synth.ligands(learned.LIGAND_RECIPE, count=10, seed=4, stream=synth.STREAM_EVAL)
     orient = synth.orientations(learned.LEARN_CONFIG)
-    S = 1024
     plain = dock.dock_batch(h, ligs, orient, S, want_all=True)
     lrn = dock.dock_batch(h, ligs, orient, S, mode=dock.DOCK_MODE_LEARNED, top_k=16,
                           margin=3.0e38, want_all=True)
@@ -225,7 +226,8 @@ def test_learned_mode_at_finer_steps():
             sc = float(res["all_scores"][l, o])
             assert abs(sc - tr.score) <= tol_of(tr.score) or tr.score_lo - 1e-3 <= sc <= tr.score_hi + 1e-3
     assert not bad, bad[:10]
-    for S_bad, top_k in ((384, 8), (4096, 63)):
-        with pytest.raises(dock.DockError):
+    for S_bad, top_k in ((4096, 32), (4096, 63), (1000, 128)):
+        with pytest.raises(dock.DockError) as e:
             dock.dock_batch(h, ligs, orient, S_bad, mode=dock.DOCK_MODE_LEARNED, top_k=top_k)
+        assert e.value.code == dock.DOCK_E_LIMIT
     h.close()
