@@ -231,3 +231,22 @@ def test_learned_mode_at_other_step_counts(S):
             dock.dock_batch(h, ligs, orient, S_bad, mode=dock.DOCK_MODE_LEARNED, top_k=top_k)
         assert e.value.code == dock.DOCK_E_LIMIT
     h.close()
+
+
+def test_learned_results_do_not_depend_on_the_batch():
+    """A ligand's learned-mode result is the same docked alone or inside a
+    larger batch (items are independent; all items advance phase by phase)."""
+    _torch()
+    pocket, h, net = _proposal_pocket()
+    ligs = synth.ligands(learned.LIGAND_RECIPE, count=40, seed=4, stream=synth.STREAM_EVAL)
+    orient = synth.orientations(learned.LEARN_CONFIG)
+    sub = ligs.subset(range(5))
+    for S, tau in ((256, 0.4), (360, -1.0)):
+        a = dock.dock_batch(h, sub, orient, S, mode=dock.DOCK_MODE_LEARNED, top_k=16, margin=tau,
+                            want_all=True)
+        b = dock.dock_batch(h, ligs, orient, S, mode=dock.DOCK_MODE_LEARNED, top_k=16, margin=tau,
+                            want_all=True)
+        assert np.array_equal(a["all_scores"], b["all_scores"][:5]), S
+        assert np.array_equal(a["best_orient"], b["best_orient"][:5]), S
+        assert np.array_equal(a["n_fallback"][:5], b["n_fallback"][:5]), S
+    h.close()
