@@ -124,6 +124,21 @@ def measured_traffic():
     return float(fields["traffic_bytes_per_launch"])
 
 
+def gather_probe(grid_floats, blocks=4096, iters=256):
+    """Random 4-byte gather rate of the part (the library's probe kernel): over
+    2 MiB, which one XCD's L2 holds, and over a buffer of the grid's size."""
+    import torch
+    from paper_1901_06229_amd import dock
+    out = torch.empty(blocks * 256, device="cuda:0")
+    res = {}
+    for name, log2 in (("2MiB", 19), ("grid_size", max(6, int(np.ceil(np.log2(grid_floats)))))):
+        buf = torch.ones(1 << log2, device="cuda:0")
+        dock.dock_probe_gather(buf, out, log2, blocks, iters)
+        ms = min(dock.dock_probe_gather(buf, out, log2, blocks, iters) for _ in range(3))
+        res[name] = {"bytes": 4 << log2, "gathers_per_s": round(blocks * 256 * iters / (ms / 1e3), 1)}
+    return res
+
+
 def copy_calibration():
     """A plain 1 GiB device-to-device copy, three times: the reference the
     FETCH_SIZE / WRITE_SIZE counters are scaled by."""
@@ -485,6 +500,7 @@ def main():
     mean_s = float(np.mean(sweep_ms)) / 1e3
     achieved = ops / mean_s / 1e12
     mq, msum = batch_counts(ligs)
+    probe = gather_probe(int(np.prod(pocket.grid.shape)))
     line = {
         "metric": METRIC, "value": round(value, 2), "unit": "ligands/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * elapsed / args.steps, 3),
@@ -511,12 +527,25 @@ def main():
                      "candidate_pairs": int(mq * O), "kept_pairs": kept_pairs,
                      "atom_angle_evals": evals,
                      "valid_angle_frac": round(evals / (msum * O * S), 4) if msum else None,
+                     "gathers": {
+                         "per_s": round(evals / mean_s, 1),
+                         "probe": probe,
+                         "note": "voxel gathers of the scoring loop (one per evaluation) per second "
+                                 "of the kernel, next to the probe's random 4-byte gathers; neighbouring "
+                                 "angles share cache lines, so the kernel can exceed the probe"},
                      "dense_equivalent": {
                          "unit": "TOP/s",
                          "value": round(dense_ops(ligs, O, S) / mean_s / 1e12, 2),
                          "note": "lane-ops the unpruned sweep would execute (every pair and "
                                  "atom at every angle) per second of this kernel; not a "
                                  "fraction of peak"}},
+    }
+    line["paper_context"] = {
+        "note": "the paper (arXiv 1901.06229) prints no throughput for this path and no workload "
+                "sizes (1500 unpublished ligands); its figures are context, not comparable",
+        "optimize_pose_gpu_speedup": "2x, OpenACC on 1 Tesla K80 GK210 vs 2x 8-core Xeon E5-2630 v3 (§4.1)",
+        "alignment_gpu_speedup": "16x, same hardware (§4.1)",
+        "hybrid_node": "5.8 ligands/s, 16 OpenMP threads + 2 GK210 GPUs, whole docking incl. alignment (§5.2)",
     }
     if args.align > 0:
         log(f"rigid alignment: {args.align} rotations per restart before the sweep")

@@ -223,6 +223,18 @@ int dock_last_align_ms(dock_pocket *p, float *ms);
  * DOCK_E_DEVICE. */
 int dock_last_sweep_work(dock_pocket *p, uint64_t *kept_pairs, uint64_t *atom_angle_evals);
 
+/* Random-gather probe (benchmark instrumentation, not part of the docking
+ * path): blocks x 256 threads each read iters 4-byte values at independent
+ * pseudo-random offsets of buf[2^log2_floats] (device memory of at least that
+ * many floats) and write one sum each to out[blocks * 256] (device memory).
+ * Runs on `stream` (hipStream_t as void*, NULL = default), waits for it and
+ * stores the kernel's duration in *ms.  Gathers per second =
+ * blocks * 256 * iters / (ms / 1000).  Limits: 6 <= log2_floats <= 28,
+ * 1 <= blocks <= 2^20, iters a multiple of 8 in [8, 65536] (DOCK_E_LIMIT);
+ * NULL or host pointers: DOCK_E_INVAL. */
+int dock_probe_gather(const float *buf, int log2_floats, int blocks, int iters, float *out,
+                      float *ms, void *stream);
+
 /* Launch mapping of the sweep kernel for calls on this handle (the knobs the
  * autotuner turns): waves_per_block in {1, 2, 4}, each wave working on its
  * own (ligand, orientation) items, or 0 (the default) for the block size that

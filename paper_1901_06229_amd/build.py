@@ -12,7 +12,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB_PATH = os.path.join(PKG, "libdock.so")
 
 SOURCES = ["sweep_kernels.hip", "sweep_pruned.hip", "align.hip", "learned.hip", "mlp.hip", "mlp_abi.hip",
-           "dock_abi.hip"]
+           "probe.hip", "dock_abi.hip"]
 
 HIP_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

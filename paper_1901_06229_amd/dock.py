@@ -104,6 +104,8 @@ def load_library(path: str = None):
     lib.dock_last_sweep_ms.argtypes = [_P, c.POINTER(c.c_float)]
     lib.dock_last_align_ms.restype = c.c_int
     lib.dock_last_align_ms.argtypes = [_P, c.POINTER(c.c_float)]
+    lib.dock_probe_gather.restype = c.c_int
+    lib.dock_probe_gather.argtypes = [_P, c.c_int, c.c_int, c.c_int, _P, c.POINTER(c.c_float), _P]
     lib.dock_last_sweep_ms.restype = c.c_int
     lib.dock_last_sweep_work.argtypes = [_P, c.POINTER(c.c_uint64), c.POINTER(c.c_uint64)]
     lib.dock_last_sweep_work.restype = c.c_int
@@ -281,6 +283,17 @@ def dock_last_sweep_ms(pocket: Pocket) -> float:
 def dock_last_align_ms(pocket: Pocket) -> float:
     ms = ctypes.c_float()
     _check(load_library().dock_last_align_ms(pocket.handle, ctypes.byref(ms)), "dock_last_align_ms")
+    return float(ms.value)
+
+
+def dock_probe_gather(buf, out, log2_floats: int, blocks: int, iters: int, stream=None) -> float:
+    """Random 4-byte gathers from buf (device tensor of >= 2^log2_floats floats) by
+    blocks x 256 threads, iters each; out: device tensor of blocks * 256 floats.
+    Returns the kernel's duration in ms."""
+    ms = ctypes.c_float()
+    st = None if stream is None else ctypes.c_void_p(stream.cuda_stream)
+    _check(load_library().dock_probe_gather(_tptr(buf), int(log2_floats), int(blocks), int(iters),
+                                            _tptr(out), ctypes.byref(ms), st), "dock_probe_gather")
     return float(ms.value)
 
 
