@@ -272,6 +272,8 @@ def learned_comparison(n_eval=10_000, n_val=2_000, n_train=156_250, epochs=10, t
         net0 = dock.Mlp(learned.init_params(12345))
         dock.dock_load_proposal(h, net0)
         _, sl0, _ = run("eval", dock.DOCK_MODE_LEARNED, -1.0, 1)
+        dock.dock_load_proposal(h, dock.Mlp(learned.stride_params(top_k)))
+        _, sl_s, _ = run("eval", dock.DOCK_MODE_LEARNED, -1.0, 1)
         dock.dock_load_proposal(h, net)
         _, sl_t, _ = run("eval", dock.DOCK_MODE_LEARNED, -1.0, 1)
         return {
@@ -284,6 +286,7 @@ def learned_comparison(n_eval=10_000, n_val=2_000, n_train=156_250, epochs=10, t
             "top_k": top_k, "margin_tau": tau if tau < 1e30 else "inf (full fallback)",
             "score_loss_mean": loss(sp, sl), "fallback_rate": nfb / (n_eval * 8 * 4),
             "no_fallback_loss_trained": loss(sp, sl_t), "no_fallback_loss_untrained": loss(sp, sl0),
+            f"no_fallback_loss_stride{top_k}": loss(sp, sl_s),
             "validation": [{"tau": c[0] if c[0] < 1e30 else "inf", "ms": round(c[1] * 1e3, 3),
                             "loss": round(c[2], 5), "fallback": round(c[3], 3)} for c in candidates],
         }

@@ -38,6 +38,15 @@ def init_params(seed: int = 0) -> np.ndarray:
     return np.concatenate(parts).astype(np.float32)
 
 
+def stride_params(k: int = 16) -> np.ndarray:
+    """A network that ignores its input and predicts one fixed landscape: 1 on
+    every (256 / k)-th bin, 0 elsewhere (all weights zero, GELU(0) = 0).  Its
+    nominations are the non-learned stride proposal of the same top_k."""
+    p = np.zeros_like(init_params(0))
+    p[-S_BINS:][:: S_BINS // k] = 1.0
+    return p
+
+
 def emit_dataset(pocket_h, n_ligands: int, seed: int, stream: int, orient, chunk: int = 20000,
                  log=print):
     """Profiles of n_ligands training ligands as device tensors (x, t, mask)."""
