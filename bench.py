@@ -412,7 +412,8 @@ def main():
                     help="most items a wave takes per work-queue atomic")
     ap.add_argument("--autotune", type=int, default=None,
                     help="time every launch mapping on this many sampled ligands first and keep "
-                         "the fastest (default: 2000 for the uneven-batch workload, else off)")
+                         "the fastest (default: 2000 for the uneven-batch workload, else off: its "
+                         "pick varies with timing noise between runs, and the gain elsewhere is ~1 %%)")
     ap.add_argument("--graph", action=argparse.BooleanOptionalAction, default=None,
                     help="replay the batch's launch sequence as a captured HIP graph "
                          "(default: on for the uneven-batch workload)")
