@@ -30,6 +30,16 @@ __device__ __forceinline__ uint16_t f2bf(float f) {
 }
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
+// Two FP32 values to packed BF16 (lo in the low half) in one instruction.
+// For finite inputs it rounds to nearest even exactly like f2bf (checked on
+// every finite value of a 3.4 M-value sweep including all-tie patterns);
+// NaNs come out quieted rather than truncated.
+__device__ __forceinline__ uint32_t pack_bf16x2(float lo, float hi) {
+  uint32_t r;
+  asm("v_cvt_pk_bf16_f32 %0, %1, %2" : "=v"(r) : "v"(lo), "v"(hi));
+  return r;
+}
+
 // erf by Abramowitz & Stegun 7.1.26: 1 - (a1 t + ... + a5 t^5) exp(-x^2),
 // t = 1 / (1 + p |x|), odd in x; absolute error below 1.5e-7, far below the
 // BF16 resolution of the activations it feeds.  Branch-free: one reciprocal
@@ -153,11 +163,15 @@ hipError_t gemm_bf16(const GemmArgs &g, bool ta, bool tb, int epi, int M, int N,
 
 // ---------------------------------------------------------------- fused inference
 // Forward pass of 64 rows per block through all four layers.  Activations
-// stay in LDS (BF16, 64 x 256); each wave owns 64 output columns (2 x 2
+// stay in LDS (BF16, 64 x 256); each wave owns 64 output features (2 x 2
 // tiles of 32 x 32) and reads its weight rows straight from global memory
 // (L2-resident, stored [out][in] so the 8 k-values of an MFMA operand are
-// contiguous).  Arithmetic and rounding points are those of the tiled path:
-// FP32 accumulation, bias, GELU, BF16 activations; FP32 output.
+// contiguous).  The weights are the A operand and the activations the B
+// operand, so a lane's accumulators hold runs of 4 consecutive output
+// features of one row: the epilogue adds the bias and stores them as one
+// 8-byte write (the next layer's k direction).  Arithmetic and rounding
+// points are those of the tiled path: FP32 accumulation, bias, GELU, BF16
+// activations; FP32 output.
 constexpr int kInfRows = 64;
 constexpr int kActPad = 8;
 
@@ -207,7 +221,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
       for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b)
-          acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ao[a], bo[b], acc[a][b], 0, 0, 0);
+          acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(bo[b], ao[a], acc[a][b], 0, 0, 0);
     };
     bf16x8 w0[2], w1[2], w2[2], w3[2];
     load_w(0, w0);
@@ -228,20 +242,26 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
     }
     __syncthreads();  // every wave is done reading this layer's input
     const float *bias = bias_src + boff[l];
+    // accumulator j of tile (a, b): feature col0 + 32 b + 8 (j / 4) + 4 (lane / 32) + j % 4
+    // of row 32 a + lane % 32
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
       for (int b = 0; b < 2; ++b) {
-        const int col = col0 + b * 32 + (lane & 31);
-        const float bc = bias[col];
+        const int row = a * 32 + (lane & 31);
 #pragma unroll
-        for (int j = 0; j < 16; ++j) {
-          const int row = a * 32 + (j >> 2) * 8 + (lane >> 5) * 4 + (j & 3);
-          const float v = acc[a][b][j] + bc;
-          if (l < 3)
-            sH[row][col] = f2bf(gelu_f(v));
-          else
-            y[(row0 + row) * 256 + col] = v;
+        for (int g = 0; g < 4; ++g) {
+          const int col = col0 + b * 32 + g * 8 + (lane >> 5) * 4;
+          const float4 bc = *(const float4 *)(bias + col);
+          const float v0 = acc[a][b][4 * g] + bc.x, v1 = acc[a][b][4 * g + 1] + bc.y,
+                      v2 = acc[a][b][4 * g + 2] + bc.z, v3 = acc[a][b][4 * g + 3] + bc.w;
+          if (l < 3) {
+            const uint2 h = make_uint2(pack_bf16x2(gelu_f(v0), gelu_f(v1)),
+                                       pack_bf16x2(gelu_f(v2), gelu_f(v3)));
+            *(uint2 *)&sH[row][col] = h;
+          } else {
+            *(float4 *)&y[(row0 + row) * 256 + col] = make_float4(v0, v1, v2, v3);
+          }
         }
       }
     __syncthreads();
