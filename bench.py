@@ -37,13 +37,15 @@ VALU_PEAK_TOPS = 256 * 128 * 2.4e9 / 1e12
 #   pruned kernel, per rotamer step:
 #     OPS_CAND per candidate cross pair (m_r q_r of them): cylinder bound
 #       (2 sub, mul, fma, cmp) and the ballot append of a kept pair;
-#     OPS_ARC per kept pair: harmonic coefficients, acos / atan2 of the clash
-#       arc, its step range and the bitmask marking;
+#     OPS_ARC per kept pair: its LDS reads, harmonic coefficients and the
+#       never / always tests, the polynomial acos / atan2 of the clash arc and
+#       its step range (marking the bitmask, 17 per 32-step word, is not
+#       counted);
 #     OPS_EVAL per (moving atom, non-bumping angle) evaluation: 6 FMA
 #       rotation, 3 clamps, 3 conversions, 2 24-bit multiply-adds, shift and
 #       the score add (the gather itself is a memory instruction).
 OPS_PAIR, OPS_ROT, OPS_VOX = 8, 23, 22
-OPS_CAND, OPS_ARC, OPS_EVAL = 17, 133, 16
+OPS_CAND, OPS_ARC, OPS_EVAL = 17, 86, 16
 # Rigid alignment, per (item, rotation, atom): 9 FMA rotation, 3 clamps,
 # 3 conversions, shift, 2 24-bit multiply-adds and the score add (the gather
 # is a memory instruction).

@@ -200,6 +200,45 @@ __device__ __forceinline__ void mark_steps(uint32_t *BM, int lo, int len, int S)
   }
 }
 
+// Polynomial arctangent and arccosine for the clash arcs (Abramowitz and
+// Stegun, Handbook of Mathematical Functions, 4.4.49 and 4.4.46: absolute
+// error below 4e-8 rad in exact arithmetic, about 2.5e-7 rad evaluated in
+// FP32, the size of the library routines' own rounding near pi).  An arc end
+// that is off by e rad moves the pair's squared distance at that step by at
+// most R e, far inside the 1e-4 A distance band the FP64 reference treats as
+// ambiguous for the pair sizes of a ligand.
+__device__ __forceinline__ float arc_atan2(float y, float x) {
+  const float ax = fabsf(x), ay = fabsf(y);
+  const float t = fminf(ax, ay) * __builtin_amdgcn_rcpf(fmaxf(ax, ay));
+  const float t2 = t * t;
+  float p = -0.0040540580f;
+  p = fmaf(p, t2, 0.0218612288f);
+  p = fmaf(p, t2, -0.0559098861f);
+  p = fmaf(p, t2, 0.0964200441f);
+  p = fmaf(p, t2, -0.1390853351f);
+  p = fmaf(p, t2, 0.1994653599f);
+  p = fmaf(p, t2, -0.3332985605f);
+  p = fmaf(p, t2, 0.9999993329f);
+  float a = t * p;
+  a = ay > ax ? 1.57079632679f - a : a;
+  a = x < 0.0f ? 3.14159265359f - a : a;
+  return y < 0.0f ? -a : a;
+}
+
+__device__ __forceinline__ float arc_acos(float c) {
+  const float ac = fabsf(c);
+  float p = -0.0012624911f;
+  p = fmaf(p, ac, 0.0066700901f);
+  p = fmaf(p, ac, -0.0170881256f);
+  p = fmaf(p, ac, 0.0308918810f);
+  p = fmaf(p, ac, -0.0501743046f);
+  p = fmaf(p, ac, 0.0889789874f);
+  p = fmaf(p, ac, -0.2145988016f);
+  p = fmaf(p, ac, 1.5707963050f);
+  const float h = __builtin_amdgcn_sqrtf(1.0f - ac) * p;
+  return c < 0.0f ? 3.14159265359f - h : h;
+}
+
 // Clash arcs of the kept pairs PI[0, cnt).  A pair bumps at angle theta iff
 // cos(theta) 2A + sin(theta) 2B > D' - r^2, i.e. cos(theta - beta) > c with
 // R = |(2A, 2B)|, beta = atan2(2B, 2A), c = (D' - r^2) / R: an open arc of
@@ -221,14 +260,16 @@ __device__ __forceinline__ void mark_kept_pairs(const WaveLds &W, const RotState
     const float rho2j = fmaf(cj.x, cj.x, fmaf(cj.y, cj.y, cj.z * cj.z));
     const float A2 = 2.0f * a_, B2 = 2.0f * b_;
     const float D = fmaf(dz, dz, rho2i + rho2j) - r2;
-    const float Rr = sqrtf(fmaf(A2, A2, B2 * B2));
-    if (!(Rr > D)) continue;  // never closer than r_bump
-    if (-Rr > D) {            // closer than r_bump at every angle
+    const float RR = fmaf(A2, A2, B2 * B2);
+    // |D| >= R: the sign of D decides (compared squared, no square root);
+    // past these tests RR > D^2 >= 0, so the arc's R is positive
+    if (D >= 0.0f && D * D >= RR) continue;  // never closer than r_bump
+    if (D < 0.0f && D * D >= RR) {           // closer than r_bump at every angle
       mark_steps(W.BM, 0, S, S);
       continue;
     }
-    const float half = acosf(fminf(fmaxf(D / Rr, -1.0f), 1.0f));
-    const float beta = atan2f(B2, A2);
+    const float half = arc_acos(__builtin_amdgcn_fmed3f(D * __builtin_amdgcn_rsqf(RR), -1.0f, 1.0f));
+    const float beta = arc_atan2(B2, A2);
     const int klo = (int)floorf((beta - half) * steps_per_rad) + 1;
     const int khi = (int)ceilf((beta + half) * steps_per_rad) - 1;
     const int len = khi - klo + 1;

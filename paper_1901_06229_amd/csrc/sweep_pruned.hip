@@ -210,8 +210,12 @@ struct PrunedChoice {
   }
 };
 
-// waves_per_block 0: the block size with the most resident waves per CU
-// (larger blocks on ties).
+// waves_per_block 0: the block size with the most resident waves per CU,
+// counted up to 6 per SIMD (larger blocks on ties).  A seventh wave per SIMD
+// (1-wave blocks at 72 VGPRs) measured slower on the 256-step workload
+// (26.5 ms against 22.3 ms at six): the extra waves mostly add L1 pressure.
+constexpr int kAutoWavesPerCu = 24;
+
 template <int TG>
 static hipError_t launch_pruned_tg(const SweepArgs &A, int nmax, const LaunchPlan &plan,
                                    int n_cu, hipStream_t st) {
@@ -228,8 +232,10 @@ static hipError_t launch_pruned_tg(const SweepArgs &A, int nmax, const LaunchPla
   if (w == 2) return c2.launch(A, nmax, n_cu, st);
   if (w == 1) return c1.launch(A, nmax, n_cu, st);
   if (w != 0) return hipErrorInvalidValue;
-  if (c4.waves() >= c2.waves() && c4.waves() >= c1.waves()) return c4.launch(A, nmax, n_cu, st);
-  if (c2.waves() >= c1.waves()) return c2.launch(A, nmax, n_cu, st);
+  const int n4 = min(c4.waves(), kAutoWavesPerCu), n2 = min(c2.waves(), kAutoWavesPerCu),
+            n1 = min(c1.waves(), kAutoWavesPerCu);
+  if (n4 >= n2 && n4 >= n1) return c4.launch(A, nmax, n_cu, st);
+  if (n2 >= n1) return c2.launch(A, nmax, n_cu, st);
   return c1.launch(A, nmax, n_cu, st);
 }
 
