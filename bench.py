@@ -35,8 +35,10 @@ VALU_PEAK_TOPS = 256 * 128 * 2.4e9 / 1e12
 #   direct kernel, per angle: 8 per cross pair (3 sub, mul, 2 fma, cmp, or),
 #     23 per Rodrigues rotation, 22 per voxel lookup and add
 #   pruned kernel, per rotamer step:
-#     OPS_CAND per candidate cross pair (m_r q_r of them): cylinder bound
-#       (2 sub, mul, fma, cmp) and the ballot append of a kept pair;
+#     OPS_CAND per candidate cross pair (m_r q_r of them): 3 lane
+#       broadcasts, the cylinder bound (2 sub, mul, fma, cmp) and the append
+#       of a kept pair (2 mbcnt on the compare's lane mask, the packed pair
+#       and its LDS address), which the wave runs whenever any lane keeps;
 #     OPS_ARC per kept pair: its LDS reads, harmonic coefficients and the
 #       never / always tests, the polynomial acos / atan2 of the clash arc and
 #       its step range (marking the bitmask, 17 per 32-step word, is not
@@ -45,7 +47,7 @@ VALU_PEAK_TOPS = 256 * 128 * 2.4e9 / 1e12
 #       rotation, 3 clamps, 3 conversions, 2 24-bit multiply-adds, shift and
 #       the score add (the gather itself is a memory instruction).
 OPS_PAIR, OPS_ROT, OPS_VOX = 8, 23, 22
-OPS_CAND, OPS_ARC, OPS_EVAL = 17, 86, 16
+OPS_CAND, OPS_ARC, OPS_EVAL = 13, 86, 16
 # Rigid alignment, per (item, rotation, atom): 9 FMA rotation, 3 clamps,
 # 3 conversions, shift, 2 24-bit multiply-adds and the score add (the gather
 # is a memory instruction).

@@ -94,10 +94,6 @@ struct RotState {
   float3 u;   // unit axis
 };
 
-__device__ __forceinline__ uint64_t lanes_below_mask(int lane) {
-  return (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-}
-
 // Topology of one rotamer step in registers: the bond-axis atoms, the
 // moving list's offset and length, and (lane t < 64) moving atom number t.
 // Loaded in two parts so the sweep can fetch the next step's topology while
@@ -134,7 +130,6 @@ __device__ __forceinline__ RotTopo topo_finish(const LigView &lig, int words, in
 // move_atoms).
 __device__ __forceinline__ RotState rotamer_setup(const WaveLds &W, int n, const RotTopo &T,
                                                   const int16_t *move_atoms, int lane) {
-  const uint64_t below = lanes_below_mask(lane);
   for (int i = lane; i < n; i += kWave) W.mov[i] = 0;
   wave_lds_sync();
   for (int t = lane; t < T.m; t += kWave) {
@@ -162,8 +157,8 @@ __device__ __forceinline__ RotState rotamer_setup(const WaveLds &W, int n, const
       const Cyl c = cyl_of(xi, R.xa, R.u);
       W.C[i] = make_float4(c.rx, c.ry, c.rz, c.z);
     }
-    const uint64_t mask = __ballot(st);
-    if (st) W.Q[q + __popcll(mask & below)] = (int16_t)i;
+    const uint64_t mask = wave_ballot(st);
+    if (st) W.Q[lanes_before(mask, q)] = (int16_t)i;
     q += __popcll(mask);
   }
   R.q = q;
@@ -179,7 +174,7 @@ __device__ __forceinline__ float rotamer_s0(const WaveLds &W, const RotState &R,
   float s = R.cst;
   for (int c0 = 0; c0 < R.m; c0 += kWave) {
     const float v = c0 + lane < R.m ? W.X[W.M[c0 + lane]].w : 0.0f;
-    const int cnt = min(kWave, R.m - c0);
+    const int cnt = __builtin_amdgcn_readfirstlane(min(kWave, R.m - c0));  // scalar loop bound
     for (int t = 0; t < cnt; ++t) s += lane_bcast(v, t);
   }
   return s;
@@ -291,13 +286,12 @@ __device__ __forceinline__ void mark_kept_pairs(const WaveLds &W, const RotState
 // the number of kept pairs.
 __device__ __forceinline__ int rotamer_bump_mask(const WaveLds &W, const RotState &R, float r2,
                                                  float thr, int S, int lane) {
-  const uint64_t below = lanes_below_mask(lane);
   for (int w = lane; w < (S + 31) / 32; w += kWave) W.BM[w] = 0u;
   int np = 0, kept = 0;
-  // appends the lane's pair if act; flushes the list before it can overflow
-  auto push = [&](bool act, int packed) {
-    const uint64_t mask = __ballot(act);
-    if (act) W.PI[np + __popcll(mask & below)] = packed;
+  // appends the lane's pair if act (mask: the wave's act bits); flushes the
+  // list before it can overflow
+  auto push = [&](uint64_t mask, bool act, int packed) {
+    if (act) W.PI[lanes_before(mask, np)] = packed;
     np += __popcll(mask);
     if (np > kPairCap - kWave) {
       wave_lds_sync();
@@ -310,7 +304,8 @@ __device__ __forceinline__ int rotamer_bump_mask(const WaveLds &W, const RotStat
   // lanes hold 64 static atoms; 64 moving atoms sit in registers, one per
   // lane, and are broadcast in turn
   for (int ib = 0; ib < R.m; ib += kWave) {
-    const int mc = min(kWave, R.m - ib);
+    // wave-uniform; kept in a scalar register so the pair loop tests it there
+    const int mc = __builtin_amdgcn_readfirstlane(min(kWave, R.m - ib));
     int il = 0;
     float zl = 0.f, rl = 0.f;
     if (lane < mc) {
@@ -323,11 +318,15 @@ __device__ __forceinline__ int rotamer_bump_mask(const WaveLds &W, const RotStat
       const bool jin = jb + lane < R.q;
       const int j = jin ? W.Q[jb + lane] : 0;
       const float4 cj = W.C[j];
-      const float zj = cj.w, rj = cyl_radius(cj);
+      // lanes past the static list get an infinite radius: their bound is
+      // +inf and never below thr
+      const float zj = cj.w, rj = jin ? cyl_radius(cj) : __builtin_inff();
       for (int t = 0; t < mc; ++t) {
         const float dz = lane_bcast(zl, t) - zj;
         const float dr = lane_bcast(rl, t) - rj;
-        push(jin && fmaf(dr, dr, dz * dz) < thr,
+        const float lb = fmaf(dr, dr, dz * dz);
+        // the ballot is the compare's own lane mask (4: ordered less-than)
+        push(__builtin_amdgcn_fcmpf(lb, thr, 4), lb < thr,
              (__builtin_amdgcn_readlane(il, t) << 16) | j);
       }
     }

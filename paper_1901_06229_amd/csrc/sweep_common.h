@@ -117,6 +117,17 @@ __device__ __forceinline__ float lane_bcast(float v, int src) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
 }
 
+// Wave ballot of a lane predicate, taken straight from the compare's lane
+// mask (no select-and-compare round trip through a vector register).
+__device__ __forceinline__ uint64_t wave_ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
+
+// base + the set bits of the wave-uniform mask m in the lanes below this one
+// (the lane's slot in a ballot compaction): two mbcnt instructions.
+__device__ __forceinline__ int lanes_before(uint64_t m, int base = 0) {
+  return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                        __builtin_amdgcn_mbcnt_lo((uint32_t)m, (uint32_t)base));
+}
+
 // Rigid starting pose X = R x + t (row-major R).
 __device__ __forceinline__ float3 orient_point(const float *T, float x, float y,
                                                float z) {
