@@ -70,8 +70,10 @@ __device__ __forceinline__ int stage_restart(const AlignArgs &A, float4 *Z, int 
       sz += x[k].z;
     }
   }
-  const float fn = (float)n;
-  const float cx = wave_sum(sx) / fn, cy = wave_sum(sy) / fn, cz = wave_sum(sz) / fn;
+  // hardware reciprocal (about 1 ulp): the centroid is this kernel's own and
+  // is folded into the composed transform it writes
+  const float inv_n = __builtin_amdgcn_rcpf((float)n);
+  const float cx = wave_sum(sx) * inv_n, cy = wave_sum(sy) * inv_n, cz = wave_sum(sz) * inv_n;
   c = make_float3(cx, cy, cz);
   const GridView &G = A.grid;
   const float ih = G.inv_h;
@@ -87,11 +89,11 @@ __device__ __forceinline__ int stage_restart(const AlignArgs &A, float4 *Z, int 
   for (int k = 0; k < kChunks; ++k) {
     const int i = lane + k * kWave;
     x[k] = make_float3((x[k].x - cx) * ih, (x[k].y - cy) * ih, (x[k].z - cz) * ih);
-    const float r = sqrtf(fmaf(x[k].x, x[k].x, fmaf(x[k].y, x[k].y, x[k].z * x[k].z)));
+    // hardware square root: its ~1 ulp is far inside kCubeMargin
+    const float r = __builtin_amdgcn_sqrtf(fmaf(x[k].x, x[k].x, fmaf(x[k].y, x[k].y, x[k].z * x[k].z)));
     inner[k] = i < n && rho * r <= reach;
     n_inner += __popcll(__ballot(inner[k]));
   }
-  const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
   int seen_in = 0, seen_out = 0;
 #pragma unroll
   for (int k = 0; k < kChunks; ++k) {
@@ -99,8 +101,7 @@ __device__ __forceinline__ int stage_restart(const AlignArgs &A, float4 *Z, int 
     const uint64_t m_in = __ballot(inner[k]);
     const uint64_t m_out = __ballot(i < n && !inner[k]);
     if (i < n) {
-      const int slot = inner[k] ? seen_in + __popcll(m_in & below)
-                                : n_inner + seen_out + __popcll(m_out & below);
+      const int slot = inner[k] ? lanes_before(m_in, seen_in) : lanes_before(m_out, n_inner + seen_out);
       Z[slot] = make_float4(x[k].x, x[k].y, x[k].z, inner[k] ? 1.0f : 0.0f);
     }
     seen_in += __popcll(m_in);

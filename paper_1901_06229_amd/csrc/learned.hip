@@ -214,7 +214,7 @@ __global__ void __launch_bounds__(kWave) learned_step_kernel(LearnedArgs A, int 
       for (int t = 0; t < A.tiles; ++t) {
         const bool nominated = (W.BM[2 * t + (lane >> 5)] >> (lane & 31)) & 1u;
         const uint64_t m = valid[t] & (__ballot(nominated) | (t == 0 ? 1ull : 0ull));
-        if ((m >> lane) & 1ull) W.CK[nvalid + mask_rank(m)] = (int16_t)(t * kWave + lane);
+        if ((m >> lane) & 1ull) W.CK[lanes_before(m, nvalid)] = (int16_t)(t * kWave + lane);
         nvalid += __popcll(m);
       }
       wave_lds_sync();

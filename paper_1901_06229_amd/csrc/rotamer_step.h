@@ -181,19 +181,23 @@ __device__ __forceinline__ float rotamer_s0(const WaveLds &W, const RotState &R,
   return s;
 }
 
-// Mark the angle steps k in [lo, lo + len) (indices mod S) in the bitmask.
-__device__ __forceinline__ void mark_steps(uint32_t *BM, int lo, int len, int S) {
-  while (len > 0) {
-    const int b = lo & 31;
-    int cnt = 32 - b;
-    cnt = cnt < len ? cnt : len;
-    cnt = cnt < S - lo ? cnt : S - lo;
-    const uint32_t bits = (cnt == 32 ? 0xFFFFFFFFu : ((1u << cnt) - 1u)) << b;
-    atomicOr(&BM[lo >> 5], bits);
-    len -= cnt;
-    lo += cnt;
-    if (lo >= S) lo = 0;
+// Mark the angle steps k in [lo, hi), 0 <= lo <= hi <= S, in the bitmask.
+// Word w takes the bits of [lo, hi) that fall in [32 w, 32 w + 32): both
+// shift counts lie in [0, 31] for every word the loop visits.
+__device__ __forceinline__ void mark_range(uint32_t *BM, int lo, int hi) {
+  for (int w = lo >> 5; w <= (hi - 1) >> 5; ++w) {
+    const int base = w << 5;
+    atomicOr(&BM[w], (0xFFFFFFFFu << max(lo - base, 0)) & (0xFFFFFFFFu >> max(base + 32 - hi, 0)));
   }
+}
+
+// Mark the angle steps k in [lo, lo + len) (indices mod S; 0 <= lo < S,
+// 0 < len <= S) in the bitmask: the part before S, then the wrapped part
+// (an empty range for arcs that do not wrap).
+__device__ __forceinline__ void mark_steps(uint32_t *BM, int lo, int len, int S) {
+  const int end = lo + len;
+  mark_range(BM, lo, min(end, S));
+  mark_range(BM, 0, max(end - S, 0));
 }
 
 // Polynomial arctangent and arccosine for the clash arcs (Abramowitz and
@@ -352,12 +356,6 @@ __device__ __forceinline__ uint64_t tile_valid_mask(const WaveLds &W, int tile, 
   return ~bumps & range;
 }
 
-// Number of set bits of a wave-uniform mask below the lane.
-__device__ __forceinline__ int mask_rank(uint64_t m) {
-  return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
-                                        __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-}
-
 // Scores of the lane's TG angle slots: static score plus the voxel values
 // of the rotated moving atoms, added in atom order.  Per chunk of 64 moving
 // atoms each lane computes one atom's voxel-space rotation basis
@@ -491,7 +489,7 @@ __device__ __forceinline__ uint64_t best_valid_step(const WaveLds &W, const RotS
 #pragma unroll
   for (int t = 0; t < TG; ++t) {
     if ((vm[t] >> lane) & 1ull)
-      W.CK[nvalid + mask_rank(vm[t])] = (int16_t)((t0 + t) * kWave + lane);
+      W.CK[lanes_before(vm[t], nvalid)] = (int16_t)((t0 + t) * kWave + lane);
     nvalid += __popcll(vm[t]);
   }
   wave_lds_sync();
