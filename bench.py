@@ -412,7 +412,7 @@ def main():
                     help="pruned: test only pairs that can clash; direct: every pair")
     ap.add_argument("--waves", type=int, default=0,
                     help="waves per block of the sweep (0: the most resident waves)")
-    ap.add_argument("--claim", type=int, default=32,
+    ap.add_argument("--claim", type=int, default=16,
                     help="most items a wave takes per work-queue atomic")
     ap.add_argument("--autotune", type=int, default=None,
                     help="time every launch mapping on this many sampled ligands first and keep "

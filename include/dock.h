@@ -241,7 +241,8 @@ int dock_probe_gather(const float *buf, int log2_floats, int blocks, int iters, 
  * keeps the most waves resident per compute unit at this batch's sizes; blocks_per_cu >= 0 caps resident blocks
  * per compute unit (0: occupancy limit); items_per_claim in [1, 64] caps how
  * many consecutive items a wave takes from the work queue per atomic (a claim
- * is a share of the items left, so it shrinks to 1 towards the end).
+ * is a share of the items left, so it shrinks to 1 towards the end).  A new
+ * handle starts at (0, 0, 16).
  * Results are bitwise identical under every mapping.  Errors: DOCK_E_INVAL. */
 int dock_set_launch(dock_pocket *p, int waves_per_block, int blocks_per_cu,
                     int items_per_claim);

@@ -43,7 +43,7 @@ struct dock_pocket {
   hipEvent_t ev_align[2] = {nullptr, nullptr};  // alignment start/end
   bool align_timed = false;
   unsigned long long *h_work = nullptr;  // pinned copy of the sweep's two work counters
-  LaunchPlan plan{0, 0, 32};
+  LaunchPlan plan{0, 0, 16};
   // last captured launch sequence of dock_batch_async (DOCK_FLAG_GRAPH)
   std::vector<unsigned char> graph_key;
   hipGraph_t graph = nullptr;

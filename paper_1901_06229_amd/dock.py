@@ -306,7 +306,7 @@ def dock_last_sweep_work(pocket: Pocket) -> tuple[int, int]:
 
 
 def dock_set_launch(pocket: Pocket, waves_per_block: int = 0, blocks_per_cu: int = 0,
-                    items_per_claim: int = 32):
+                    items_per_claim: int = 16):
     _check(load_library().dock_set_launch(pocket.handle, int(waves_per_block), int(blocks_per_cu),
                                           int(items_per_claim)), "dock_set_launch")
 

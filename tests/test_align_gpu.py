@@ -127,7 +127,7 @@ def test_full_c2_batch_with_alignment(pockets):
     ligs = synth.ligands(2)
     orient = synth.orientations(2)
     rots = synth.align_rotations(2, 64)
-    dock.dock_set_launch(h, 0, 0, 32)
+    dock.dock_set_launch(h, 0, 0, 16)
     p, res = _run(pockets, 2, ligs, orient, 256, rots)
     assert (res["status"] == 0).all()
     sc = res["all_scores"]

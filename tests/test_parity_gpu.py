@@ -95,7 +95,7 @@ def test_c5_subset_parity(pockets):
 
 def test_full_c2_batch_in_bench_configuration(pockets):
     """The C2 batch at full size (10,000 ligands x 256 orientations x 256
-    steps) under the launch bench.py times (automatic block size, claim cap 32):
+    steps) under the launch bench.py times (automatic block size, claim cap 16):
     items sampled across the cost-sorted queue are replayed by the reference
     one by one, and every ligand's winner is the best of its 256 orientation
     scores with the lowest index on ties."""
@@ -103,7 +103,7 @@ def test_full_c2_batch_in_bench_configuration(pockets):
     ligs = synth.ligands(2)
     assert ligs.n_ligands == 10_000
     orient = synth.orientations(2)
-    dock.dock_set_launch(h, 0, 0, 32)
+    dock.dock_set_launch(h, 0, 0, 16)
     res = _run(pockets, 2, ligs, orient, 256)[1]
     assert (res["status"] == 0).all()
     sc = res["all_scores"]
@@ -235,7 +235,7 @@ def test_results_independent_of_launch_mapping(pockets):
     orient = synth.orientations(2, 32)
     ref = None
     for waves, bpc, claim in ((4, 0, 1), (1, 0, 1), (2, 1, 4), (4, 2, 8), (1, 3, 64), (4, 0, 3),
-                              (0, 0, 32)):
+                              (0, 0, 32), (0, 0, 16)):
         dock.dock_set_launch(h, waves, bpc, claim)
         res = dock.dock_batch(h, ligs, orient, 128, want_all=True)
         if ref is None:
@@ -243,7 +243,7 @@ def test_results_independent_of_launch_mapping(pockets):
             continue
         for k in ("best_score", "best_orient", "angle_idx", "xyz", "all_scores", "all_angle_idx"):
             assert np.array_equal(ref[k], res[k]), (waves, bpc, claim, k)
-    dock.dock_set_launch(h, 0, 0, 32)
+    dock.dock_set_launch(h, 0, 0, 16)
 
 
 def test_autotune_picks_fastest_and_keeps_results(pockets):
@@ -260,7 +260,7 @@ def test_autotune_picks_fastest_and_keeps_results(pockets):
     after = dock.dock_batch(h, ligs, orient, 128, want_all=True)
     for k in ("best_score", "best_orient", "angle_idx", "xyz", "all_scores", "all_angle_idx"):
         assert np.array_equal(before[k], after[k]), k
-    dock.dock_set_launch(h, 0, 0, 32)
+    dock.dock_set_launch(h, 0, 0, 16)
 
 
 def _device_batch(ligs, orient, S, torch):
