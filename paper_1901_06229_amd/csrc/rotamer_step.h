@@ -27,11 +27,15 @@ namespace dock {
 
 constexpr int kPairCap = 128;  // LDS pair-list entries per wave
 
-// Most compacted tiles scored in one pass for a group of TG tiles: two for
-// groups of up to 4 tiles (fewer live registers, more waves resident), all of
-// them for wider groups (measured on gfx950; results are the same either way).
+// Most compacted tiles scored in one pass for a group of TG tiles: two (fewer
+// live registers, 6 waves per SIMD instead of 4) except for 6-tile groups
+// (257-384 steps), which score all six in one pass.  Measured on gfx950: two-
+// tile passes take 4096 steps over 32-atom ligands from 4.02 M to 4.23 M
+// ligands/s end to end, but slow 360 steps over 100-250-atom ligands (LDS
+// already limits residency) from 53.1 to 55.9 ms.  Results are the same
+// either way.
 template <int TG>
-constexpr int kMaxScoreTiles = TG <= 4 ? (TG < 2 ? TG : 2) : TG;
+constexpr int kMaxScoreTiles = TG == 6 ? 6 : (TG < 2 ? TG : 2);
 
 __host__ __device__ inline int wave_head_bytes(int nmax) {
   // X, C (float4), Q, M (int16), mov (uint8)
