@@ -156,6 +156,22 @@ def test_edge_cases(pockets):
     assert res["best_score"].shape == (0,)
 
 
+@pytest.mark.parametrize("S", [3, 5, 7, 31, 32, 33, 95, 97, 360])
+def test_step_counts_around_mask_words(pockets, S):
+    """Clash arcs are marked 32 steps to a bitmask word, an arc that wraps past
+    step S - 1 as two ranges: step counts below, at and just past word and
+    tile boundaries, on C2 ligands, every item replayed by the reference."""
+    p, h = pockets(2)
+    ligs = synth.ligands(2, count=24, first=7000)
+    orient = synth.orientations(2, 16)
+    print(f"[gpu] step counts: C2 subset, S={S}", flush=True)
+    res = dock.dock_batch(h, ligs, orient, S, want_all=True)
+    assert (res["status"] == 0).all()
+    rep = check_batch(p, ligs, orient, S, res)
+    print(rep.summary())
+    assert rep.ok(), (S, rep.summary())
+
+
 def test_max_size_ligand(pockets):
     """A 256-atom ligand (the per-ligand maximum) with 255 rotamers."""
     p, h = pockets(5)
