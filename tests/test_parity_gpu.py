@@ -160,11 +160,12 @@ def test_edge_cases(pockets):
 def test_step_counts_around_mask_words(pockets, S):
     """Clash arcs are marked 32 steps to a bitmask word, an arc that wraps past
     step S - 1 as two ranges: step counts below, at and just past word and
-    tile boundaries, on C2 ligands, every item replayed by the reference."""
+    tile boundaries, on 24 ligands of 20-80 atoms (128^3 pocket) x 16
+    orientations, every item replayed by the reference."""
     p, h = pockets(2)
     ligs = synth.ligands(2, count=24, first=7000)
     orient = synth.orientations(2, 16)
-    print(f"[gpu] step counts: C2 subset, S={S}", flush=True)
+    print(f"[gpu] step counts: 24 ligands x 16 orientations, S={S}", flush=True)
     res = dock.dock_batch(h, ligs, orient, S, want_all=True)
     assert (res["status"] == 0).all()
     rep = check_batch(p, ligs, orient, S, res)
