@@ -71,7 +71,8 @@ extern "C" {
 
 #define DOCK_FLAG_NO_LPT 1u   /* keep input order instead of cost-sorted items */
 #define DOCK_FLAG_TIME_SWEEP 2u /* record HIP events around the sweep kernel
-                                   (read with dock_last_sweep_ms)           */
+                                   (read with dock_last_sweep_ms or
+                                   dock_sweep_ms_history)                   */
 #define DOCK_FLAG_DIRECT_BUMP 4u /* test every cross pair at every angle
                                     (default: only pairs that can clash)    */
 #define DOCK_FLAG_GRAPH 8u       /* dock_batch_async: capture the launch
@@ -205,6 +206,16 @@ size_t dock_workspace_size(int32_t n_ligands, int64_t total_rot, int n_orient,
  * (batch preparation, alignment, sweep and finalize).  Errors:
  * DOCK_E_INVAL (NULL), DOCK_E_STATE (no timed call yet), DOCK_E_DEVICE. */
 int dock_last_sweep_ms(dock_pocket *p, float *ms);
+
+/* Sweep durations in ms of the last n calls on this handle that set
+ * DOCK_FLAG_TIME_SWEEP, oldest first, into ms[0 .. n) (timed as in
+ * dock_last_sweep_ms; ms[n - 1] is that function's value).  The handle keeps
+ * the events of its last 16 timed calls, so a caller can enqueue up to 16
+ * timed calls back to back and read them all afterwards instead of waiting
+ * after each one.  Waits for the n calls' sweeps to finish.  Errors:
+ * DOCK_E_INVAL (NULL, n outside [1, 16]), DOCK_E_STATE (fewer than n timed
+ * calls so far), DOCK_E_DEVICE. */
+int dock_sweep_ms_history(dock_pocket *p, int n, float *ms);
 
 /* Duration in ms of the alignment kernels of the last call on this handle
  * that set DOCK_FLAG_TIME_SWEEP and n_align > 0, not replayed as a HIP graph

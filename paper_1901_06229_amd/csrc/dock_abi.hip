@@ -25,6 +25,9 @@
 
 using namespace dock;
 
+// Timed calls whose sweep start/end events a handle keeps (dock_sweep_ms_history).
+constexpr int kTimingRing = 16;
+
 struct dock_pocket {
   int device = 0;
   float *d_grid = nullptr;
@@ -38,8 +41,11 @@ struct dock_pocket {
   size_t io_bytes = 0;
   void *sync_ws = nullptr;    // workspace of synchronous calls
   size_t sync_ws_bytes = 0;
-  hipEvent_t ev_sweep[3] = {nullptr, nullptr, nullptr};  // sweep start/end, counter copied
-  bool timed = false;
+  // sweep start/end of the last kTimingRing timed calls; slot ring_next is
+  // the next call's, ring_count of them hold a recorded call
+  hipEvent_t ev_ring[kTimingRing][2] = {};
+  int ring_next = 0, ring_count = 0;
+  hipEvent_t ev_work = nullptr;  // the last timed call's work counters copied to h_work
   hipEvent_t ev_align[2] = {nullptr, nullptr};  // alignment start/end
   bool align_timed = false;
   unsigned long long *h_work = nullptr;  // pinned copy of the sweep's two work counters
@@ -62,6 +68,12 @@ struct dock_pocket {
   int32_t *lw_fallback = nullptr;
   int64_t lw_fallback_n = 0;
 };
+
+// The timed call just enqueued takes its ring slot.
+static void ring_advance(dock_pocket *p) {
+  p->ring_next = (p->ring_next + 1) % kTimingRing;
+  if (p->ring_count < kTimingRing) ++p->ring_count;
+}
 
 namespace {
 
@@ -405,7 +417,7 @@ int enqueue_batch(dock_pocket *p, const dock_ligands *ligs, const float *orient,
     LA.top_k = prm->top_k;
     LA.margin = prm->margin;
     LA.n_fallback = nfb;
-    if (ev && (e = hipEventRecord(p->ev_sweep[0], st)) != hipSuccess)
+    if (ev && (e = hipEventRecord(p->ev_ring[p->ring_next][0], st)) != hipSuccess)
       return hip_fail(e, "hipEventRecord");
     if ((e = enqueue_learned_begin(LA, p->n_cu, st)) != hipSuccess)
       return hip_fail(e, "learned begin kernel");
@@ -417,12 +429,12 @@ int enqueue_batch(dock_pocket *p, const dock_ligands *ligs, const float *orient,
       if (e != hipSuccess) return hip_fail(e, "learned step");
     }
     if (timed) {
-      if (ev && (e = hipEventRecord(p->ev_sweep[1], st)) != hipSuccess)
+      if (ev && (e = hipEventRecord(p->ev_ring[p->ring_next][1], st)) != hipSuccess)
         return hip_fail(e, "hipEventRecord");
       e = hipMemcpyAsync(p->h_work, A.small + 4, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st);
-      if (e == hipSuccess && ev) e = hipEventRecord(p->ev_sweep[2], st);
+      if (e == hipSuccess && ev) e = hipEventRecord(p->ev_work, st);
       if (e != hipSuccess) return hip_fail(e, "timing");
-      if (ev) p->timed = true;
+      if (ev) ring_advance(p);
     }
     FinalOut F{out->best_score, out->best_orient, out->angle_idx, out->xyz_out, out->align_idx,
                item_align};
@@ -436,7 +448,7 @@ int enqueue_batch(dock_pocket *p, const dock_ligands *ligs, const float *orient,
     }
     return DOCK_OK;
   }
-  if (ev && (e = hipEventRecord(p->ev_sweep[0], st)) != hipSuccess)
+  if (ev && (e = hipEventRecord(p->ev_ring[p->ring_next][0], st)) != hipSuccess)
     return hip_fail(e, "hipEventRecord");
   const SweepMode mode = (prm->flags & DOCK_FLAG_DIRECT_BUMP) ? kSweepDirect : kSweepPruned;
   if (mode == kSweepDirect)
@@ -445,12 +457,12 @@ int enqueue_batch(dock_pocket *p, const dock_ligands *ligs, const float *orient,
     e = enqueue_sweep_pruned(A, max_atoms, p->plan, p->n_cu, st);
   if (e != hipSuccess) return hip_fail(e, "sweep kernel");
   if (timed) {
-    if (ev && (e = hipEventRecord(p->ev_sweep[1], st)) != hipSuccess)
+    if (ev && (e = hipEventRecord(p->ev_ring[p->ring_next][1], st)) != hipSuccess)
       return hip_fail(e, "hipEventRecord");
     e = hipMemcpyAsync(p->h_work, A.small + 4, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st);
     if (e != hipSuccess) return hip_fail(e, "copy pair count");
-    if (ev && (e = hipEventRecord(p->ev_sweep[2], st)) != hipSuccess) return hip_fail(e, "hipEventRecord");
-    if (ev) p->timed = true;
+    if (ev && (e = hipEventRecord(p->ev_work, st)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+    if (ev) ring_advance(p);
   }
   FinalOut F{out->best_score, out->best_orient, out->angle_idx, out->xyz_out, out->align_idx,
              item_align};
@@ -487,9 +499,9 @@ const char *dock_last_error(void) { return g_last_error.c_str(); }
 int dock_last_sweep_work(dock_pocket *p, uint64_t *kept_pairs, uint64_t *atom_angle_evals) {
   g_last_error.clear();
   if (!p || !kept_pairs || !atom_angle_evals) return fail(DOCK_E_INVAL, "NULL argument");
-  if (!p->timed) return fail(DOCK_E_STATE, "no call with DOCK_FLAG_TIME_SWEEP yet");
+  if (p->ring_count == 0) return fail(DOCK_E_STATE, "no call with DOCK_FLAG_TIME_SWEEP yet");
   DeviceGuard g(p->device);
-  hipError_t e = hipEventSynchronize(p->ev_sweep[2]);
+  hipError_t e = hipEventSynchronize(p->ev_work);
   if (e != hipSuccess) return hip_fail(e, "sweep counters");
   *kept_pairs = (uint64_t)((volatile unsigned long long *)p->h_work)[0];
   *atom_angle_evals = (uint64_t)((volatile unsigned long long *)p->h_work)[1];
@@ -614,13 +626,21 @@ int dock_autotune(dock_pocket *p, const dock_ligands *ligs, const float *orient,
   return DOCK_OK;
 }
 
-int dock_last_sweep_ms(dock_pocket *p, float *ms) {
+int dock_last_sweep_ms(dock_pocket *p, float *ms) { return dock_sweep_ms_history(p, 1, ms); }
+
+int dock_sweep_ms_history(dock_pocket *p, int n, float *ms) {
   g_last_error.clear();
   if (!p || !ms) return fail(DOCK_E_INVAL, "NULL argument");
-  if (!p->timed) return fail(DOCK_E_STATE, "no call with DOCK_FLAG_TIME_SWEEP yet");
+  if (n < 1 || n > kTimingRing) return fail(DOCK_E_INVAL, "n outside [1, %d]", kTimingRing);
+  if (p->ring_count < n)
+    return fail(DOCK_E_STATE, "%d calls with DOCK_FLAG_TIME_SWEEP so far, %d asked for", p->ring_count, n);
   DeviceGuard g(p->device);
-  hipError_t e = hipEventSynchronize(p->ev_sweep[1]);
-  if (e == hipSuccess) e = hipEventElapsedTime(ms, p->ev_sweep[0], p->ev_sweep[1]);
+  hipError_t e = hipSuccess;
+  for (int i = 0; i < n && e == hipSuccess; ++i) {
+    const int slot = (p->ring_next - n + i + 2 * kTimingRing) % kTimingRing;  // oldest first
+    e = hipEventSynchronize(p->ev_ring[slot][1]);
+    if (e == hipSuccess) e = hipEventElapsedTime(ms + i, p->ev_ring[slot][0], p->ev_ring[slot][1]);
+  }
   return e == hipSuccess ? DOCK_OK : hip_fail(e, "sweep timing");
 }
 
@@ -674,9 +694,10 @@ int dock_init_pocket(const float *grid, int nx, int ny, int nz, const float orig
     return hip_fail(e, "hipMalloc(grid)");
   }
   e = hipStreamCreateWithFlags(&p->stream, hipStreamNonBlocking);
-  if (e == hipSuccess) e = hipEventCreate(&p->ev_sweep[0]);
-  if (e == hipSuccess) e = hipEventCreate(&p->ev_sweep[1]);
-  if (e == hipSuccess) e = hipEventCreate(&p->ev_sweep[2]);
+  for (auto &pair : p->ev_ring)
+    for (hipEvent_t &x : pair)
+      if (e == hipSuccess) e = hipEventCreate(&x);
+  if (e == hipSuccess) e = hipEventCreate(&p->ev_work);
   if (e == hipSuccess) e = hipEventCreate(&p->ev_align[0]);
   if (e == hipSuccess) e = hipEventCreate(&p->ev_align[1]);
   if (e == hipSuccess) e = hipHostMalloc((void **)&p->h_work, 2 * sizeof(unsigned long long), 0);
@@ -702,8 +723,10 @@ void dock_free_pocket(dock_pocket *p) {
     if (p->io) (void)hipFree(p->io);
     if (p->sync_ws) (void)hipFree(p->sync_ws);
     if (p->stream) (void)hipStreamDestroy(p->stream);
-    for (hipEvent_t ev : p->ev_sweep)
-      if (ev) (void)hipEventDestroy(ev);
+    for (auto &pair : p->ev_ring)
+      for (hipEvent_t x : pair)
+        if (x) (void)hipEventDestroy(x);
+    if (p->ev_work) (void)hipEventDestroy(p->ev_work);
     for (hipEvent_t ev : p->ev_align)
       if (ev) (void)hipEventDestroy(ev);
     if (p->h_work) (void)hipHostFree(p->h_work);
@@ -807,14 +830,14 @@ int dock_batch_async(dock_pocket *p, const dock_ligands *ligs, const float *orie
     p->graph_key = key;
   }
   const bool timed = (prm->flags & DOCK_FLAG_TIME_SWEEP) != 0;
-  if (timed && (e = hipEventRecord(p->ev_sweep[0], st)) != hipSuccess)
+  if (timed && (e = hipEventRecord(p->ev_ring[p->ring_next][0], st)) != hipSuccess)
     return hip_fail(e, "hipEventRecord");
   if ((e = hipGraphLaunch(p->graph_exec, st)) != hipSuccess) return hip_fail(e, "hipGraphLaunch");
   if (timed) {
-    if ((e = hipEventRecord(p->ev_sweep[1], st)) != hipSuccess ||
-        (e = hipEventRecord(p->ev_sweep[2], st)) != hipSuccess)
+    if ((e = hipEventRecord(p->ev_ring[p->ring_next][1], st)) != hipSuccess ||
+        (e = hipEventRecord(p->ev_work, st)) != hipSuccess)
       return hip_fail(e, "hipEventRecord");
-    p->timed = true;
+    ring_advance(p);
   }
   return DOCK_OK;
 }

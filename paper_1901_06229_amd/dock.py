@@ -107,6 +107,8 @@ def load_library(path: str = None):
     lib.dock_probe_gather.restype = c.c_int
     lib.dock_probe_gather.argtypes = [_P, c.c_int, c.c_int, c.c_int, _P, c.POINTER(c.c_float), _P]
     lib.dock_last_sweep_ms.restype = c.c_int
+    lib.dock_sweep_ms_history.argtypes = [_P, c.c_int, c.POINTER(c.c_float)]
+    lib.dock_sweep_ms_history.restype = c.c_int
     lib.dock_last_sweep_work.argtypes = [_P, c.POINTER(c.c_uint64), c.POINTER(c.c_uint64)]
     lib.dock_last_sweep_work.restype = c.c_int
     lib.dock_set_launch.argtypes = [_P, c.c_int, c.c_int, c.c_int]
@@ -278,6 +280,13 @@ def dock_last_sweep_ms(pocket: Pocket) -> float:
     ms = ctypes.c_float()
     _check(load_library().dock_last_sweep_ms(pocket.handle, ctypes.byref(ms)), "dock_last_sweep_ms")
     return float(ms.value)
+
+
+def dock_sweep_ms_history(pocket: Pocket, n: int) -> list[float]:
+    """Sweep durations (ms) of the last n timed calls on the handle, oldest first."""
+    ms = (ctypes.c_float * max(int(n), 1))()
+    _check(load_library().dock_sweep_ms_history(pocket.handle, int(n), ms), "dock_sweep_ms_history")
+    return [float(x) for x in ms[:n]]
 
 
 def dock_last_align_ms(pocket: Pocket) -> float:

@@ -333,6 +333,49 @@ def test_graph_replay_with_sweep_timing(pockets):
             assert np.array_equal(ref[k], out[k].cpu().numpy()), k
 
 
+def test_sweep_ms_history():
+    """Timed calls enqueued back to back, read afterwards: the handle keeps the
+    sweep events of its last 16 timed calls, oldest first, the last equal to
+    dock_last_sweep_ms; asking for more than were made, or than it keeps, fails.
+    A fresh handle, so no earlier timed call is on it."""
+    import torch
+    pocket = synth.pocket(2)
+    h = dock.dock_init_pocket(pocket.grid, pocket.origin, pocket.spacing)
+    try:
+        ligs = synth.ligands(2, count=40, first=3000)
+        orient = synth.orientations(2, 8)
+        d, od, out = _device_batch(ligs, orient, 64, torch)
+        ws = torch.empty(dock.dock_workspace_size(ligs.n_ligands, d["total_rot"], 8, 64),
+                         dtype=torch.uint8, device="cuda:0")
+        st = torch.cuda.Stream()
+        prm = dock.make_params(max_atoms=int(np.diff(ligs.atom_offset).max()),
+                               flags=dock.DOCK_FLAG_TIME_SWEEP)
+        with pytest.raises(dock.DockError) as e:
+            dock.dock_sweep_ms_history(h, 1)
+        assert e.value.code == dock.DOCK_E_STATE
+        for _ in range(3):
+            dock.dock_batch_async(h, d, od, 64, out, prm, workspace=ws, stream=st)
+        ms = dock.dock_sweep_ms_history(h, 3)
+        assert len(ms) == 3 and all(0.0 < x < 1e4 for x in ms), ms
+        assert ms[-1] == dock.dock_last_sweep_ms(h)
+        with pytest.raises(dock.DockError) as e:
+            dock.dock_sweep_ms_history(h, 4)
+        assert e.value.code == dock.DOCK_E_STATE
+        for _ in range(17):  # wraps the ring
+            dock.dock_batch_async(h, d, od, 64, out, prm, workspace=ws, stream=st)
+        ms = dock.dock_sweep_ms_history(h, 16)
+        assert len(ms) == 16 and all(0.0 < x < 1e4 for x in ms), ms
+        assert ms[-1] == dock.dock_last_sweep_ms(h)
+        for bad in (0, 17):
+            with pytest.raises(dock.DockError) as e:
+                dock.dock_sweep_ms_history(h, bad)
+            assert e.value.code == dock.DOCK_E_INVAL
+        st.synchronize()
+        assert int((out["status"] != 0).sum()) == 0
+    finally:
+        h.close()
+
+
 def test_async_rejects_host_memory(pockets):
     """Pageable host arrays passed to the device-array entry point are refused
     on the host before anything is enqueued.  The workspace is also too small,
