@@ -29,40 +29,52 @@ __global__ void cs_table_kernel(float2 *cs, int S) {
 }
 
 // ---------------------------------------------------------------- validation
-// One thread per ligand; writes DOCK_OK or an error code into status[l].
-__global__ void validate_kernel(LigView L, int max_atoms, int32_t *status,
-                                int32_t *n_bad) {
-  int l = blockIdx.x * blockDim.x + threadIdx.x;
-  if (l >= L.n_ligands) return;
+// One wave per ligand; writes DOCK_OK or an error code into status[l].  The
+// ligand's offsets are checked first (wave-uniform); only then do the lanes
+// take its rotamers in turn and walk their moving lists, so every read stays
+// inside the arrays the checked offsets bound.
+constexpr int kValidateWaves = 4;
+
+__global__ void __launch_bounds__(kValidateWaves * kWave)
+    validate_kernel(LigView L, int max_atoms, int32_t *status, int32_t *n_bad) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int l = blockIdx.x * kValidateWaves + (int)(threadIdx.x / kWave);
+  if (l >= L.n_ligands) return;  // whole waves
   int err = 0;
-  int a0 = L.atom_offset[l], a1 = L.atom_offset[l + 1];
-  int r0 = L.rot_offset[l], r1 = L.rot_offset[l + 1];
-  int n = a1 - a0, R = r1 - r0;
+  const int a0 = L.atom_offset[l], a1 = L.atom_offset[l + 1];
+  const int r0 = L.rot_offset[l], r1 = L.rot_offset[l + 1];
+  const int n = a1 - a0, R = r1 - r0;
   if (a0 < 0 || a1 < a0 || (int64_t)a1 > L.total_atoms || r0 < 0 || r1 < r0 ||
       (int64_t)r1 > L.total_rot)
     err = -1;
   else if (n < 1 || n > max_atoms || R > 255)
     err = -2;
-  for (int r = r0; r < r1 && !err; ++r) {
-    int a = L.rot_axis[2 * r], b = L.rot_axis[2 * r + 1];
-    int m0 = L.move_offset[r], m1 = L.move_offset[r + 1];
-    if (a < 0 || a >= n || b < 0 || b >= n || a == b || m0 < 0 || m1 < m0 ||
-        (int64_t)m1 > L.total_move || m1 - m0 > n - 2) {
-      err = -1;
-      break;
-    }
-    int prev = -1;
-    for (int t = m0; t < m1; ++t) {
-      int i = L.move_atoms[t];
-      if (i <= prev || i >= n || i == a || i == b) {
-        err = -1;
+  if (!err) {
+    bool bad = false;
+    for (int r = r0 + lane; r < r1 && !bad; r += kWave) {
+      const int a = L.rot_axis[2 * r], b = L.rot_axis[2 * r + 1];
+      const int m0 = L.move_offset[r], m1 = L.move_offset[r + 1];
+      if (a < 0 || a >= n || b < 0 || b >= n || a == b || m0 < 0 || m1 < m0 ||
+          (int64_t)m1 > L.total_move || m1 - m0 > n - 2) {
+        bad = true;
         break;
       }
-      prev = i;
+      int prev = -1;
+      for (int t = m0; t < m1; ++t) {
+        const int i = L.move_atoms[t];
+        if (i <= prev || i >= n || i == a || i == b) {
+          bad = true;
+          break;
+        }
+        prev = i;
+      }
     }
+    if (__ballot(bad) != 0ull) err = -1;
   }
-  status[l] = err;
-  if (err) atomicAdd(n_bad, 1);
+  if (lane == 0) {
+    status[l] = err;
+    if (err) atomicAdd(n_bad, 1);
+  }
 }
 
 // ---------------------------------------------------------------- LPT order
@@ -333,8 +345,8 @@ hipError_t enqueue_prepare(const SweepArgs &A, int max_atoms, bool lpt,
   hipLaunchKernelGGL(cs_table_kernel, dim3(blocks_for(A.S, 256)), dim3(256), 0, st,
                      const_cast<float2 *>(A.cs), A.S);
   if (L > 0) {
-    hipLaunchKernelGGL(validate_kernel, dim3(blocks_for(L, 256)), dim3(256), 0, st, A.lig,
-                       max_atoms, const_cast<int32_t *>(A.status), n_bad);
+    hipLaunchKernelGGL(validate_kernel, dim3(blocks_for(L, kValidateWaves)), dim3(kValidateWaves * kWave),
+                       0, st, A.lig, max_atoms, const_cast<int32_t *>(A.status), n_bad);
     if (lpt) {
       hipLaunchKernelGGL(lpt_bucket_kernel, dim3(blocks_for(L, 256)), dim3(256), 0, st,
                          A.lig, A.S, A.status, bucket_of, counts);

@@ -376,6 +376,48 @@ def test_sweep_ms_history():
         h.close()
 
 
+def test_device_validation_codes(pockets):
+    """Device-array calls validate every ligand on the device (one wave per
+    ligand): malformed ligands get their DOCK_E_* code and best_orient = -1,
+    and the valid ligands between them get the synchronous call's results."""
+    import torch
+    p, h = pockets(2)
+    src = synth.ligands(2, count=16, first=4000)
+    parts = [src.ligand(i) for i in range(src.n_ligands)]
+    mx = max(len(q["xyz"]) for q in parts)
+    with_rot = [i for i, q in enumerate(parts) if len(q["move_offset"]) > 2 and
+                q["move_offset"][1] - q["move_offset"][0] >= 2]
+    i0, i1, i2 = with_rot[:3]
+    out_of_range = dict(parts[i0], move_atoms=parts[i0]["move_atoms"].copy())
+    out_of_range["move_atoms"][0] = len(out_of_range["xyz"])          # atom index past n
+    same_axis = dict(parts[i1], rot_axis=parts[i1]["rot_axis"].copy())
+    same_axis["rot_axis"][0, 1] = same_axis["rot_axis"][0, 0]          # a == b
+    unsorted = dict(parts[i2], move_atoms=parts[i2]["move_atoms"].copy())
+    m0 = int(unsorted["move_offset"][0])
+    unsorted["move_atoms"][[m0, m0 + 1]] = unsorted["move_atoms"][[m0 + 1, m0]]  # not increasing
+    reps = -(-(mx + 1) // len(parts[0]["xyz"]))
+    big = dict(xyz=np.tile(parts[0]["xyz"], (reps, 1))[:mx + 1], rot_axis=np.zeros((0, 2), np.int32),
+               move_offset=np.zeros(1, np.int32), move_atoms=np.zeros(0, np.int16))  # n > max_atoms
+    good = [parts[j] for j in range(len(parts)) if j not in (i0, i1, i2)][:4]
+    batch = [good[0], out_of_range, good[1], same_axis, good[2], unsorted, big, good[3]]
+    want = [0, dock.DOCK_E_INVAL, 0, dock.DOCK_E_INVAL, 0, dock.DOCK_E_INVAL, dock.DOCK_E_LIMIT, 0]
+    ligs = synth.Ligands.from_parts(batch)
+    orient = synth.orientations(2, 8)
+    d, od, out = _device_batch(ligs, orient, 64, torch)
+    st = torch.cuda.Stream()
+    print("[gpu] device validation: 8 ligands, 4 malformed", flush=True)
+    dock.dock_batch_async(h, d, od, 64, out, dock.make_params(max_atoms=mx), stream=st)
+    st.synchronize()
+    assert out["status"].cpu().tolist() == want
+    best_orient = out["best_orient"].cpu().numpy()
+    assert (best_orient[[1, 3, 5, 6]] == -1).all()
+    ref = dock.dock_batch(h, synth.Ligands.from_parts(good), orient, 64, want_all=True)
+    rows = [0, 2, 4, 7]
+    assert np.array_equal(out["best_score"].cpu().numpy()[rows], ref["best_score"])
+    assert np.array_equal(best_orient[rows], ref["best_orient"])
+    assert np.array_equal(out["all_scores"].cpu().numpy()[rows], ref["all_scores"])
+
+
 def test_async_rejects_host_memory(pockets):
     """Pageable host arrays passed to the device-array entry point are refused
     on the host before anything is enqueued.  The workspace is also too small,
