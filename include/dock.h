@@ -78,7 +78,8 @@ extern "C" {
 #define DOCK_FLAG_GRAPH 8u       /* dock_batch_async: capture the launch
                                     sequence in a HIP graph and replay it
                                     while arguments repeat (needs a
-                                    non-default stream)                      */
+                                    non-default stream; plain mode only:
+                                    with DOCK_MODE_LEARNED, DOCK_E_INVAL)    */
 
 typedef struct dock_pocket dock_pocket;
 
@@ -115,7 +116,8 @@ typedef struct {
                         predicted best minus the (top_k+1)-th is below this   */
   uint32_t flags;    /* DOCK_FLAG_*                                             */
   int32_t max_atoms; /* async calls: upper bound on atoms per ligand (0: 256)   */
-  int32_t max_rot;   /* async learned calls: upper bound on rotamers (0: 255)   */
+  int32_t max_rot;   /* async learned calls: upper bound on rotamers, 0 .. 255
+                        (0: 255); a ligand with more gets status DOCK_E_LIMIT */
   int32_t n_align;   /* rotations in the alignment set, 0 .. DOCK_MAX_ALIGN;
                         0 = no alignment (the sweep starts from R_o X_ref + t_o) */
   const float *align_rot; /* [n_align][9] row-major rotation matrices (host

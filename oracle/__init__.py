@@ -47,6 +47,8 @@ def _load():
         lib.oracle_rotate.argtypes = [P, P, c.c_double, P, P]
         lib.oracle_voxel_value.restype = c.c_double
         lib.oracle_voxel_value.argtypes = [P, c.c_int, c.c_int, c.c_int, P, c.c_float, P]
+        lib.oracle_voxel_interval.argtypes = [P, c.c_int, c.c_int, c.c_int, P, c.c_float, P,
+                                              c.c_double, P, P, P]
         lib.oracle_trace_item.argtypes = (
             [P, c.c_int, c.c_int, c.c_int, P, c.c_float, c.c_int, P, c.c_int, P, P, P, P,
              c.c_int, c.c_double, c.c_int, P, c.c_double, P, P, P, P, P, P, P, P, P,
@@ -80,6 +82,20 @@ def voxel_value(pocket, p) -> float:
     nz, ny, nx = g.shape
     return _load().oracle_voxel_value(_p(g), nx, ny, nz, _p(_c(pocket.origin, np.float32)),
                                       float(pocket.spacing), _p(_c(p, np.float64)))
+
+
+def voxel_interval(pocket, p, delta: float = DELTA):
+    """(lo, hi, ambiguous): the range of voxel values a lookup of p can take if
+    p moves by less than delta on each axis, and whether p lies within delta
+    of a voxel face."""
+    g = _c(pocket.grid, np.float32)
+    nz, ny, nx = g.shape
+    lo, hi = np.zeros(1), np.zeros(1)
+    am = np.zeros(1, np.int32)
+    _load().oracle_voxel_interval(_p(g), nx, ny, nz, _p(_c(pocket.origin, np.float32)),
+                                  float(pocket.spacing), _p(_c(p, np.float64)), float(delta),
+                                  _p(lo), _p(hi), _p(am))
+    return float(lo[0]), float(hi[0]), bool(am[0])
 
 
 @dataclass

@@ -358,6 +358,17 @@ double oracle_voxel_value(const float *grid, int nx, int ny, int nz,
   return voxel_value(P, p);
 }
 
+// Range [lo, hi] of voxel values within delta of p, and whether p lies
+// within delta of a voxel face on any axis (exported for its closed-form pins).
+void oracle_voxel_interval(const float *grid, int nx, int ny, int nz,
+                           const float *origin, float spacing, const double p[3],
+                           double delta, double *lo, double *hi, int *ambiguous) {
+  Pocket P = make_pocket(grid, nx, ny, nz, origin, spacing);
+  bool am = false;
+  voxel_interval(P, p, delta, lo, hi, &am);
+  *ambiguous = am ? 1 : 0;
+}
+
 // One (ligand, orientation) item with the full per-step record.  forced_k
 // (NULL or [passes*R]) makes the trajectory follow the given choices (used to
 // replay another implementation's path); k_star always receives this

@@ -19,10 +19,11 @@
 // one L2 cache line per lane.  The block therefore first copies a cube of
 // grid values around the ligand's first restart into LDS (the voxels of
 // indices lo .. lo + side - 1 per axis, clamped to the box as the score
-// requires).  The image t of an atom, in voxel units, is computed the same
-// way on either route; t - lo is exact in FP32 (an integer subtracted from a
-// value of the same or larger magnitude below 2^24), so a lane inside the
-// cube reads exactly the voxel the global lookup would.  Atoms whose images
+// requires; the corner lo is kept at or above 0).  The image t of an atom, in
+// voxel units, is computed the same way on either route; for t >= lo >= 0,
+// t - lo is exact in FP32 (a non-negative integer no larger than t subtracted
+// from t below 2^24), so a lane inside the cube reads exactly the voxel the
+// global lookup would.  Atoms whose images
 // provably stay inside the cube for every rotation (distance from the
 // centroid times the largest row norm of the set, plus the centroid's offset
 // from the cube centre, below half the side) take the LDS route without a
@@ -148,8 +149,10 @@ __global__ void __launch_bounds__(align_waves<MAXN>() * kWave)
     float3 c0;
     stage_restart<MAXN>(A, Z, a0, n, 0, rho, far, lane, c0, q0x, q0y, q0z);
   }
-  const int lox = (int)floorf(q0x) - kCubeHalf, loy = (int)floorf(q0y) - kCubeHalf,
-            loz = (int)floorf(q0z) - kCubeHalf;
+  // a corner below 0 would make t - lo an addition, which can round up
+  // across a face; clamped cells past the far border are read as stored
+  const int lox = max((int)floorf(q0x) - kCubeHalf, 0), loy = max((int)floorf(q0y) - kCubeHalf, 0),
+            loz = max((int)floorf(q0z) - kCubeHalf, 0);
   const float C[3] = {(float)lox + 0.5f * kCubeSide, (float)loy + 0.5f * kCubeSide,
                       (float)loz + 0.5f * kCubeSide};
   for (int v = threadIdx.x; v < kCubeVox; v += WAVES * kWave) {

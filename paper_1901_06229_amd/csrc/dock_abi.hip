@@ -308,10 +308,15 @@ int grow_learned(dock_pocket *p, int64_t items, int nmax, int tiles) {
   return DOCK_OK;
 }
 
+// max_rot: the most rotamers a ligand of this batch has (synchronous calls
+// know it exactly, asynchronous ones take dock_params.max_rot, 0 meaning
+// 255); in learned mode the step launches cover max_rot x passes steps and
+// the device validation rejects ligands with more rotamers (DOCK_E_LIMIT).
 int enqueue_batch(dock_pocket *p, const dock_ligands *ligs, const float *orient, int O, int S,
                   const dock_params *prm, const dock_results *out, void *ws, size_t ws_bytes,
-                  hipStream_t st, uint16_t *emit_x = nullptr, uint16_t *emit_t = nullptr,
-                  uint32_t *emit_mask = nullptr, bool events = true) {
+                  hipStream_t st, int max_rot, uint16_t *emit_x = nullptr,
+                  uint16_t *emit_t = nullptr, uint32_t *emit_mask = nullptr,
+                  bool events = true) {
   const int64_t L = ligs->n_ligands;
   const int max_atoms = prm->max_atoms > 0 ? prm->max_atoms : DOCK_MAX_ATOMS;
   if (L * (int64_t)O >= ((int64_t)1 << 31)) return fail(DOCK_E_LIMIT, "n_ligands * n_orient >= 2^31");
@@ -321,8 +326,8 @@ int enqueue_batch(dock_pocket *p, const dock_ligands *ligs, const float *orient,
     if (prm->top_k < 1 || prm->top_k > 63) return fail(DOCK_E_LIMIT, "top_k outside [1, 63]");
     if (prm->top_k * ((S + 255) / 256) + 1 > 512)
       return fail(DOCK_E_LIMIT, "top_k x ceil(angle_steps / 256) must be below 512");
-    if (prm->max_rot < 0 || prm->max_rot > DOCK_MAX_ROT) return fail(DOCK_E_LIMIT, "max_rot outside [0, 255]");
   }
+  if (max_rot < 0 || max_rot > DOCK_MAX_ROT) return fail(DOCK_E_LIMIT, "max_rot outside [0, 255]");
   WsLayout w = ws_layout(L, ligs->total_rot, O, S, prm->passes, prm->n_align);
   if (ws_bytes < w.total) return fail(DOCK_E_INVAL, "workspace too small: %zu < %zu", ws_bytes, w.total);
   char *base = (char *)ws;
@@ -357,7 +362,8 @@ int enqueue_batch(dock_pocket *p, const dock_ligands *ligs, const float *orient,
   A.emit_mask = emit_mask;
   int32_t *counts = A.small + 64, *cursor = A.small + 64 + kLptBuckets;
   bool lpt = !(prm->flags & DOCK_FLAG_NO_LPT) && !learned;
-  hipError_t e = enqueue_prepare(A, max_atoms, lpt, (int32_t *)(base + w.bucket), counts, cursor,
+  hipError_t e = enqueue_prepare(A, max_atoms, learned ? max_rot : DOCK_MAX_ROT, lpt,
+                                 (int32_t *)(base + w.bucket), counts, cursor,
                                  A.small + 1, st);
   if (e != hipSuccess) return hip_fail(e, "prepare kernels");
   const int maxn = maxn_bucket(max_atoms);
@@ -421,7 +427,7 @@ int enqueue_batch(dock_pocket *p, const dock_ligands *ligs, const float *orient,
       return hip_fail(e, "hipEventRecord");
     if ((e = enqueue_learned_begin(LA, p->n_cu, st)) != hipSuccess)
       return hip_fail(e, "learned begin kernel");
-    const int steps = (prm->max_rot > 0 ? prm->max_rot : DOCK_MAX_ROT) * prm->passes;
+    const int steps = max_rot * prm->passes;
     const int rows = (int)((L * O + 63) / 64 * 64);
     for (int s = 0; s < steps; ++s) {
       e = mlp_infer(p->lw_feat, rows, p->prop_wb, p->prop_w, p->lw_z[3], st);
@@ -784,10 +790,17 @@ int dock_batch_async(dock_pocket *p, const dock_ligands *ligs, const float *orie
     workspace_bytes = p->ws_bytes;
   }
   hipStream_t st = (hipStream_t)stream;
+  if (prm->max_rot < 0 || prm->max_rot > DOCK_MAX_ROT)
+    return fail(DOCK_E_LIMIT, "max_rot outside [0, 255]");
+  const int max_rot = prm->max_rot > 0 ? prm->max_rot : DOCK_MAX_ROT;
   if (!(prm->flags & DOCK_FLAG_GRAPH))
     return enqueue_batch(p, ligs, orient, n_orient, angle_steps, prm, out, workspace,
-                         workspace_bytes, st);
+                         workspace_bytes, st, max_rot);
   if (!st) return fail(DOCK_E_INVAL, "DOCK_FLAG_GRAPH needs a non-default stream");
+  // learned mode grows handle-owned buffers with allocations that a capture
+  // cannot hold, and a graph would keep their addresses past a regrowth
+  if (prm->mode == DOCK_MODE_LEARNED)
+    return fail(DOCK_E_INVAL, "DOCK_FLAG_GRAPH cannot be combined with DOCK_MODE_LEARNED");
   // The launch sequence depends only on these values: replay it if they repeat.
   std::vector<unsigned char> key;
   auto put = [&](const void *v, size_t bytes) {
@@ -812,7 +825,7 @@ int dock_batch_async(dock_pocket *p, const dock_ligands *ligs, const float *orie
     if ((e = hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed)) != hipSuccess)
       return hip_fail(e, "hipStreamBeginCapture");
     rc = enqueue_batch(p, ligs, orient, n_orient, angle_steps, prm, out, workspace,
-                       workspace_bytes, st, nullptr, nullptr, nullptr, false);
+                       workspace_bytes, st, max_rot, nullptr, nullptr, nullptr, false);
     hipGraph_t graph = nullptr;
     e = hipStreamEndCapture(st, &graph);
     if (rc) {
@@ -923,7 +936,7 @@ static int run_sync(dock_pocket *p, const dock_ligands *ligs, const float *orien
   pr.max_rot = max_r;
   pr.align_rot = NAL > 0 ? (const float *)(d + o_rot) : nullptr;
   rc = enqueue_batch(p, &dl, (const float *)(d + o_or), n_orient, angle_steps, &pr, &dr,
-                     p->sync_ws, p->sync_ws_bytes, st, emit_x, emit_t, emit_mask);
+                     p->sync_ws, p->sync_ws_bytes, st, max_r, emit_x, emit_t, emit_mask);
   if (rc) return rc;
   auto d2h = [&](void *dst, size_t at, size_t bytes) {
     if (e == hipSuccess && dst && bytes)

@@ -93,7 +93,8 @@ struct LaunchPlan {
   int items_per_claim;  // 1 .. 64
 };
 
-hipError_t enqueue_prepare(const SweepArgs &A, int max_atoms, bool lpt, int32_t *bucket_of,
+// max_rot: ligands with more rotamers get status DOCK_E_LIMIT (at most 255).
+hipError_t enqueue_prepare(const SweepArgs &A, int max_atoms, int max_rot, bool lpt, int32_t *bucket_of,
                            int32_t *counts, int32_t *cursor, int32_t *n_bad,
                            hipStream_t st);
 hipError_t enqueue_fill_i32(int32_t *p, int n, int32_t v, hipStream_t st);

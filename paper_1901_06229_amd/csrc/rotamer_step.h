@@ -360,6 +360,29 @@ __device__ __forceinline__ uint64_t tile_valid_mask(const WaveLds &W, int tile, 
   return ~bumps & range;
 }
 
+// One atom's rotation basis in voxel units relative to the grid corner:
+// ((p - o)/h, e/h, f/h).  At angle (c, s) the atom's image is
+// p' + c e' + s f', whose voxel is voxel_byte_offset of that point.  The
+// angle scores and the application of the chosen angle both go through these
+// two functions, so the voxel value a pose carries into the next step is the
+// one its angle was scored with.
+struct VoxBasis {
+  float px, py, pz, ex, ey, ez, fx, fy, fz;
+};
+
+__device__ __forceinline__ VoxBasis voxel_basis(const RotBasis &bs, const GridView &G) {
+  return VoxBasis{(bs.px - G.ox) * G.inv_h, (bs.py - G.oy) * G.inv_h, (bs.pz - G.oz) * G.inv_h,
+                  bs.ex * G.inv_h,          bs.ey * G.inv_h,          bs.ez * G.inv_h,
+                  bs.fx * G.inv_h,          bs.fy * G.inv_h,          bs.fz * G.inv_h};
+}
+
+__device__ __forceinline__ uint32_t basis_voxel_offset(const GridScaled &GS, const VoxBasis &b,
+                                                       float c, float s) {
+  return voxel_byte_offset(GS, fmaf(s, b.fx, fmaf(c, b.ex, b.px)),
+                           fmaf(s, b.fy, fmaf(c, b.ey, b.py)),
+                           fmaf(s, b.fz, fmaf(c, b.ez, b.pz)));
+}
+
 // Scores of the lane's TG angle slots: static score plus the voxel values
 // of the rotated moving atoms, added in atom order.  Per chunk of 64 moving
 // atoms each lane computes one atom's voxel-space rotation basis
@@ -379,16 +402,10 @@ __device__ __forceinline__ void rotamer_scores(const WaveLds &W, const RotState 
           b8 = 0.f;
     if (c0 + lane < R.m) {
       const float4 ci = W.C[W.M[c0 + lane]];
-      const RotBasis bs = rot_basis(Cyl{ci.x, ci.y, ci.z, ci.w}, R.xa, R.u);
-      b0 = (bs.px - G.ox) * G.inv_h;
-      b1 = (bs.py - G.oy) * G.inv_h;
-      b2 = (bs.pz - G.oz) * G.inv_h;
-      b3 = bs.ex * G.inv_h;
-      b4 = bs.ey * G.inv_h;
-      b5 = bs.ez * G.inv_h;
-      b6 = bs.fx * G.inv_h;
-      b7 = bs.fy * G.inv_h;
-      b8 = bs.fz * G.inv_h;
+      const VoxBasis vb = voxel_basis(rot_basis(Cyl{ci.x, ci.y, ci.z, ci.w}, R.xa, R.u), G);
+      b0 = vb.px, b1 = vb.py, b2 = vb.pz;
+      b3 = vb.ex, b4 = vb.ey, b5 = vb.ez;
+      b6 = vb.fx, b7 = vb.fy, b8 = vb.fz;
     }
     const int cnt = min(kWave, R.m - c0);
     if constexpr (LB) {
@@ -411,12 +428,10 @@ __device__ __forceinline__ void rotamer_scores(const WaveLds &W, const RotState 
         ex = lane_bcast(b3, tt), ey = lane_bcast(b4, tt), ez = lane_bcast(b5, tt);
         fx = lane_bcast(b6, tt), fy = lane_bcast(b7, tt), fz = lane_bcast(b8, tt);
       }
+      const VoxBasis vb{px, py, pz, ex, ey, ez, fx, fy, fz};
       uint32_t off[TG];
 #pragma unroll
-      for (int t = 0; t < TG; ++t)
-        off[t] = voxel_byte_offset(GS, fmaf(ss[t], fx, fmaf(cc[t], ex, px)),
-                                   fmaf(ss[t], fy, fmaf(cc[t], ey, py)),
-                                   fmaf(ss[t], fz, fmaf(cc[t], ez, pz)));
+      for (int t = 0; t < TG; ++t) off[t] = basis_voxel_offset(GS, vb, cc[t], ss[t]);
 #pragma unroll
       for (int t = 0; t < TG; ++t) v[t] = grid_load(grsrc, off[t]);
       __builtin_amdgcn_sched_barrier(0);  // adds stay behind these loads
@@ -523,15 +538,20 @@ __device__ __forceinline__ uint64_t best_valid_step(const WaveLds &W, const RotS
   return best;
 }
 
-// Rotate the moving atoms of the pose in LDS by the angle (c, s).
+// Rotate the moving atoms of the pose in LDS by the angle (c, s).  Each
+// atom's voxel value comes from the same voxel-space expression the angle's
+// score used (voxel_basis, basis_voxel_offset), not from a lookup of the
+// rotated world coordinates, which can round across a voxel face differently.
 __device__ __forceinline__ void rotamer_apply(const WaveLds &W, const RotState &R,
                                               const GridView &G, float c, float s, int lane) {
+  const GridScaled GS = grid_scaled(G);
   for (int t = lane; t < R.m; t += kWave) {
     const int i = W.M[t];
     const float4 ci = W.C[i];
     const RotBasis bs = rot_basis(Cyl{ci.x, ci.y, ci.z, ci.w}, R.xa, R.u);
     const float3 y = rot_apply(bs, c, s);
-    W.X[i] = make_float4(y.x, y.y, y.z, voxel_value(G, y.x, y.y, y.z));
+    const uint32_t off = basis_voxel_offset(GS, voxel_basis(bs, G), c, s);
+    W.X[i] = make_float4(y.x, y.y, y.z, G.grid[off >> 2]);
   }
   wave_lds_sync();
 }

@@ -1,10 +1,15 @@
 // Device helpers shared by the sweep kernels (gfx950, wave64).
 //
 // Every floating-point step a pose goes through (orientation, axis,
-// rotation, voxel index) lives here as one function, so the evaluation of an
-// angle, the application of the chosen angle and the final replay of the
-// winning orientation perform bit-identical arithmetic.  The library is built
-// with -ffp-contract=off; fused multiply-adds appear only where written.
+// rotation, voxel index) lives here or in rotamer_step.h as one function.
+// Within one sweep form the evaluation of an angle, the application of the
+// chosen angle and the final replay of the winning orientation therefore do
+// the same arithmetic: the pruned sweep scores and applies an angle through
+// one voxel-space expression, the direct sweep through rodrigues and
+// voxel_value.  The two forms differ from each other (and from an FP64
+// evaluation) only where an atom lies within rounding of a voxel face or a
+// pair within rounding of the bump radius.  The library is built with
+// -ffp-contract=off; fused multiply-adds appear only where written.
 #pragma once
 
 #include <hip/hip_runtime.h>

@@ -36,7 +36,7 @@ __global__ void cs_table_kernel(float2 *cs, int S) {
 constexpr int kValidateWaves = 4;
 
 __global__ void __launch_bounds__(kValidateWaves * kWave)
-    validate_kernel(LigView L, int max_atoms, int32_t *status, int32_t *n_bad) {
+    validate_kernel(LigView L, int max_atoms, int max_rot, int32_t *status, int32_t *n_bad) {
   const int lane = threadIdx.x & (kWave - 1);
   const int l = blockIdx.x * kValidateWaves + (int)(threadIdx.x / kWave);
   if (l >= L.n_ligands) return;  // whole waves
@@ -47,7 +47,7 @@ __global__ void __launch_bounds__(kValidateWaves * kWave)
   if (a0 < 0 || a1 < a0 || (int64_t)a1 > L.total_atoms || r0 < 0 || r1 < r0 ||
       (int64_t)r1 > L.total_rot)
     err = -1;
-  else if (n < 1 || n > max_atoms || R > 255)
+  else if (n < 1 || n > max_atoms || R > max_rot)
     err = -2;
   if (!err) {
     bool bad = false;
@@ -334,7 +334,7 @@ hipError_t enqueue_fill_i32(int32_t *p, int n, int32_t v, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t enqueue_prepare(const SweepArgs &A, int max_atoms, bool lpt,
+hipError_t enqueue_prepare(const SweepArgs &A, int max_atoms, int max_rot, bool lpt,
                            int32_t *bucket_of, int32_t *counts, int32_t *cursor,
                            int32_t *n_bad, hipStream_t st) {
   const int L = A.lig.n_ligands;
@@ -346,7 +346,7 @@ hipError_t enqueue_prepare(const SweepArgs &A, int max_atoms, bool lpt,
                      const_cast<float2 *>(A.cs), A.S);
   if (L > 0) {
     hipLaunchKernelGGL(validate_kernel, dim3(blocks_for(L, kValidateWaves)), dim3(kValidateWaves * kWave),
-                       0, st, A.lig, max_atoms, const_cast<int32_t *>(A.status), n_bad);
+                       0, st, A.lig, max_atoms, max_rot, const_cast<int32_t *>(A.status), n_bad);
     if (lpt) {
       hipLaunchKernelGGL(lpt_bucket_kernel, dim3(blocks_for(L, 256)), dim3(256), 0, st,
                          A.lig, A.S, A.status, bucket_of, counts);

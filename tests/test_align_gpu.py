@@ -39,6 +39,7 @@ def _check(p, ligs, orient, S, res, rots, **kw):
     rep = check_batch(p, ligs, orient, S, res, align=rots, **kw)
     print(rep.summary())
     assert rep.ok(), rep.summary()
+    rep.assert_rare()
     return rep
 
 

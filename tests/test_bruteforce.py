@@ -42,9 +42,14 @@ def _greedy_reference(pocket, lig, orient, S, r_bump):
 @pytest.mark.parametrize("S", [8, 12, 16])
 def test_greedy_step_is_argmax_with_greedy_prefix(S):
     rng = np.random.default_rng(S)
+    checked = trials = 0
     for lig in _tiny_ligands():
         for trial in range(3):
+            trials += 1
             pocket = random_pocket(rng, G=24, h=0.5)
+            # a random sub-voxel shift keeps one geometric near-coincidence of
+            # an atom with a face from repeating over every trial
+            pocket.origin = (pocket.origin + rng.uniform(0, 0.5, 3)).astype(np.float32)
             orient = IDENTITY
             tr = oracle.trace_item(pocket, lig, orient, S, r_bump=2.0)
             if (tr.prof_flags & (oracle.FLAG_VAMB | oracle.FLAG_SAMB)).any():
@@ -53,6 +58,9 @@ def test_greedy_step_is_argmax_with_greedy_prefix(S):
             assert list(tr.k_star) == ks
             assert np.abs(tr.xyz - X).max() < 1e-9
             assert abs(tr.score - np_voxel(pocket, X).sum()) < 1e-9
+            checked += 1
+    # the band is 1e-4 A wide: nearly every trial is a real comparison
+    assert checked >= 0.8 * trials, (checked, trials)
 
 
 @pytest.mark.parametrize("S", [8, 16])

@@ -250,3 +250,44 @@ def test_learned_results_do_not_depend_on_the_batch():
         assert np.array_equal(a["best_orient"], b["best_orient"][:5]), S
         assert np.array_equal(a["n_fallback"][:5], b["n_fallback"][:5]), S
     h.close()
+
+
+def test_async_learned_rejects_ligands_above_max_rot():
+    """Asynchronous learned calls run max_rot x passes step launches, so a
+    ligand with more rotamers than dock_params.max_rot cannot finish: the
+    device validation gives it DOCK_E_LIMIT (and best_orient = -1) while the
+    other ligands get the synchronous call's results."""
+    torch = _torch()
+    from tests.test_parity_gpu import _device_batch
+    pocket, h, net = _proposal_pocket()
+    ligs = synth.ligands(2, count=8, first=200)  # 2-12 rotamers
+    R = np.diff(ligs.rot_offset)
+    cap = int(np.median(R))
+    over = R > cap
+    assert over.any() and not over.all()
+    orient = synth.orientations(learned.LEARN_CONFIG)
+    d, od, out = _device_batch(ligs, orient, 256, torch)
+    out["n_fallback"] = torch.empty(ligs.n_ligands, dtype=torch.int32, device="cuda:0")
+    st = torch.cuda.Stream()
+    prm = dock.make_params(mode=dock.DOCK_MODE_LEARNED, top_k=16, margin=0.4,
+                           max_atoms=int(np.diff(ligs.atom_offset).max()), max_rot=cap)
+    print(f"[gpu] learned async, max_rot={cap}, {int(over.sum())} ligands above it", flush=True)
+    dock.dock_batch_async(h, d, od, 256, out, prm, stream=st)
+    st.synchronize()
+    status = out["status"].cpu().numpy()
+    assert (status[over] == dock.DOCK_E_LIMIT).all()
+    assert (status[~over] == 0).all()
+    bo = out["best_orient"].cpu().numpy()
+    assert (bo[over] == -1).all() and (bo[~over] >= 0).all()
+    keep = np.nonzero(~over)[0]
+    ref = dock.dock_batch(h, ligs.subset(keep), orient, 256, mode=dock.DOCK_MODE_LEARNED, top_k=16,
+                          margin=0.4, want_all=True)
+    assert np.array_equal(out["all_scores"].cpu().numpy()[keep], ref["all_scores"])
+    assert np.array_equal(bo[keep], ref["best_orient"])
+    # a HIP graph cannot hold the learned mode's buffer growth: refused
+    with pytest.raises(dock.DockError) as e:
+        dock.dock_batch_async(h, d, od, 256, out,
+                              dock.make_params(mode=dock.DOCK_MODE_LEARNED, flags=dock.DOCK_FLAG_GRAPH),
+                              stream=st)
+    assert e.value.code == dock.DOCK_E_INVAL
+    h.close()

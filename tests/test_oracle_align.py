@@ -84,6 +84,7 @@ def test_alignment_is_rigid_and_matches_brute_force():
     rots = synth.align_rotations(2, 64)
     R64 = rots.astype(np.float64)
     orient = synth.orientations(2, n=3)
+    checked = total = 0
     for l in range(ligs.n_ligands):
         lig = ligs.ligand(l)
         none = np.full(max(1, len(lig["rot_axis"])), -1, np.int16)
@@ -95,9 +96,12 @@ def test_alignment_is_rigid_and_matches_brute_force():
             # atom sits within the ambiguity band of a voxel face
             for a in range(len(rots)):
                 s = np_voxel(p, c + (X - c) @ R64[a].T).sum()
+                total += 1
                 if not tr.align_flags[a] & oracle.FLAG_SAMB:
                     assert abs(s - tr.align_s[a]) <= 1e-9, (l, o, a)
+                    checked += 1
                 assert tr.align_lo[a] - 1e-9 <= tr.align_s[a] <= tr.align_hi[a] + 1e-9
+                assert tr.align_lo[a] - 1e-9 <= s <= tr.align_hi[a] + 1e-9
             assert tr.a_star == int(np.argmax(tr.align_s))
             assert tr.align_s[tr.a_star] >= tr.align_s[0]  # the identity is a candidate
             Y = tr.xyz  # no rotamer moves: the aligned pose itself
@@ -107,6 +111,7 @@ def test_alignment_is_rigid_and_matches_brute_force():
             dY = np.linalg.norm(Y[:, None] - Y[None], axis=-1)
             np.testing.assert_allclose(dY, dX, atol=1e-9)
             assert tr.score == tr.align_s[tr.a_star]
+    assert checked >= 0.8 * total, (checked, total)
 
 
 def test_alignment_then_sweep_equals_the_composed_orientation():

@@ -43,6 +43,7 @@ def test_linear_grid_closed_form():
     S = 48
     tr = oracle.trace_item(p, lig, IDENTITY, S, r_bump=0.0)
     X = lig["xyz"].astype(np.float64)
+    checked = 0
     for r in range(len(lig["rot_axis"])):
         a, b = lig["rot_axis"][r]
         M = lig["move_atoms"][lig["move_offset"][r]:lig["move_offset"][r + 1]]
@@ -53,9 +54,13 @@ def test_linear_grid_closed_form():
             ix = np.clip(np.floor((Y[:, 0] - p.origin[0]) / p.spacing), 0, 39)
             if not tr.prof_flags[r, k] & oracle.FLAG_SAMB:
                 assert tr.prof_s[r, k] == ix.sum()
+                checked += 1
+            else:
+                assert tr.prof_lo[r, k] <= ix.sum() <= tr.prof_hi[r, k]
         k = int(tr.k_star[r])
         if k:
             X[M] = scipy_rotate(X[M], X[a], X[b], 2 * np.pi * k / S)
+    assert checked >= 0.95 * len(lig["rot_axis"]) * S, checked
 
 
 def test_single_hot_voxel_hitting_angle():

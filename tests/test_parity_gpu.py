@@ -44,6 +44,7 @@ def test_c1_parity(pockets):
     rep = check_batch(p, ligs, orient, 64, res)
     print(rep.summary())
     assert rep.ok(), rep.summary()
+    rep.assert_rare()
     ref = oracle.dock_batch(p, ligs, orient, 64)
     assert abs(res["best_score"][0] - ref.best_score[0]) <= tol_of(ref.best_score[0])
     assert np.abs(res["all_scores"] - ref.all_scores).max() <= tol_of(np.abs(ref.all_scores).max())
@@ -60,11 +61,13 @@ def test_c2_subset_parity(pockets):
     rep = check_batch(p, ligs, orient, 256, res, ligands=range(6))
     print(rep.summary())
     assert rep.ok(), rep.summary()
+    rep.assert_rare()
     rng = np.random.default_rng(0)
     rep2 = check_batch(p, ligs, orient, 256, res, ligands=range(200),
                        orients=rng.choice(256, 8, replace=False))
     print(rep2.summary())
     assert rep2.ok(), rep2.summary()
+    rep2.assert_rare()
     amb = rep2.steps["ambiguous"] / max(1, sum(rep2.steps.values()))
     assert amb < 0.01
 
@@ -79,6 +82,7 @@ def test_c3_subset_parity(pockets):
                       orients=rng.choice(128, 4, replace=False))
     print(rep.summary())
     assert rep.ok(), rep.summary()
+    rep.assert_rare()
 
 
 def test_c5_subset_parity(pockets):
@@ -91,6 +95,7 @@ def test_c5_subset_parity(pockets):
                       orients=rng.choice(64, 2, replace=False))
     print(rep.summary())
     assert rep.ok(), rep.summary()
+    rep.assert_rare()
 
 
 def test_full_c2_batch_in_bench_configuration(pockets):
@@ -116,6 +121,7 @@ def test_full_c2_batch_in_bench_configuration(pockets):
                       orients=rng.choice(256, 3, replace=False))
     print(rep.summary())
     assert rep.ok(), rep.summary()
+    rep.assert_rare()
 
 
 def test_determinism_and_order_independence(pockets):
@@ -144,12 +150,14 @@ def test_edge_cases(pockets):
         res = dock.dock_batch(h, ligs, orient, S, want_all=True)
         rep = check_batch(p, ligs, orient, S, res)
         assert rep.ok(), (S, rep.summary())
+        rep.assert_rare()
         assert np.array_equal(res["best_score"][0], res["best_score"][3])
     # a bump radius so large that no angle (not even k = 0) is valid: k* = -1, no move
     res = dock.dock_batch(h, ligs, orient, 16, r_bump=50.0, want_all=True)
     assert (res["angle_idx"] == -1).all()
     rep = check_batch(p, ligs, orient, 16, res, r_bump=50.0)
     assert rep.ok(), rep.summary()
+    rep.assert_rare()
     # empty batch
     empty = synth.Ligands.from_parts([])
     res = dock.dock_batch(h, empty, orient, 16)
@@ -171,6 +179,7 @@ def test_step_counts_around_mask_words(pockets, S):
     rep = check_batch(p, ligs, orient, S, res)
     print(rep.summary())
     assert rep.ok(), (S, rep.summary())
+    rep.assert_rare()
 
 
 def test_max_size_ligand(pockets):
@@ -200,6 +209,7 @@ def test_max_size_ligand(pockets):
     rep = check_batch(p, ligs, orient, 32, res)
     print(rep.summary())
     assert rep.ok(), rep.summary()
+    rep.assert_rare()
 
 
 def test_passes_refinement(pockets):
@@ -211,6 +221,7 @@ def test_passes_refinement(pockets):
     rep = check_batch(p, ligs, orient, 64, res, passes=3)
     print(rep.summary())
     assert rep.ok(), rep.summary()
+    rep.assert_rare()
 
 
 def test_invalid_inputs_rejected_before_launch(pockets):
@@ -237,11 +248,13 @@ def test_direct_bump_mode_parity(pockets):
     rep = check_batch(p, ligs, orient, 256, res, ligands=range(40), orients=range(0, 32, 4))
     print(rep.summary())
     assert rep.ok(), rep.summary()
+    rep.assert_rare()
     ligs1 = synth.ligands(1)
     o1 = synth.orientations(1)
     p1, r1 = _run(pockets, 1, ligs1, o1, 64, flags=dock.DOCK_FLAG_DIRECT_BUMP)
     rep = check_batch(p1, ligs1, o1, 64, r1)
     assert rep.ok(), rep.summary()
+    rep.assert_rare()
 
 
 def test_results_independent_of_launch_mapping(pockets):
