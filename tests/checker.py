@@ -41,6 +41,7 @@ class Report:
     failures: list = field(default_factory=list)
     items: int = 0
     score_band: int = 0     # final scores accepted only inside the reference's interval
+    score_flagged: int = 0  # items whose reference final pose has an atom within the face band
     max_coord_err: float = 0.0
     max_score_rel: float = 0.0
 
@@ -53,18 +54,23 @@ class Report:
         n_steps = sum(v for k, v in self.steps.items() if not k.startswith("align_"))
         return (self.steps["ambiguous"] / max(1, n_steps), self.score_band / max(1, self.items))
 
-    def assert_rare(self, step_frac: float = 0.01, score_frac: float = 0.02) -> None:
+    def assert_rare(self, step_frac: float = 0.01, flagged_frac: float = 0.5) -> None:
         """Acceptances through the ambiguity band must stay rare: at delta =
         1e-4 A an FP32 pose lands across a face or r_bump only occasionally.
+        A final score can fall in its band only through an atom within delta
+        of a voxel face (score_flagged counts those items); an FP32 pose off
+        by ~1e-5 A crosses such a face in well under half of them, whereas a
+        kernel that indexed voxels wrongly at faces would cross in nearly all.
         A batch of a few items may hold one or two such cases."""
         n_steps = sum(v for k, v in self.steps.items() if not k.startswith("align_"))
         amb_ok = max(2.0, step_frac * n_steps)
-        band_ok = max(1.0, score_frac * self.items)
+        band_ok = max(2.0, flagged_frac * self.score_flagged)
         assert self.steps["ambiguous"] <= amb_ok, f"too many ambiguous steps: {self.summary()}"
         assert self.score_band <= band_ok, f"too many band-accepted scores: {self.summary()}"
 
     def summary(self) -> str:
         return (f"items={self.items} steps={dict(self.steps)} score_band={self.score_band} "
+                f"(of {self.score_flagged} flagged) "
                 f"max|dx|={self.max_coord_err:.2e} "
                 f"max score rel={self.max_score_rel:.2e} failures={len(self.failures)} "
                 f"{self.failures[:5]}")
@@ -136,6 +142,8 @@ def check_item(pocket, lig, orient, S, r_bump, passes, gpu_k, gpu_score, gpu_xyz
             counts[c] += 1
     tol = tol_of(tr.score)
     rel = abs(gpu_score - tr.score) / max(abs(tr.score), 1.0)
+    if tr.score_lo < tr.score_hi:
+        counts["score_flagged"] += 1
     if abs(gpu_score - tr.score) > tol:
         if tr.score_lo - tol <= gpu_score <= tr.score_hi + tol:
             counts["score_band"] += 1
@@ -194,6 +202,7 @@ def check_batch(pocket, ligs, orient, S, res, r_bump=2.0, passes=1, ligands=None
         for l, o, counts, fails, dx, rel in ex.map(run, jobs):
             rep.items += 1
             rep.score_band += counts.pop("score_band", 0)
+            rep.score_flagged += counts.pop("score_flagged", 0)
             rep.steps.update(counts)
             rep.max_coord_err = max(rep.max_coord_err, dx)
             rep.max_score_rel = max(rep.max_score_rel, rel)

@@ -77,10 +77,23 @@ def test_rarity_bound():
     else:
         raise AssertionError("30 ambiguous steps in 1020 passed the 1 % bound")
     r.steps["ambiguous"] = 0
-    r.score_band = 5
+    r.score_band = 2
+    r.assert_rare()
+    r.score_band = 3
     try:
         r.assert_rare()
     except AssertionError:
         pass
     else:
-        raise AssertionError("5 band-accepted scores in 100 items passed the 2 % bound")
+        raise AssertionError("3 band-accepted scores with no flagged item passed")
+    # half the items whose final pose sits within the face band may cross it
+    r.score_flagged = 20
+    r.score_band = 10
+    r.assert_rare()
+    r.score_band = 11
+    try:
+        r.assert_rare()
+    except AssertionError:
+        pass
+    else:
+        raise AssertionError("11 band-accepted scores of 20 flagged items passed the 1/2 bound")
