@@ -197,6 +197,26 @@ int dock_batch_async(dock_pocket *p, const dock_ligands *ligs,
                      const dock_params *prm, dock_results *out,
                      void *workspace, size_t workspace_bytes, void *stream);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): dock_batch_async in plain
+ * mode with no workspace argument.  The workspace is a fixed device array of
+ * DOCK_STATIC_SCRATCH_BYTES inside the library, one copy per device, held
+ * until the process ends; its address is resolved by dock_init_pocket.  The
+ * call allocates nothing (no hipMalloc, no hipFree, no allocating library
+ * routine) and otherwise behaves as dock_batch_async with workspace = NULL.
+ * Every call on one device shares that device's array and overwrites what
+ * the previous call left there (the counters it needs zeroed are cleared by
+ * the call's own kernels), so calls that overlap in time on one device race:
+ * serialise them (one stream, or wait between them).
+ * Errors: as dock_batch_async; DOCK_E_LIMIT when dock_workspace_size() of
+ * the batch exceeds DOCK_STATIC_SCRATCH_BYTES (e.g. 10,000 ligands of 12
+ * rotamers at 256 orientations need about 59 MiB); DOCK_E_INVAL for
+ * DOCK_MODE_LEARNED or DOCK_FLAG_GRAPH, which allocate. */
+#define DOCK_STATIC_SCRATCH_BYTES (64u << 20)
+int dock_batch_async_static(dock_pocket *p, const dock_ligands *ligs,
+                            const float *orient, int n_orient, int angle_steps,
+                            const dock_params *prm, dock_results *out, void *stream);
+
 /* Bytes of device workspace dock_batch_async needs for these sizes (n_align
  * as in dock_params: alignment adds 50 bytes per item). */
 size_t dock_workspace_size(int32_t n_ligands, int64_t total_rot, int n_orient,

@@ -28,6 +28,16 @@ using namespace dock;
 // Timed calls whose sweep start/end events a handle keeps (dock_sweep_ms_history).
 constexpr int kTimingRing = 16;
 
+// Fixed workspace of dock_batch_async_static: one copy per device, held from
+// the library's load until the process ends.  Host code never takes this
+// symbol's address directly (on the host it names a stand-in, not device
+// memory): dock_init_pocket resolves each device's copy once with
+// hipGetSymbolAddress and the handle keeps that pointer.
+static __device__ __align__(256) unsigned char scratch[DOCK_STATIC_SCRATCH_BYTES];
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[kMaxDevices] = {};
+
 struct dock_pocket {
   int device = 0;
   float *d_grid = nullptr;
@@ -50,6 +60,7 @@ struct dock_pocket {
   bool align_timed = false;
   unsigned long long *h_work = nullptr;  // pinned copy of the sweep's two work counters
   LaunchPlan plan{0, 0, 16};
+  void *scratch = nullptr;    // this device's copy of the static workspace
   // last captured launch sequence of dock_batch_async (DOCK_FLAG_GRAPH)
   std::vector<unsigned char> graph_key;
   hipGraph_t graph = nullptr;
@@ -693,6 +704,25 @@ int dock_init_pocket(const float *grid, int nx, int ny, int nz, const float orig
     delete p;
     return hip_fail(e, "hipDeviceGetAttribute");
   }
+  if (p->device < 0 || p->device >= kMaxDevices) {
+    delete p;
+    return fail(DOCK_E_LIMIT, "device ordinal %d outside [0, %d)", p->device, kMaxDevices);
+  }
+  {
+    // once per device, with that device current (it is: p->device is the
+    // current device)
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[p->device]) {
+      void *ptr = nullptr;
+      e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+      if (e != hipSuccess || !ptr) {
+        delete p;
+        return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol, "hipGetSymbolAddress(scratch)");
+      }
+      g_scratch_ptr[p->device] = ptr;
+    }
+    p->scratch = g_scratch_ptr[p->device];
+  }
   size_t bytes = sizeof(float) * (size_t)nx * ny * nz;
   e = hipMalloc((void **)&p->d_grid, bytes);
   if (e != hipSuccess) {
@@ -746,10 +776,14 @@ void dock_free_pocket(dock_pocket *p) {
   delete p;
 }
 
-int dock_batch_async(dock_pocket *p, const dock_ligands *ligs, const float *orient, int n_orient,
-                     int angle_steps, const dock_params *prm, dock_results *out, void *workspace,
-                     size_t workspace_bytes, void *stream) {
-  g_last_error.clear();
+}  // extern "C"
+
+// Host-side checks shared by the two asynchronous entry points: sizes,
+// non-NULL arrays and that every array is device-accessible.  Runs with the
+// handle's device current.
+static int check_async_args(const dock_pocket *p, const dock_ligands *ligs, const float *orient,
+                            int n_orient, int angle_steps, const dock_params *prm,
+                            const dock_results *out, const void *workspace) {
   if (!p || !ligs || !orient || !out) return fail(DOCK_E_INVAL, "NULL argument");
   int rc = check_params(prm, n_orient, angle_steps);
   if (rc) return rc;
@@ -763,7 +797,6 @@ int dock_batch_async(dock_pocket *p, const dock_ligands *ligs, const float *orie
   if (ligs->n_ligands > 0 && (!out->best_score || !out->best_orient || !out->xyz_out))
     return fail(DOCK_E_INVAL, "result array is NULL");
   if (ligs->total_rot > 0 && !out->angle_idx) return fail(DOCK_E_INVAL, "angle_idx is NULL");
-  DeviceGuard g(p->device);
   {
     const bool rot = ligs->total_rot > 0, mv = ligs->total_move > 0, al = prm->n_align > 0;
     const std::pair<const void *, const char *> ptrs[] = {
@@ -780,6 +813,21 @@ int dock_batch_async(dock_pocket *p, const dock_ligands *ligs, const float *orie
       for (const auto &q : ptrs)
         if ((rc = abi_check_device(q.first, q.second)) != DOCK_OK) return rc;
   }
+  if (prm->max_rot < 0 || prm->max_rot > DOCK_MAX_ROT)
+    return fail(DOCK_E_LIMIT, "max_rot outside [0, 255]");
+  return DOCK_OK;
+}
+
+extern "C" {
+
+int dock_batch_async(dock_pocket *p, const dock_ligands *ligs, const float *orient, int n_orient,
+                     int angle_steps, const dock_params *prm, dock_results *out, void *workspace,
+                     size_t workspace_bytes, void *stream) {
+  g_last_error.clear();
+  if (!p) return fail(DOCK_E_INVAL, "NULL argument");
+  DeviceGuard g(p->device);
+  int rc = check_async_args(p, ligs, orient, n_orient, angle_steps, prm, out, workspace);
+  if (rc) return rc;
   std::lock_guard<std::mutex> lk(p->mu);
   if (!workspace) {
     size_t need = dock_workspace_size(ligs->n_ligands, ligs->total_rot, n_orient, angle_steps,
@@ -790,8 +838,6 @@ int dock_batch_async(dock_pocket *p, const dock_ligands *ligs, const float *orie
     workspace_bytes = p->ws_bytes;
   }
   hipStream_t st = (hipStream_t)stream;
-  if (prm->max_rot < 0 || prm->max_rot > DOCK_MAX_ROT)
-    return fail(DOCK_E_LIMIT, "max_rot outside [0, 255]");
   const int max_rot = prm->max_rot > 0 ? prm->max_rot : DOCK_MAX_ROT;
   if (!(prm->flags & DOCK_FLAG_GRAPH))
     return enqueue_batch(p, ligs, orient, n_orient, angle_steps, prm, out, workspace,
@@ -853,6 +899,32 @@ int dock_batch_async(dock_pocket *p, const dock_ligands *ligs, const float *orie
     ring_advance(p);
   }
   return DOCK_OK;
+}
+
+int dock_batch_async_static(dock_pocket *p, const dock_ligands *ligs, const float *orient,
+                            int n_orient, int angle_steps, const dock_params *prm,
+                            dock_results *out, void *stream) {
+  g_last_error.clear();
+  if (!p) return fail(DOCK_E_INVAL, "NULL argument");
+  DeviceGuard g(p->device);
+  int rc = check_async_args(p, ligs, orient, n_orient, angle_steps, prm, out, nullptr);
+  if (rc) return rc;
+  // learned mode grows handle-owned buffers and a graph needs instantiating:
+  // both allocate
+  if (prm->mode != DOCK_MODE_PLAIN)
+    return fail(DOCK_E_INVAL, "dock_batch_async_static runs the plain sweep only");
+  if (prm->flags & DOCK_FLAG_GRAPH)
+    return fail(DOCK_E_INVAL, "dock_batch_async_static does not take DOCK_FLAG_GRAPH");
+  if (!p->scratch) return fail(DOCK_E_STATE, "static workspace not resolved for this handle");
+  const size_t need = dock_workspace_size(ligs->n_ligands, ligs->total_rot, n_orient, angle_steps,
+                                          prm->passes, prm->n_align);
+  if (need == 0 || need > (size_t)DOCK_STATIC_SCRATCH_BYTES)
+    return fail(DOCK_E_LIMIT, "batch needs %zu bytes of workspace; the static workspace holds %zu",
+                need, (size_t)DOCK_STATIC_SCRATCH_BYTES);
+  std::lock_guard<std::mutex> lk(p->mu);
+  const int max_rot = prm->max_rot > 0 ? prm->max_rot : DOCK_MAX_ROT;
+  return enqueue_batch(p, ligs, orient, n_orient, angle_steps, prm, out, p->scratch,
+                       (size_t)DOCK_STATIC_SCRATCH_BYTES, (hipStream_t)stream, max_rot);
 }
 
 static int run_sync(dock_pocket *p, const dock_ligands *ligs, const float *orient, int n_orient,

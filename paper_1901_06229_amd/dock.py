@@ -21,6 +21,7 @@ DOCK_FLAG_TIME_SWEEP = 2
 DOCK_FLAG_DIRECT_BUMP = 4
 DOCK_FLAG_GRAPH = 8
 DOCK_MAX_ATOMS, DOCK_MAX_ROT, DOCK_MAX_STEPS = 256, 255, 4096
+DOCK_STATIC_SCRATCH_BYTES = 64 << 20
 
 _P = ctypes.c_void_p
 
@@ -99,6 +100,9 @@ def load_library(path: str = None):
                                      c.POINTER(dock_params), c.POINTER(dock_results), _P,
                                      c.c_size_t, _P]
     lib.dock_batch_async.restype = c.c_int
+    lib.dock_batch_async_static.argtypes = [_P, c.POINTER(dock_ligands), _P, c.c_int, c.c_int,
+                                            c.POINTER(dock_params), c.POINTER(dock_results), _P]
+    lib.dock_batch_async_static.restype = c.c_int
     lib.dock_workspace_size.argtypes = [c.c_int32, c.c_int64, c.c_int, c.c_int, c.c_int, c.c_int]
     lib.dock_workspace_size.restype = c.c_size_t
     lib.dock_last_sweep_ms.argtypes = [_P, c.POINTER(c.c_float)]
@@ -360,6 +364,19 @@ def _tptr(t):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
 
 
+def _async_structs(dev: dict, out: dict):
+    dl = dock_ligands(int(dev["n_ligands"]), int(dev["total_atoms"]), int(dev["total_rot"]),
+                      int(dev["total_move"]), _tptr(dev["atom_offset"]), _tptr(dev["xyz"]),
+                      _tptr(dev["rot_offset"]), _tptr(dev.get("rot_axis")),
+                      _tptr(dev.get("move_offset")), _tptr(dev.get("move_atoms")))
+    dr = dock_results(_tptr(out["best_score"]), _tptr(out["best_orient"]),
+                      _tptr(out.get("angle_idx")), _tptr(out["xyz"]),
+                      _tptr(out.get("all_scores")), _tptr(out.get("all_angle_idx")),
+                      _tptr(out.get("status")), _tptr(out.get("n_fallback")),
+                      _tptr(out.get("align_idx")), _tptr(out.get("all_align_idx")))
+    return dl, dr
+
+
 def dock_batch_async(pocket: Pocket, dev: dict, orient_dev, angle_steps: int, out: dict,
                      params: dock_params, workspace=None, stream=None):
     """Enqueue a batch whose arrays are device tensors (torch) on ``stream``.
@@ -370,15 +387,7 @@ def dock_batch_async(pocket: Pocket, dev: dict, orient_dev, angle_steps: int, ou
     all_scores, all_angle_idx, status, n_fallback, align_idx, all_align_idx.
     """
     lib = load_library()
-    dl = dock_ligands(int(dev["n_ligands"]), int(dev["total_atoms"]), int(dev["total_rot"]),
-                      int(dev["total_move"]), _tptr(dev["atom_offset"]), _tptr(dev["xyz"]),
-                      _tptr(dev["rot_offset"]), _tptr(dev.get("rot_axis")),
-                      _tptr(dev.get("move_offset")), _tptr(dev.get("move_atoms")))
-    dr = dock_results(_tptr(out["best_score"]), _tptr(out["best_orient"]),
-                      _tptr(out.get("angle_idx")), _tptr(out["xyz"]),
-                      _tptr(out.get("all_scores")), _tptr(out.get("all_angle_idx")),
-                      _tptr(out.get("status")), _tptr(out.get("n_fallback")),
-                      _tptr(out.get("align_idx")), _tptr(out.get("all_align_idx")))
+    dl, dr = _async_structs(dev, out)
     n_orient = int(orient_dev.shape[0])
     ws_ptr = _tptr(workspace)
     ws_bytes = 0 if workspace is None else workspace.numel() * workspace.element_size()
@@ -386,6 +395,20 @@ def dock_batch_async(pocket: Pocket, dev: dict, orient_dev, angle_steps: int, ou
     _check(lib.dock_batch_async(pocket.handle, ctypes.byref(dl), _tptr(orient_dev), n_orient,
                                 int(angle_steps), ctypes.byref(params), ctypes.byref(dr), ws_ptr,
                                 ws_bytes, st), "dock_batch_async")
+
+
+def dock_batch_async_static(pocket: Pocket, dev: dict, orient_dev, angle_steps: int, out: dict,
+                            params: dock_params, stream=None):
+    """dock_batch_async in plain mode on the library's fixed per-device
+    workspace: allocates nothing (batches needing more than
+    DOCK_STATIC_SCRATCH_BYTES of workspace are refused)."""
+    lib = load_library()
+    dl, dr = _async_structs(dev, out)
+    st = None if stream is None else ctypes.c_void_p(stream.cuda_stream)
+    _check(lib.dock_batch_async_static(pocket.handle, ctypes.byref(dl), _tptr(orient_dev),
+                                       int(orient_dev.shape[0]), int(angle_steps),
+                                       ctypes.byref(params), ctypes.byref(dr), st),
+           "dock_batch_async_static")
 
 
 # ---------------------------------------------------------------- learned proposal

@@ -55,6 +55,7 @@ def test_null_arguments_are_rejected_on_the_host(lib):
     assert lib.dock_init_pocket(g, 2, 2, 2, o, -1.0, ctypes.byref(h)) == dock.DOCK_E_INVAL
     assert lib.dock_batch(None, None, None, 1, 1, None, None) == dock.DOCK_E_INVAL
     assert lib.dock_batch_async(None, None, None, 1, 1, None, None, None, 0, None) == dock.DOCK_E_INVAL
+    assert lib.dock_batch_async_static(None, None, None, 1, 1, None, None, None) == dock.DOCK_E_INVAL
     lib.dock_free_pocket(None)
 
 
