@@ -1,14 +1,19 @@
 """Throughput benchmark of the batched rotamer sweep on one MI355X.
 
-Default workload: 10,000 ligands (20-80 atoms, 2-12 rotamers) x 256 rigid
-orientations x 256 angle steps against a 128^3 pocket (synthetic, seeded).
-Inputs are resident in HBM before the timed region; one step = one
+Headline workload: 100,000 ligands (lognormal 8-150 atoms, 0-40 rotamers) x
+128 rigid orientations x 128 angle steps against a 128^3 pocket (synthetic,
+seeded), launch mapping autotuned, the launch sequence replayed as a HIP
+graph.  Inputs are resident in HBM before the timed region; one step = one
 dock_batch_async call over the whole batch (every restart of every ligand,
 the per-ligand best reduction and the pose write-back).
 
 Prints one JSON line (rank 0): ligands/s, the sweep kernel's roofline
-fraction (HIP events around that kernel on its own stream) and the FP64
-reference timed on a bounded sample on the host cores.
+fraction (HIP events on the kernel's own stream), the synchronous
+host-array figure (H2D + kernels + D2H), the FP64 reference timed on bounded
+samples on the host cores, and the extra legs under their own keys: the
+10,000-ligand batch (c2, with the rigid-alignment leg), the large-ligand
+batch (c5, plain and learned proposal side by side, per-ligand error against
+the FP64 reference) and the learned-proposal comparison (learned).
 """
 from __future__ import annotations
 
@@ -57,7 +62,7 @@ ALIGN_ROTATIONS = 64
 # Sources of the sweep kernel: the HBM traffic measured by the FETCH_SIZE /
 # WRITE_SIZE counters is reported only while these are unchanged.
 KERNEL_SOURCES = ("sweep_pruned.hip", "rotamer_step.h", "sweep_common.h", "dock_internal.h")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_pruned_c2_traffic.md")
+TRAFFIC_FILES = {cfg: os.path.join(ROOT, "profiles", f"sweep_pruned_c{cfg}_traffic.md") for cfg in (2, 3, 5)}
 
 WORKLOADS = {
     1: "C1: 64^3 pocket @0.5A, 1 ligand (32 atoms, 4 rotamers), 8 orientations, 64 steps",
@@ -115,11 +120,14 @@ def kernel_sources_digest() -> str:
     return h.hexdigest()
 
 
-def measured_traffic():
-    """HBM bytes per sweep launch from the committed counter summary, if it
-    was taken on the current kernel sources (else None)."""
+def measured_traffic(cfg):
+    """HBM bytes per sweep launch of this workload from the committed counter
+    summary, if it was taken on the current kernel sources (else None)."""
+    path = TRAFFIC_FILES.get(cfg)
+    if path is None:
+        return None
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(path) as f:
             fields = dict(l.split(":", 1) for l in f.read().splitlines() if l.startswith(("traffic_", "sources_")))
     except OSError:
         return None
@@ -154,36 +162,6 @@ def copy_calibration():
         dst.copy_(src)
     torch.cuda.synchronize()
     print("copied 1 GiB x 3", flush=True)
-
-
-def cpu_baseline(pocket, ligs, orient, S, budget_s=20.0, gpu_best=None):
-    """The FP64 reference on a bounded sample of the same workload: the first
-    ligands, doubling the count until one run takes at least budget_s / 2.
-    gpu_best: optional {name: per-ligand best scores of a GPU run}; each is
-    compared with the reference on the sampled ligands."""
-    import oracle
-    threads = min(16, os.cpu_count() or 1)
-    sample = 8
-    t_used = 0.0
-    while True:
-        sub = ligs.subset(range(sample))
-        t0 = time.perf_counter()
-        ref = oracle.dock_batch(pocket, sub, orient, S, n_threads=threads).best_score
-        t_used = time.perf_counter() - t0
-        if t_used >= budget_s / 2 or sample * 2 > ligs.n_ligands:
-            break
-        sample *= 2
-    res = {"value": sample / t_used, "unit": "ligands/s", "cores": threads, "kind": "oracle",
-           "sample": f"first {sample} ligands of the workload, all orientations and steps, "
-                     f"FP64, {threads} threads, {t_used:.1f} s"}
-    if gpu_best:
-        res["best_score_vs_oracle"] = {
-            name: {"ligands": sample,
-                   "max_rel_err": float(np.max(np.abs(b[:sample] - ref) / np.maximum(np.abs(ref), 1.0))),
-                   "mean_rel_err": float(np.mean(np.abs(b[:sample] - ref) / np.maximum(np.abs(ref), 1.0))),
-                   "mean_loss": float(np.mean((ref - b[:sample]) / np.maximum(np.abs(ref), 1.0)))}
-            for name, b in gpu_best.items()}
-    return res
 
 
 def device_batch(ligs, orient, want_all=False):
@@ -400,82 +378,69 @@ def align_leg(cfg, h, ligs, d, orient_d, S, out, stream, steps, warmup, max_atom
     }
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    # the first sweep after the batch is staged runs ~10 % slower (22.3 ms,
-    # then 20.0 ms on the 10,000-ligand x 256 x 256 batch)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", type=int, default=2, choices=sorted(WORKLOADS))
-    ap.add_argument("--ligands", type=int, default=0, help="override the ligand count")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--bump", choices=("pruned", "direct"), default="pruned",
-                    help="pruned: test only pairs that can clash; direct: every pair")
-    ap.add_argument("--waves", type=int, default=0,
-                    help="waves per block of the sweep (0: the most resident waves)")
-    ap.add_argument("--claim", type=int, default=16,
-                    help="most items a wave takes per work-queue atomic")
-    ap.add_argument("--autotune", type=int, default=None,
-                    help="time every launch mapping on this many sampled ligands first and keep "
-                         "the fastest (default: 2000 for the uneven-batch workload, else off: its "
-                         "pick varies with timing noise between runs, and the gain elsewhere is ~1 %%)")
-    ap.add_argument("--graph", action=argparse.BooleanOptionalAction, default=None,
-                    help="replay the batch's launch sequence as a captured HIP graph "
-                         "(default: on for the uneven-batch workload)")
-    ap.add_argument("--no-learned", action="store_true", help="skip the learned-proposal comparison")
-    ap.add_argument("--align", type=int, default=ALIGN_ROTATIONS,
-                    help="rotations of the rigid-alignment leg (0: skip it)")
-    ap.add_argument("--proposal", default=None, help="directory of trained proposal weights")
-    ap.add_argument("--copy-calibration", action="store_true",
-                    help="only run the 1 GiB copy that calibrates the HBM byte counters")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(a batch would shard by ligand, with no exchange between GPUs)", file=sys.stderr)
-        sys.exit(2)
+def cpu_info() -> dict:
+    """Host description for the oracle timings: model, logical CPUs and the
+    CPUs this process may run on."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for l in f:
+                if l.startswith("model name"):
+                    model = l.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        allowed = len(os.sched_getaffinity(0))
+    except AttributeError:
+        allowed = os.cpu_count()
+    return {"model": model, "nproc": os.cpu_count(), "allowed": allowed}
 
-    if args.copy_calibration:
-        copy_calibration()
-        return
 
+def upload(ligs, orient, n_orient, S, want_all=False):
+    """CSR batch, orientation table, results and workspace as device tensors."""
     import torch
-    from paper_1901_06229_amd import dock, synth
-
-    cfg = args.config
-    preset = synth.PRESETS[cfg]
-    S, O = preset["angle_steps"], preset["n_orient"]
-    L = args.ligands or preset["n_ligands"]
-    log(f"config {cfg}: generating {L} ligands")
-    pocket = synth.pocket(cfg)
-    ligs = synth.ligands(cfg, count=L)
-    orient = synth.orientations(cfg)
-    torch.cuda.set_device(0)
+    from paper_1901_06229_amd import dock
     dev = torch.device("cuda:0")
-    h = dock.dock_init_pocket(pocket.grid, pocket.origin, pocket.spacing)
     d = dict(n_ligands=ligs.n_ligands, total_atoms=int(ligs.atom_offset[-1]),
              total_rot=int(ligs.rot_offset[-1]), total_move=int(ligs.move_offset[-1]))
     for k, dt in (("atom_offset", torch.int32), ("xyz", torch.float32), ("rot_offset", torch.int32),
                   ("rot_axis", torch.int32), ("move_offset", torch.int32), ("move_atoms", torch.int16)):
         d[k] = torch.from_numpy(np.ascontiguousarray(getattr(ligs, k))).to(dev, dt)
-    orient_d = torch.from_numpy(orient).to(dev)
-    NA, NR = d["total_atoms"], d["total_rot"]
+    L, NA, NR = ligs.n_ligands, d["total_atoms"], d["total_rot"]
     out = dict(best_score=torch.empty(L, device=dev), best_orient=torch.empty(L, dtype=torch.int32, device=dev),
                angle_idx=torch.empty(max(NR, 1), dtype=torch.int16, device=dev),
                xyz=torch.empty(max(NA, 1), 3, device=dev),
                status=torch.empty(L, dtype=torch.int32, device=dev))
-    ws = torch.empty(dock.dock_workspace_size(L, NR, O, S), dtype=torch.uint8, device=dev)
+    ws = torch.empty(dock.dock_workspace_size(L, NR, n_orient, S), dtype=torch.uint8, device=dev)
+    return d, torch.from_numpy(np.ascontiguousarray(orient)).to(dev), out, ws
+
+
+def plain_leg(cfg, steps, warmup, bump="pruned", waves=0, claim=16, autotune=0, graph=False,
+              n_ligands=0, end_to_end=True):
+    """Time the plain batched sweep on one workload: warm-up steps, then
+    `steps` dock_batch_async calls enqueued back to back on resident inputs.
+    Returns (result dict, context for the legs that reuse the batch)."""
+    import torch
+    from paper_1901_06229_amd import dock, synth
+    preset = synth.PRESETS[cfg]
+    S, O = preset["angle_steps"], preset["n_orient"]
+    L = n_ligands or preset["n_ligands"]
+    log(f"config {cfg}: generating {L} ligands")
+    pocket = synth.pocket(cfg)
+    ligs = synth.ligands(cfg, count=L)
+    orient = synth.orientations(cfg)
+    h = dock.dock_init_pocket(pocket.grid, pocket.origin, pocket.spacing)
+    d, orient_d, out, ws = upload(ligs, orient, O, S)
     max_atoms = int(np.diff(ligs.atom_offset).max())
-    flags = dock.DOCK_FLAG_TIME_SWEEP | (dock.DOCK_FLAG_DIRECT_BUMP if args.bump == "direct" else 0)
-    autotune = args.autotune if args.autotune is not None else (2000 if cfg == 3 else 0)
-    graph = args.graph if args.graph is not None else cfg == 3
+    flags = dock.DOCK_FLAG_TIME_SWEEP | (dock.DOCK_FLAG_DIRECT_BUMP if bump == "direct" else 0)
     if graph:
         flags |= dock.DOCK_FLAG_GRAPH
     prm = dock.make_params(r_bump=synth.R_BUMP, max_atoms=max_atoms, flags=flags)
-    dock.dock_set_launch(h, args.waves, 0, args.claim)
+    dock.dock_set_launch(h, waves, 0, claim)
     tune = None
     if autotune > 0:
-        log(f"autotuning the launch mapping on {autotune} sampled ligands")
+        log(f"config {cfg}: autotuning the launch mapping on {autotune} sampled ligands")
         tune = dock.dock_autotune(h, ligs, orient, S, sample_ligands=min(autotune, L), seed=1,
                                   r_bump=synth.R_BUMP, flags=flags & dock.DOCK_FLAG_DIRECT_BUMP)
     launch = dict(zip(("waves_per_block", "blocks_per_cu", "items_per_claim"), dock.dock_get_launch(h)))
@@ -485,41 +450,37 @@ def main():
     def step():
         dock.dock_batch_async(h, d, orient_d, S, out, prm, workspace=ws, stream=stream)
 
-    for w in range(args.warmup):
+    for w in range(warmup):
         step()
-        log(f"warmup {w}: sweep {dock.dock_last_sweep_ms(h):.1f} ms")
+        log(f"config {cfg}: warmup {w}: sweep {dock.dock_last_sweep_ms(h):.1f} ms")
     torch.cuda.synchronize()
     # the timed steps are enqueued back to back (no host wait between them);
     # the library keeps the sweep events of the last 16 timed calls, read
     # after the loop, in chunks of up to 16 steps
     sweep_ms = []
     t0 = time.perf_counter()
-    for s in range(args.steps):
+    for s in range(steps):
         step()
-        if (s + 1) % 16 == 0 or s + 1 == args.steps:
+        if (s + 1) % 16 == 0 or s + 1 == steps:
             sweep_ms += dock.dock_sweep_ms_history(h, s + 1 - len(sweep_ms))
     stream.synchronize()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    work = [dock.dock_last_sweep_work(h)]  # the same batch every step: the same counters
+    kept_pairs, evals = dock.dock_last_sweep_work(h)  # the same batch every step: the same counters
     # checked after the timed steps: a torch kernel between the warm-up and the
     # first timed sweep made that sweep ~1.3 ms slower on the 256 x 256 batch
     assert int((out["status"] != 0).sum()) == 0
-    for s, ms in enumerate(sweep_ms):
-        log(f"step {s}: sweep {ms:.1f} ms")
-    value = args.steps * L / elapsed
-    gpu_best = {"plain": out["best_score"].cpu().numpy().copy()}
-    kept_pairs, evals = work[-1]
-    ops = algorithmic_ops(ligs, O, S, args.bump, kept_pairs, evals)
+    log(f"config {cfg}: sweep ms per step " + " ".join(f"{ms:.2f}" for ms in sweep_ms))
+    value = steps * L / elapsed
+    best = out["best_score"].cpu().numpy().copy()
+    ops = algorithmic_ops(ligs, O, S, bump, kept_pairs, evals)
     mean_s = float(np.mean(sweep_ms)) / 1e3
     achieved = ops / mean_s / 1e12
     mq, msum = batch_counts(ligs)
     probe = gather_probe(int(np.prod(pocket.grid.shape)))
-    line = {
-        "metric": METRIC, "value": round(value, 2), "unit": "ligands/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * elapsed / args.steps, 3),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
-        "data": "synthetic", "mode": "plain", "bump": args.bump,
+    res = {
+        "value": round(value, 2), "unit": "ligands/s", "steps": steps, "warmup": warmup,
+        "ms_per_step": round(1e3 * elapsed / steps, 3),
         "launch": dict(launch, autotuned=tune is not None, graph=graph,
                        **({"tune_entries": len(tune)} if tune else {})),
         "config": {"workload": WORKLOADS[cfg] if L == preset["n_ligands"] else
@@ -527,16 +488,16 @@ def main():
                    "n_ligands": L, "n_orient": O, "angle_steps": S, "r_bump": synth.R_BUMP},
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 2),
                      "unit": "TOP/s", "frac": round(achieved / VALU_PEAK_TOPS, 4),
-                     "traffic": measured_traffic() if (cfg == 2 and args.bump == "pruned"
-                                                       and L == preset["n_ligands"]) else None,
-                     "kernel": "sweep_pruned_kernel" if args.bump == "pruned" else "sweep_kernel",
+                     "traffic": measured_traffic(cfg) if (bump == "pruned" and L == preset["n_ligands"])
+                     else None,
+                     "kernel": "sweep_pruned_kernel" if bump == "pruned" else "sweep_kernel",
                      "kernel_ms": round(1e3 * mean_s, 3),
                      **({"timed": "around each replayed graph (preparation, sweep, finalize)"}
                         if graph else {}),
                      "work": (f"lane-ops: {OPS_CAND} per candidate pair per rotamer step + "
                               f"{OPS_ARC} per kept pair (clash arc) + {OPS_EVAL} per (moving atom, "
                               "non-bumping angle) evaluation")
-                     if args.bump == "pruned" else
+                     if bump == "pruned" else
                      "dense lane-ops per angle: 8 per cross pair + 45 per moving atom",
                      "candidate_pairs": int(mq * O), "kept_pairs": kept_pairs,
                      "atom_angle_evals": evals,
@@ -554,6 +515,152 @@ def main():
                                  "atom at every angle) per second of this kernel; not a "
                                  "fraction of peak"}},
     }
+    if end_to_end:
+        # the synchronous host-array call: H2D of the batch, the kernels, D2H
+        # of the results (pageable numpy arrays); 1 warm-up, median of 5
+        times = []
+        for rep in range(6):
+            t0 = time.perf_counter()
+            r = dock.dock_batch(h, ligs, orient, S, r_bump=synth.R_BUMP)
+            if rep:
+                times.append(time.perf_counter() - t0)
+        assert np.array_equal(r["best_score"], best), "synchronous and resident runs disagree"
+        med = float(np.median(times))
+        res["end_to_end"] = {
+            "call": "dock_batch on host arrays: H2D + kernels + D2H, pageable host memory",
+            "runs": [round(1e3 * t, 3) for t in times], "median_ms": round(1e3 * med, 3),
+            "ligands_per_s": round(L / med, 2)}
+        log(f"config {cfg}: end to end {1e3 * med:.2f} ms ({L / med:,.0f} ligands/s)")
+    ctx = dict(h=h, pocket=pocket, ligs=ligs, orient=orient, d=d, orient_d=orient_d, out=out,
+               stream=stream, S=S, O=O, max_atoms=max_atoms, best=best, step_s=elapsed / steps)
+    return res, ctx
+
+
+def oracle_check(ctx, gpu_best, budget_s=10.0):
+    """Per-ligand best-score error of GPU runs against the FP64 reference on
+    the first ligands of the batch (as many as fit the time budget)."""
+    import oracle
+    from paper_1901_06229_amd import synth
+    threads = min(16, cpu_info()["allowed"] or 1)
+    ligs = ctx["ligs"]
+    n, ref, t_used = 1, None, 0.0
+    while True:
+        sub = ligs.subset(range(n))
+        t0 = time.perf_counter()
+        ref = oracle.dock_batch(ctx["pocket"], sub, ctx["orient"], ctx["S"], r_bump=synth.R_BUMP,
+                                n_threads=threads).best_score
+        t_used = time.perf_counter() - t0
+        if t_used >= budget_s / 2 or n * 2 > ligs.n_ligands or n >= threads:
+            break
+        n *= 2
+    out = {"ligands": n, "seconds": round(t_used, 1)}
+    for name, b in gpu_best.items():
+        err = (ref - b[:n]) / np.maximum(np.abs(ref), 1.0)
+        out[name] = {"max_abs_rel_err": float(np.max(np.abs(err))),
+                     "mean_abs_rel_err": float(np.mean(np.abs(err))),
+                     "mean_loss": float(np.mean(err)), "per_ligand_rel_err": [float(x) for x in err]}
+    return out
+
+
+def cpu_baseline(ctx, budget_s=16.0, single_s=6.0):
+    """The FP64 reference on bounded samples of the headline workload (the
+    first ligands, doubling the count until one run takes at least half the
+    budget): on every CPU this process may use (at most 16, the host share
+    of one GPU) and on one core."""
+    import oracle
+    from paper_1901_06229_amd import synth
+    info = cpu_info()
+    threads = max(1, min(16, info["allowed"] or 1))
+    ligs = ctx["ligs"]
+
+    def rate(n_threads, budget):
+        n = max(1, n_threads)
+        while True:
+            sub = ligs.subset(range(n))
+            t0 = time.perf_counter()
+            oracle.dock_batch(ctx["pocket"], sub, ctx["orient"], ctx["S"], r_bump=synth.R_BUMP,
+                              n_threads=n_threads)
+            t = time.perf_counter() - t0
+            if t >= budget / 2 or n * 2 > ligs.n_ligands:
+                return n, t
+            n *= 2
+
+    n_all, t_all = rate(threads, budget_s)
+    n_one, t_one = rate(1, single_s)
+    return {"value": n_all / t_all, "unit": "ligands/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {n_all} ligands of the headline workload, all orientations and steps, "
+                      f"FP64, {threads} threads, {t_all:.1f} s",
+            "single_core": {"value": n_one / t_one, "sample": f"first {n_one} ligands, 1 thread, {t_one:.1f} s"},
+            "host": info}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    # the first sweep after a batch is staged runs ~10 % slower
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", type=int, default=3, choices=sorted(WORKLOADS),
+                    help="headline workload (default: the 100,000-ligand uneven batch)")
+    ap.add_argument("--ligands", type=int, default=0, help="override the headline ligand count")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--bump", choices=("pruned", "direct"), default="pruned",
+                    help="pruned: test only pairs that can clash; direct: every pair")
+    ap.add_argument("--waves", type=int, default=0,
+                    help="waves per block of the sweep (0: the most resident waves)")
+    ap.add_argument("--claim", type=int, default=16,
+                    help="most items a wave takes per work-queue atomic")
+    ap.add_argument("--autotune", type=int, default=None,
+                    help="time every launch mapping on this many sampled ligands first and keep "
+                         "the fastest (default: 2000 for the uneven-batch workload, else off)")
+    ap.add_argument("--graph", action=argparse.BooleanOptionalAction, default=None,
+                    help="replay the batch's launch sequence as a captured HIP graph "
+                         "(default: on for the uneven-batch workload)")
+    ap.add_argument("--legs", default=None,
+                    help="comma list of extra legs: c2 (the 10,000-ligand batch), c5 (large "
+                         "ligands, plain and learned side by side), align, learned; default: all "
+                         "for the uneven-batch headline, none otherwise")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-proposal legs")
+    ap.add_argument("--align", type=int, default=ALIGN_ROTATIONS,
+                    help="rotations of the rigid-alignment leg (0: skip it)")
+    ap.add_argument("--no-end-to-end", action="store_true",
+                    help="skip the synchronous host-array timing")
+    ap.add_argument("--proposal", default=None, help="directory of trained proposal weights")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run the 1 GiB copy that calibrates the HBM byte counters")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(a batch would shard by ligand, with no exchange between GPUs)", file=sys.stderr)
+        sys.exit(2)
+
+    if args.copy_calibration:
+        copy_calibration()
+        return
+
+    import torch
+    torch.cuda.set_device(0)
+    cfg = args.config
+    legs = (args.legs.split(",") if args.legs is not None else
+            (["c2", "c5", "align", "learned"] if cfg == 3 else []))
+    legs = [x for x in legs if x]
+    if args.no_learned:
+        legs = [x for x in legs if x != "learned"]
+    if args.align <= 0:
+        legs = [x for x in legs if x != "align"]
+    autotune = args.autotune if args.autotune is not None else (2000 if cfg == 3 else 0)
+    graph = args.graph if args.graph is not None else cfg == 3
+    head, ctx = plain_leg(cfg, args.steps, args.warmup, args.bump, args.waves, args.claim, autotune,
+                          graph, args.ligands, end_to_end=not args.no_end_to_end)
+    line = {
+        "metric": METRIC, "value": head["value"], "unit": "ligands/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic", "mode": "plain", "bump": args.bump, "launch": head["launch"],
+        "config": head["config"], "roofline": head["roofline"],
+    }
+    if "end_to_end" in head:
+        line["end_to_end"] = head["end_to_end"]
     line["paper_context"] = {
         "note": "the paper (arXiv 1901.06229) prints no throughput for this path and no workload "
                 "sizes (1500 unpublished ligands); its figures are context, not comparable",
@@ -561,25 +668,38 @@ def main():
         "alignment_gpu_speedup": "16x, same hardware (§4.1)",
         "hybrid_node": "5.8 ligands/s, 16 OpenMP threads + 2 GK210 GPUs, whole docking incl. alignment (§5.2)",
     }
-    if args.align > 0:
-        log(f"rigid alignment: {args.align} rotations per restart before the sweep")
-        line["align"] = align_leg(cfg, h, ligs, d, orient_d, S, out, stream, args.steps, args.warmup,
-                                  max_atoms, args.align)
-    if not args.no_learned:
+    if not args.no_cpu_baseline:
+        log("timing the FP64 reference on samples of the headline workload")
+        line["cpu_baseline"] = cpu_baseline(ctx)
+    net = None
+    if "learned" in legs:
         log("learned proposal: training on the GPU and comparing with the plain sweep")
         line["learned"], net = learned_comparison(proposal=args.proposal)
-        if cfg == 5:
+    extra = {}
+    for name, c in (("c2", 2), ("c5", 5)):
+        if name not in legs or c == cfg:
+            continue
+        res, lctx = plain_leg(c, args.steps, args.warmup, args.bump, end_to_end=not args.no_end_to_end)
+        gpu_best = {"plain": lctx["best"]}
+        if c == 2 and "align" in legs:
+            log(f"rigid alignment: {args.align} rotations per restart before the sweep")
+            res["align"] = align_leg(c, lctx["h"], lctx["ligs"], lctx["d"], lctx["orient_d"], lctx["S"],
+                                     lctx["out"], lctx["stream"], args.steps, args.warmup,
+                                     lctx["max_atoms"], args.align)
+        if c == 5 and net is not None:
             log("large-ligand workload: plain and learned sweep side by side")
-            line["learned"]["side_by_side"], gpu_best["learned"] = learned_side_by_side(
-                h, ligs, orient, d, orient_d, S, out, stream, args.steps, args.warmup, max_atoms, net,
-                gpu_best["plain"], elapsed / args.steps)
-            line["learned"]["side_by_side"]["workload"] = WORKLOADS[cfg]
-    if not args.no_cpu_baseline:
-        log("timing the FP64 reference on a sample")
-        line["cpu_baseline"] = cpu_baseline(pocket, ligs, orient, S,
-                                            gpu_best=gpu_best if cfg == 5 else None)
+            res["learned_side_by_side"], gpu_best["learned"] = learned_side_by_side(
+                lctx["h"], lctx["ligs"], lctx["orient"], lctx["d"], lctx["orient_d"], lctx["S"],
+                lctx["out"], lctx["stream"], args.steps, args.warmup, lctx["max_atoms"], net,
+                lctx["best"], lctx["step_s"])
+        if c == 5 and not args.no_cpu_baseline:
+            log("large-ligand workload: per-ligand error against the FP64 reference")
+            res["vs_oracle"] = oracle_check(lctx, gpu_best)
+        lctx["h"].close()
+        extra[name] = res
+    line.update(extra)
     print(json.dumps(line), flush=True)
-    h.close()
+    ctx["h"].close()
 
 
 if __name__ == "__main__":

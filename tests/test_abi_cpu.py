@@ -68,9 +68,10 @@ def test_bench_traffic_is_reported_only_for_the_measured_kernel(tmp_path, monkey
     good.write_text(f"# x\n\ntraffic_bytes_per_launch: 1234\nsources_sha256: {digest}\n")
     stale = tmp_path / "stale.md"
     stale.write_text("traffic_bytes_per_launch: 1234\nsources_sha256: " + "0" * 64 + "\n")
-    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(good))
-    assert bench.measured_traffic() == 1234.0
-    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(stale))
-    assert bench.measured_traffic() is None
-    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(tmp_path / "missing.md"))
-    assert bench.measured_traffic() is None
+    monkeypatch.setattr(bench, "TRAFFIC_FILES", {3: str(good)})
+    assert bench.measured_traffic(3) == 1234.0
+    assert bench.measured_traffic(2) is None
+    monkeypatch.setattr(bench, "TRAFFIC_FILES", {3: str(stale)})
+    assert bench.measured_traffic(3) is None
+    monkeypatch.setattr(bench, "TRAFFIC_FILES", {3: str(tmp_path / "missing.md")})
+    assert bench.measured_traffic(3) is None
