@@ -532,7 +532,8 @@ def plain_leg(cfg, steps, warmup, bump="pruned", waves=0, claim=16, autotune=0, 
             "ligands_per_s": round(L / med, 2)}
         log(f"config {cfg}: end to end {1e3 * med:.2f} ms ({L / med:,.0f} ligands/s)")
     ctx = dict(h=h, pocket=pocket, ligs=ligs, orient=orient, d=d, orient_d=orient_d, out=out,
-               stream=stream, S=S, O=O, max_atoms=max_atoms, best=best, step_s=elapsed / steps)
+               stream=stream, S=S, O=O, max_atoms=max_atoms, best=best, step_s=elapsed / steps,
+               workload=res["config"]["workload"])
     return res, ctx
 
 
@@ -594,6 +595,59 @@ def cpu_baseline(ctx, budget_s=16.0, single_s=6.0):
             "host": info}
 
 
+def hybrid_leg(ctx, runs=3):
+    """Node throughput with host threads beside the GPU (paper §4.2 and §5.1:
+    CPU processes add to the GPU process): the same host-array batch docked
+    by the GPU alone (pipelined chunks, no host threads) and by the GPU with
+    host threads from the same dispenser; then the host threads alone on a
+    bounded sample.  Median of `runs` after one warm-up each."""
+    from paper_1901_06229_amd import dock, synth
+    h, ligs, orient, S = ctx["h"], ctx["ligs"], ctx["orient"], ctx["S"]
+    L = ligs.n_ligands
+    threads = max(0, min(16, cpu_info()["allowed"] or 1) - 1)
+
+    def timed(**kw):
+        times, res = [], None
+        for rep in range(runs + 1):
+            t0 = time.perf_counter()
+            res = dock.dock_batch_hybrid(h, ligs, orient, S, r_bump=synth.R_BUMP, **kw)
+            if rep:
+                times.append(time.perf_counter() - t0)
+        return float(np.median(times)), res
+
+    t_gpu, r_gpu = timed(cpu_threads=0)
+    assert np.array_equal(r_gpu["best_score"], ctx["best"]), "hybrid GPU-only run disagrees"
+    t_hyb, r_hyb = timed(cpu_threads=threads)
+    gpu_l = r_hyb["done_by"] == 0
+    assert np.array_equal(r_hyb["best_score"][gpu_l], ctx["best"][gpu_l])
+    log(f"hybrid: GPU only {L / t_gpu:,.0f} ligands/s, GPU + {threads} host threads "
+        f"{L / t_hyb:,.0f} ligands/s ({r_hyb['stats']['cpu_ligands']} ligands on the host)")
+    # host threads alone on the first ligands (about 3 s)
+    n = 64
+    while True:
+        sub = ligs.subset(range(n))
+        t0 = time.perf_counter()
+        dock.dock_batch_hybrid(h, sub, orient, S, r_bump=synth.R_BUMP, cpu_threads=threads, use_gpu=False)
+        t_host = time.perf_counter() - t0
+        if t_host >= 1.5 or 2 * n > L:
+            break
+        n *= 2
+    return {
+        "workload": ctx["workload"] + ", host arrays in and out",
+        "gpu_only_ligands_per_s": round(L / t_gpu, 1),
+        "hybrid_ligands_per_s": round(L / t_hyb, 1),
+        "gain": round(t_gpu / t_hyb, 4),
+        "host_threads": threads,
+        "host_ligands": int(r_hyb["stats"]["cpu_ligands"]),
+        "gpu_chunks": int(r_hyb["stats"]["gpu_chunks"]),
+        "ms": {"gpu_only": round(1e3 * t_gpu, 2), "hybrid": round(1e3 * t_hyb, 2)},
+        "host_only": {"ligands_per_s": round(n / t_host, 1), "threads": threads,
+                      "sample": f"first {n} ligands, FP32 host sweep (AVX2), {t_host:.2f} s"},
+        "note": "gpu_only is the same call with no host threads (GPU chunks pipelined with their "
+                "copies); host-only rate of the product FP32 CPU sweep, not the FP64 reference",
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -617,7 +671,8 @@ def main():
                     help="replay the batch's launch sequence as a captured HIP graph "
                          "(default: on for the uneven-batch workload)")
     ap.add_argument("--legs", default=None,
-                    help="comma list of extra legs: c2 (the 10,000-ligand batch), c5 (large "
+                    help="comma list of extra legs: hybrid (GPU and host threads on the headline "
+                         "batch), c2 (the 10,000-ligand batch), c5 (large "
                          "ligands, plain and learned side by side), align, learned; default: all "
                          "for the uneven-batch headline, none otherwise")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-proposal legs")
@@ -642,7 +697,7 @@ def main():
     torch.cuda.set_device(0)
     cfg = args.config
     legs = (args.legs.split(",") if args.legs is not None else
-            (["c2", "c5", "align", "learned"] if cfg == 3 else []))
+            (["hybrid", "c2", "c5", "align", "learned"] if cfg == 3 else []))
     legs = [x for x in legs if x]
     if args.no_learned:
         legs = [x for x in legs if x != "learned"]
@@ -668,6 +723,9 @@ def main():
         "alignment_gpu_speedup": "16x, same hardware (§4.1)",
         "hybrid_node": "5.8 ligands/s, 16 OpenMP threads + 2 GK210 GPUs, whole docking incl. alignment (§5.2)",
     }
+    if "hybrid" in legs:
+        log("hybrid: GPU and host threads from one dispenser")
+        line["hybrid"] = hybrid_leg(ctx)
     if not args.no_cpu_baseline:
         log("timing the FP64 reference on samples of the headline workload")
         line["cpu_baseline"] = cpu_baseline(ctx)

@@ -222,6 +222,52 @@ int dock_batch_async_static(dock_pocket *p, const dock_ligands *ligs,
 size_t dock_workspace_size(int32_t n_ligands, int64_t total_rot, int n_orient,
                            int angle_steps, int passes, int n_align);
 
+/* ------------------------------------------------------------------------
+ * Hybrid host + GPU docking (paper §4.2: host threads and accelerators
+ * share one ligand queue; §5.1: CPU processes beside the GPU process raise
+ * the node's throughput).  One dispenser hands the GPU large contiguous
+ * ranges of the batch from the front (two in flight on two streams: pack,
+ * copy in, sweep, copy out) and host threads a few ligands at a time from
+ * the back, until the ends meet.  Host
+ * threads run an FP32 CPU form of the same greedy sweep (AVX2 + FMA,
+ * vectorised over angles), so each ligand's result is the GPU's or the
+ * host's, equal up to FP32 rounding.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+  int32_t cpu_threads; /* host docking threads: 0 none (GPU only), -1 one per
+                          hardware thread minus one (the GPU feeder's)      */
+  int32_t use_gpu;     /* 1: the GPU takes chunks; 0: host threads only      */
+  int32_t gpu_chunk;   /* most ligands per GPU claim (0: n_ligands/4, at
+                          least 256); a claim takes a quarter of what is
+                          left, at least a quarter of this cap            */
+  int32_t cpu_chunk;   /* ligands per host claim (0: 1)                       */
+} dock_hybrid_opts;
+
+typedef struct {
+  int64_t gpu_ligands, cpu_ligands; /* ligands docked by each side          */
+  int32_t gpu_chunks, cpu_threads;  /* GPU chunks run, host threads used     */
+  double wall_ms;                   /* the whole call                        */
+  double gpu_busy_ms;               /* chunk times summed (copy in, sweep,
+                                       copy out; the two streams overlap)    */
+  double cpu_busy_ms;               /* host threads' working time, summed   */
+  double feed_ms;                   /* GPU feeder packing and scattering     */
+  double wait_ms;                   /* GPU feeder waiting for chunks         */
+  int8_t *done_by;                  /* optional [n_ligands] (caller-owned,
+                                       host): 0 GPU, 1 host thread           */
+} dock_hybrid_stats;
+
+/* Synchronous hybrid batch: host arrays in and out as in dock_batch, the
+ * same validation and outputs (all_scores and all_angle_idx together or
+ * neither; n_fallback, align_idx and all_align_idx are not written).  Plain
+ * mode only, no alignment set (DOCK_E_INVAL otherwise).  stats may be NULL.
+ * Errors: as dock_batch; DOCK_E_INVAL with use_gpu = 0 and no host
+ * threads; DOCK_E_STATE when host threads are asked for on a CPU without
+ * AVX2 and FMA; DOCK_E_LIMIT above 1024 threads. */
+int dock_batch_hybrid(dock_pocket *p, const dock_ligands *ligs, const float *orient,
+                      int n_orient, int angle_steps, const dock_params *prm,
+                      dock_results *out, const dock_hybrid_opts *opt,
+                      dock_hybrid_stats *stats);
+
 /* Duration in ms of the sweep kernel of the last call on this handle that
  * set DOCK_FLAG_TIME_SWEEP (waits for that kernel to finish).  A call
  * replayed as a HIP graph (DOCK_FLAG_GRAPH) is timed around the whole graph

@@ -19,6 +19,7 @@
 #include "dock.h"
 #include <utility>
 
+#include "abi_internal.h"
 #include "dock_internal.h"
 #include "learned_internal.h"
 #include "mlp_internal.h"
@@ -61,6 +62,8 @@ struct dock_pocket {
   unsigned long long *h_work = nullptr;  // pinned copy of the sweep's two work counters
   LaunchPlan plan{0, 0, 16};
   void *scratch = nullptr;    // this device's copy of the static workspace
+  std::vector<float> host_grid;  // host copy of the grid, made on first use (hybrid calls)
+  HybridCache hybrid;            // the hybrid entry point's streams and buffers
   // last captured launch sequence of dock_batch_async (DOCK_FLAG_GRAPH)
   std::vector<unsigned char> graph_key;
   hipGraph_t graph = nullptr;
@@ -496,6 +499,59 @@ int enqueue_batch(dock_pocket *p, const dock_ligands *ligs, const float *orient,
 
 }  // namespace
 
+namespace dock {
+
+int abi_check_sync(const dock_ligands *ligs, const float *orient, int n_orient, int angle_steps,
+                   const dock_params *prm, int *max_n, int *max_r) {
+  int rc = check_params(prm, n_orient, angle_steps);
+  if (rc) return rc;
+  rc = check_ligands_host(ligs, max_n, max_r);
+  if (rc) return rc;
+  for (int a = 0; a < n_orient * 12; ++a)
+    if (!std::isfinite(orient[a])) return fail(DOCK_E_INVAL, "orientation table is not finite");
+  if (prm->n_align > 0 && (rc = check_rotations_host(prm->align_rot, prm->n_align)) != DOCK_OK)
+    return rc;
+  for (int64_t a = 0; a < ligs->total_atoms * 3; ++a)
+    if (!std::isfinite(ligs->xyz[a])) return fail(DOCK_E_INVAL, "coordinates are not finite");
+  return DOCK_OK;
+}
+
+int abi_enqueue_plain(dock_pocket *p, const dock_ligands *ligs, const float *orient, int n_orient,
+                      int angle_steps, const dock_params *prm, const dock_results *out, void *ws,
+                      size_t ws_bytes, hipStream_t st) {
+  if (prm->mode != DOCK_MODE_PLAIN) return fail(DOCK_E_INVAL, "plain mode expected");
+  return enqueue_batch(p, ligs, orient, n_orient, angle_steps, prm, out, ws, ws_bytes, st,
+                       DOCK_MAX_ROT);
+}
+
+int abi_device(const dock_pocket *p) { return p->device; }
+
+int abi_host_grid(dock_pocket *p, HostGrid *g) {
+  const size_t nvox = (size_t)p->view.nx * p->view.ny * p->view.nz;
+  if (p->host_grid.size() != nvox) {
+    try {
+      p->host_grid.resize(nvox);
+    } catch (const std::bad_alloc &) {
+      return fail(DOCK_E_NOMEM, "host copy of the grid");
+    }
+    hipError_t e = hipMemcpy(p->host_grid.data(), p->d_grid, sizeof(float) * nvox, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) {
+      p->host_grid.clear();
+      return hip_fail(e, "grid download");
+    }
+  }
+  *g = HostGrid{p->host_grid.data(), p->view.nx, p->view.ny, p->view.nz, p->view.ox, p->view.oy,
+                p->view.oz, p->view.inv_h};
+  return DOCK_OK;
+}
+
+HybridCache *abi_hybrid_cache(dock_pocket *p) { return &p->hybrid; }
+
+void abi_lock(dock_pocket *p) { p->mu.lock(); }
+void abi_unlock(dock_pocket *p) { p->mu.unlock(); }
+
+}  // namespace dock
+
 extern "C" {
 
 const char *dock_strerror(int code) {
@@ -769,6 +825,7 @@ void dock_free_pocket(dock_pocket *p) {
     if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
     if (p->graph) (void)hipGraphDestroy(p->graph);
     free_learned(p);
+    if (p->hybrid.state && p->hybrid.release) p->hybrid.release(p->hybrid.state);
     if (p->lw_fallback) (void)hipFree(p->lw_fallback);
     if (p->prop_wb) (void)hipFree(p->prop_wb);
     if (p->prop_w) (void)hipFree(p->prop_w);

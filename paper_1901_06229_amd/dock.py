@@ -51,6 +51,19 @@ class dock_tune_entry(ctypes.Structure):
                 ("items_per_claim", ctypes.c_int32), ("sweep_ms", ctypes.c_float)]
 
 
+class dock_hybrid_opts(ctypes.Structure):
+    _fields_ = [("cpu_threads", ctypes.c_int32), ("use_gpu", ctypes.c_int32),
+                ("gpu_chunk", ctypes.c_int32), ("cpu_chunk", ctypes.c_int32)]
+
+
+class dock_hybrid_stats(ctypes.Structure):
+    _fields_ = [("gpu_ligands", ctypes.c_int64), ("cpu_ligands", ctypes.c_int64),
+                ("gpu_chunks", ctypes.c_int32), ("cpu_threads", ctypes.c_int32),
+                ("wall_ms", ctypes.c_double), ("gpu_busy_ms", ctypes.c_double),
+                ("cpu_busy_ms", ctypes.c_double), ("feed_ms", ctypes.c_double),
+                ("wait_ms", ctypes.c_double), ("done_by", ctypes.c_void_p)]
+
+
 class DockError(RuntimeError):
     def __init__(self, code: int, where: str, detail: str):
         super().__init__(f"{where}: {detail or 'error'} (code {code})")
@@ -103,6 +116,10 @@ def load_library(path: str = None):
     lib.dock_batch_async_static.argtypes = [_P, c.POINTER(dock_ligands), _P, c.c_int, c.c_int,
                                             c.POINTER(dock_params), c.POINTER(dock_results), _P]
     lib.dock_batch_async_static.restype = c.c_int
+    lib.dock_batch_hybrid.argtypes = [_P, c.POINTER(dock_ligands), _P, c.c_int, c.c_int,
+                                      c.POINTER(dock_params), c.POINTER(dock_results),
+                                      c.POINTER(dock_hybrid_opts), c.POINTER(dock_hybrid_stats)]
+    lib.dock_batch_hybrid.restype = c.c_int
     lib.dock_workspace_size.argtypes = [c.c_int32, c.c_int64, c.c_int, c.c_int, c.c_int, c.c_int]
     lib.dock_workspace_size.restype = c.c_size_t
     lib.dock_last_sweep_ms.argtypes = [_P, c.POINTER(c.c_float)]
@@ -220,15 +237,9 @@ def make_params(r_bump=2.0, passes=1, mode=DOCK_MODE_PLAIN, top_k=16, margin=0.0
                        int(flags), int(max_atoms), int(max_rot), n_align, _any_ptr(align))
 
 
-def dock_batch(pocket: Pocket, ligs, orient, angle_steps: int, r_bump: float = 2.0,
-               passes: int = 1, mode: int = DOCK_MODE_PLAIN, top_k: int = 16,
-               margin: float = 0.0, flags: int = 0, want_all: bool = False, align=None) -> dict:
-    """Synchronous batch on host arrays (``ligs``: any object with the CSR fields).
-
-    align: optional [A, 3, 3] rotation set; every restart is first aligned
-    rigidly to its best rotation (``align_idx`` per ligand, ``all_align_idx``
-    per item with want_all)."""
-    lib = load_library()
+def _sync_call(ligs, orient, passes, mode, want_all, align, hybrid=False):
+    """Host arrays of a synchronous call: (dock_ligands, dock_results, outputs,
+    orientation table, arrays to keep alive)."""
     ao = _c(ligs.atom_offset, np.int32)
     xyz = _c(ligs.xyz, np.float32)
     ro = _c(ligs.rot_offset, np.int32)
@@ -247,7 +258,7 @@ def dock_batch(pocket: Pocket, ligs, orient, angle_steps: int, r_bump: float = 2
     if want_all:
         out["all_scores"] = np.empty((L, O), np.float32)
         out["all_angle_idx"] = np.empty(max(NR * passes * O, 1), np.int16)
-    if mode == DOCK_MODE_LEARNED:
+    if mode == DOCK_MODE_LEARNED and not hybrid:
         out["n_fallback"] = np.empty(max(L, 1), np.int32)
     if align is not None:
         align = _c(align, np.float32).reshape(-1, 3, 3)
@@ -259,9 +270,11 @@ def dock_batch(pocket: Pocket, ligs, orient, angle_steps: int, r_bump: float = 2
                       _np_ptr(out.get("all_scores")), _np_ptr(out.get("all_angle_idx")),
                       _np_ptr(out["status"]), _np_ptr(out.get("n_fallback")),
                       _np_ptr(out.get("align_idx")), _np_ptr(out.get("all_align_idx")))
-    prm = make_params(r_bump, passes, mode, top_k, margin, flags, align=align)
-    _check(lib.dock_batch(pocket.handle, ctypes.byref(dl), _np_ptr(orient), O, int(angle_steps),
-                          ctypes.byref(prm), ctypes.byref(dr)), "dock_batch")
+    return dl, dr, out, orient, align, (ao, xyz, ro, ax, mo, mv), (L, O, NA, NR)
+
+
+def _trim(out, sizes, passes, want_all, align):
+    L, O, NA, NR = sizes
     out["angle_idx"] = out["angle_idx"][:NR * passes]
     out["xyz"] = out["xyz"][:NA]
     out["status"] = out["status"][:L]
@@ -271,6 +284,46 @@ def dock_batch(pocket: Pocket, ligs, orient, angle_steps: int, r_bump: float = 2
         out["align_idx"] = out["align_idx"][:L]
         if want_all:
             out["all_align_idx"] = out["all_align_idx"][:L]
+    return out
+
+
+def dock_batch(pocket: Pocket, ligs, orient, angle_steps: int, r_bump: float = 2.0,
+               passes: int = 1, mode: int = DOCK_MODE_PLAIN, top_k: int = 16,
+               margin: float = 0.0, flags: int = 0, want_all: bool = False, align=None) -> dict:
+    """Synchronous batch on host arrays (``ligs``: any object with the CSR fields).
+
+    align: optional [A, 3, 3] rotation set; every restart is first aligned
+    rigidly to its best rotation (``align_idx`` per ligand, ``all_align_idx``
+    per item with want_all)."""
+    lib = load_library()
+    dl, dr, out, orient, align, _keep, sizes = _sync_call(ligs, orient, passes, mode, want_all, align)
+    prm = make_params(r_bump, passes, mode, top_k, margin, flags, align=align)
+    _check(lib.dock_batch(pocket.handle, ctypes.byref(dl), _np_ptr(orient), sizes[1],
+                          int(angle_steps), ctypes.byref(prm), ctypes.byref(dr)), "dock_batch")
+    return _trim(out, sizes, passes, want_all, align)
+
+
+def dock_batch_hybrid(pocket: Pocket, ligs, orient, angle_steps: int, r_bump: float = 2.0,
+                      passes: int = 1, cpu_threads: int = -1, use_gpu: bool = True,
+                      gpu_chunk: int = 0, cpu_chunk: int = 0, want_all: bool = False,
+                      mode: int = DOCK_MODE_PLAIN, align=None) -> dict:
+    """Synchronous batch docked by the GPU and host threads from one dispenser.
+    Returns the dock_batch outputs plus ``stats`` (a dict) and ``done_by``
+    (per ligand: 0 GPU, 1 host thread)."""
+    lib = load_library()
+    dl, dr, out, orient, align, _keep, sizes = _sync_call(ligs, orient, passes, mode, want_all, align,
+                                                          hybrid=True)
+    prm = make_params(r_bump, passes, mode, align=align)
+    done_by = np.full(max(sizes[0], 1), -1, np.int8)
+    opts = dock_hybrid_opts(int(cpu_threads), int(bool(use_gpu)), int(gpu_chunk), int(cpu_chunk))
+    st = dock_hybrid_stats()
+    st.done_by = done_by.ctypes.data
+    _check(lib.dock_batch_hybrid(pocket.handle, ctypes.byref(dl), _np_ptr(orient), sizes[1],
+                                 int(angle_steps), ctypes.byref(prm), ctypes.byref(dr),
+                                 ctypes.byref(opts), ctypes.byref(st)), "dock_batch_hybrid")
+    out = _trim(out, sizes, passes, want_all, align)
+    out["done_by"] = done_by[:sizes[0]]
+    out["stats"] = {k: getattr(st, k) for k, _ in dock_hybrid_stats._fields_ if k != "done_by"}
     return out
 
 
