@@ -7,7 +7,7 @@ import pytest
 
 import oracle
 import oracle.mlp as om
-from oracle.features import features as ref_features, landscape as ref_landscape
+from oracle.features import features as ref_features, landscape as ref_landscape, lattice_points
 from paper_1901_06229_amd import dock, learned, synth
 from tests.checker import check_item, item_steps, tol_of
 
@@ -33,6 +33,12 @@ def _rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30))
 
 
+# Per-tensor gradient bar: relative Frobenius error 1e-3 for every weight
+# and bias tensor (measured on gfx950: at most 1e-4, in W1, where the BF16
+# rounding flips of the pre-activation gradients accumulate most).
+GRAD_TOL = {}
+
+
 def test_mlp_forward_and_gradient_match_reference():
     torch = _torch()
     rng = np.random.default_rng(0)
@@ -47,8 +53,12 @@ def test_mlp_forward_and_gradient_match_reference():
     net.forward(xb, y)
     torch.cuda.synchronize()
     y_ref, _ = om.forward(theta32.astype(np.float64), _bits_to_f64(torch, xb), bf16=True)
-    print("forward rel err", _rel(y.cpu().numpy(), y_ref))
-    assert _rel(y.cpu().numpy().astype(np.float64), y_ref) < 1e-2
+    # element by element, one BF16 step at the output's scale (the bar an
+    # independent FP32 evaluation meets in tests/test_mlp_oracle.py)
+    err = np.abs(y.cpu().numpy().astype(np.float64) - y_ref)
+    tol = 2.0 ** -7 * float(np.sqrt(np.mean(y_ref * y_ref)))
+    print("forward: max element error / bar", float(err.max() / tol), "rel Frobenius", _rel(y.cpu().numpy(), y_ref))
+    assert (err <= tol).all(), float(err.max() / tol)
     g = torch.empty(om.N_PARAMS, device="cuda")
     loss = net.loss_grad(xb, tb, grad_out=g)
     l_ref, g_ref = om.loss_and_grad(theta32.astype(np.float64), _bits_to_f64(torch, xb),
@@ -56,12 +66,15 @@ def test_mlp_forward_and_gradient_match_reference():
     assert abs(loss - l_ref) / l_ref < 1e-3
     gg = g.cpu().numpy().astype(np.float64)
     at = 0
-    for (o, i) in om.SIZES:
-        for size in (o * i, o):
+    errs = []
+    for li, (o, i) in enumerate(om.SIZES):
+        for name, size in (("W", o * i), ("b", o)):
             e = _rel(gg[at:at + size], g_ref[at:at + size])
-            print("grad block", at, size, e)
-            assert e < 1e-2
+            errs.append((f"{name}{li + 1}", e))
             at += size
+    print("gradient relative errors per tensor", errs)
+    for name, e in errs:
+        assert e < GRAD_TOL.get(name, 1e-3), (name, e)
 
 
 def test_mlp_adam_step_matches_reference():
@@ -99,7 +112,8 @@ def test_emitted_profiles_match_reference():
     res = dock.dock_batch(h, ligs, orient, 256, want_all=True)
     xs, ts = _bits_to_f64(torch, x), _bits_to_f64(torch, t)
     mask = mk.cpu().numpy().view(np.uint32)
-    n_feat = n_feat_ok = n_t = n_t_ok = n_v = n_v_ok = 0
+    bad_feat, bad_t = [], []
+    n_feat = n_feat_ok = n_feat_band = n_t = n_t_ok = n_t_band = n_v = n_v_ok = 0
     for l in range(ligs.n_ligands):
         lig = ligs.ligand(l)
         R = len(lig["rot_axis"])
@@ -110,12 +124,35 @@ def test_emitted_profiles_match_reference():
             X = lig["xyz"].astype(np.float64) @ orient[o][:9].reshape(3, 3).astype(np.float64).T
             for r in range(R):
                 row = (int(ligs.rot_offset[l]) * 8 + o * R) + r
+                # features: the lattice point's voxel value, clamped at -1, as
+                # BF16; a point within 1e-4 A of a voxel face may take any
+                # value of its alternative voxels
                 f_ref = ref_features(pocket, X, lig, r)
-                n_feat += 64
-                n_feat_ok += int(np.sum(np.abs(xs[row] - f_ref) <= 2 ** -7 * np.maximum(np.abs(f_ref), 1e-3) + 1e-6))
+                pts = lattice_points(X, lig, r)
+                for f in range(64):
+                    n_feat += 1
+                    if _bf16_close(xs[row, f], f_ref[f]):
+                        n_feat_ok += 1
+                        continue
+                    lo, hi, amb = oracle.voxel_interval(pocket, pts[f])
+                    if amb and max(lo, -1.0) - _ulp(lo) <= xs[row, f] <= max(hi, -1.0) + _ulp(hi):
+                        n_feat_band += 1
+                    else:
+                        bad_feat.append((l, o, r, f, float(xs[row, f]), float(f_ref[f]), lo, hi))
+                # targets: max(s_k - max s, -4) as BF16 over all 256 steps,
+                # each score within its own ambiguity interval
                 t_ref = ref_landscape(tr.prof_s[r])
-                n_t += 256
-                n_t_ok += int(np.sum(np.abs(ts[row] - t_ref) <= 2 ** -7 * np.abs(t_ref) + 2e-5 * (1 + abs(tr.prof_s[r].max()))))
+                sc_tol = tol_of(float(np.abs(tr.prof_s[r]).max()))
+                t_lo = np.maximum(tr.prof_lo[r] - tr.prof_hi[r].max(), -4.0)
+                t_hi = np.maximum(tr.prof_hi[r] - tr.prof_lo[r].max(), -4.0)
+                for kk in range(256):
+                    n_t += 1
+                    if abs(ts[row, kk] - t_ref[kk]) <= _ulp(t_ref[kk]) + 2 * sc_tol:
+                        n_t_ok += 1
+                    elif t_lo[kk] - _ulp(t_lo[kk]) - 2 * sc_tol <= ts[row, kk] <= t_hi[kk] + _ulp(t_hi[kk]) + 2 * sc_tol:
+                        n_t_band += 1
+                    else:
+                        bad_t.append((l, o, r, kk, float(ts[row, kk]), float(t_ref[kk])))
                 bits = np.array([(mask[row, kk // 32] >> (kk % 32)) & 1 for kk in range(256)], bool)
                 ok_v = (tr.prof_flags[r] & oracle.FLAG_VALID) > 0
                 amb = (tr.prof_flags[r] & oracle.FLAG_VAMB) > 0
@@ -125,11 +162,24 @@ def test_emitted_profiles_match_reference():
                 if kk > 0:
                     from tests.helpers import step_pose
                     X = step_pose(X, lig, r, kk, 256)
-    print("features", n_feat_ok, "/", n_feat, "targets", n_t_ok, "/", n_t, "validity", n_v_ok, "/", n_v)
+    print("features", n_feat_ok, "+", n_feat_band, "in band /", n_feat, "targets", n_t_ok, "+",
+          n_t_band, "in band /", n_t, "validity", n_v_ok, "/", n_v)
     assert n_v_ok == n_v
-    assert n_feat_ok >= 0.995 * n_feat
-    assert n_t_ok >= 0.99 * n_t
+    assert not bad_feat, bad_feat[:10]
+    assert not bad_t, bad_t[:10]
+    # acceptances through the band stay rare
+    assert n_feat_band <= max(4, 0.005 * n_feat) and n_t_band <= max(8, 0.005 * n_t)
     h.close()
+
+
+def _ulp(v):
+    """One BF16 step at |v| (8 significant bits)."""
+    return 2.0 ** (np.floor(np.log2(max(abs(float(v)), 1e-30))) - 7)
+
+
+def _bf16_close(got, ref):
+    """got (a BF16 value) is ref rounded to BF16, give or take one step."""
+    return abs(float(got) - float(ref)) <= _ulp(ref) + 1e-30
 
 
 def _proposal_pocket(seed=5):
@@ -165,7 +215,7 @@ def test_learned_choices_are_valid_and_replayable():
     res = dock.dock_batch(h, ligs, orient, 256, mode=dock.DOCK_MODE_LEARNED, top_k=16,
                           margin=-1.0, want_all=True)
     assert (res["n_fallback"] == 0).all()
-    bad = []
+    bad, band, flagged = [], 0, 0
     for l in range(ligs.n_ligands):
         lig = ligs.ligand(l)
         for o in range(8):
@@ -176,14 +226,29 @@ def test_learned_choices_are_valid_and_replayable():
                 if kk < 0 or not (f & (oracle.FLAG_VALID | oracle.FLAG_VAMB)):
                     bad.append((l, o, s, int(kk)))
             sc = float(res["all_scores"][l, o])
-            assert abs(sc - tr.score) <= tol_of(tr.score) or tr.score_lo - 1e-3 <= sc <= tr.score_hi + 1e-3
+            band += _score_ok(sc, tr, bad, (l, o))
+            flagged += tr.score_lo < tr.score_hi
         ob = int(res["best_orient"][l])
         a0, a1 = ligs.atom_offset[l], ligs.atom_offset[l + 1]
         k = item_steps(ligs, l, ob, 8, 1, res["all_angle_idx"])
         tr = oracle.trace_item(pocket, lig, orient[ob], 256, forced_k=k)
         assert np.abs(res["xyz"][a0:a1] - tr.xyz).max() < 1e-4
     assert not bad, bad[:10]
+    assert band <= max(2, flagged // 2), (band, flagged)
     h.close()
+
+
+def _score_ok(sc, tr, bad, where):
+    """1 if the final score is accepted only through the reference's interval
+    (atoms within 1e-4 A of a voxel face), 0 if within 1e-5 relative; a
+    failure is recorded in bad."""
+    tol = tol_of(tr.score)
+    if abs(sc - tr.score) <= tol:
+        return 0
+    if tr.score_lo - tol <= sc <= tr.score_hi + tol:
+        return 1
+    bad.append(where + ("score", sc, tr.score, tr.score_lo, tr.score_hi))
+    return 0
 
 
 def test_training_reduces_loss():
@@ -213,7 +278,7 @@ def test_learned_mode_at_other_step_counts(S):
     res = dock.dock_batch(h, ligs, orient, S, mode=dock.DOCK_MODE_LEARNED, top_k=8,
                           margin=-1.0, want_all=True)
     assert (res["n_fallback"] == 0).all()
-    bad = []
+    bad, band, flagged = [], 0, 0
     for l in range(ligs.n_ligands):
         lig = ligs.ligand(l)
         for o in (0, 5):
@@ -224,8 +289,10 @@ def test_learned_mode_at_other_step_counts(S):
                 if kk < 0 or not (f & (oracle.FLAG_VALID | oracle.FLAG_VAMB)):
                     bad.append((l, o, s, int(kk)))
             sc = float(res["all_scores"][l, o])
-            assert abs(sc - tr.score) <= tol_of(tr.score) or tr.score_lo - 1e-3 <= sc <= tr.score_hi + 1e-3
+            band += _score_ok(sc, tr, bad, (l, o))
+            flagged += tr.score_lo < tr.score_hi
     assert not bad, bad[:10]
+    assert band <= max(2, flagged // 2), (band, flagged)
     for S_bad, top_k in ((4096, 32), (4096, 63), (1000, 128)):
         with pytest.raises(dock.DockError) as e:
             dock.dock_batch(h, ligs, orient, S_bad, mode=dock.DOCK_MODE_LEARNED, top_k=top_k)
@@ -290,4 +357,80 @@ def test_async_learned_rejects_ligands_above_max_rot():
                               dock.make_params(mode=dock.DOCK_MODE_LEARNED, flags=dock.DOCK_FLAG_GRAPH),
                               stream=st)
     assert e.value.code == dock.DOCK_E_INVAL
+    h.close()
+
+
+def _replay_learned(pocket, ligs, orient, S, res, passes=1, orients=None):
+    """Learned-mode results replayed by the reference along the GPU's own
+    choices: every chosen angle valid (or within the bump radius's band),
+    final scores within 1e-5 relative or the reference's interval (counted),
+    the winners' coordinates within 1e-4 A.  Returns (bad, band, flagged)."""
+    O = orient.shape[0]
+    bad, band, flagged = [], 0, 0
+    for l in range(ligs.n_ligands):
+        lig = ligs.ligand(l)
+        ob = int(res["best_orient"][l])
+        for o in sorted(set(range(O) if orients is None else orients) | {ob}):
+            k = item_steps(ligs, l, o, O, passes, res["all_angle_idx"])
+            tr = oracle.trace_item(pocket, lig, orient[o], S, passes=passes, forced_k=k)
+            for s, kk in enumerate(k):
+                f = tr.prof_flags[s][int(kk)] if kk >= 0 else 0
+                if kk < 0 or not (f & (oracle.FLAG_VALID | oracle.FLAG_VAMB)):
+                    bad.append((l, o, s, int(kk)))
+            band += _score_ok(float(res["all_scores"][l, o]), tr, bad, (l, o))
+            flagged += tr.score_lo < tr.score_hi
+            if o == ob:
+                a0, a1 = ligs.atom_offset[l], ligs.atom_offset[l + 1]
+                dx = float(np.abs(res["xyz"][a0:a1] - tr.xyz).max())
+                if dx > 1e-4:
+                    bad.append((l, o, "coords", dx))
+    return bad, band, flagged
+
+
+def test_learned_mode_on_large_ligands():
+    """The learned sweep on the large-ligand workload's sizes (100-250 atoms,
+    60-120 rotamers, 256^3 pocket, 360 steps): fallback everywhere is the
+    plain sweep bit for bit; without fallback every choice replays."""
+    _torch()
+    pocket = synth.pocket(5)
+    h = dock.dock_init_pocket(pocket.grid, pocket.origin, pocket.spacing)
+    net = dock.Mlp(learned.init_params(5))
+    dock.dock_load_proposal(h, net)
+    ligs = synth.ligands(5, count=3, first=11)
+    orient = synth.orientations(5, 4)
+    print(f"[gpu] learned, large ligands: {ligs.n_ligands} x 4 orientations, S=360, "
+          f"atoms {np.diff(ligs.atom_offset).tolist()}, rotamers {np.diff(ligs.rot_offset).tolist()}", flush=True)
+    plain = dock.dock_batch(h, ligs, orient, 360, want_all=True)
+    lrn = dock.dock_batch(h, ligs, orient, 360, mode=dock.DOCK_MODE_LEARNED, top_k=16,
+                          margin=3.0e38, want_all=True)
+    for k in ("best_score", "best_orient", "angle_idx", "xyz", "all_scores", "all_angle_idx"):
+        assert np.array_equal(plain[k], lrn[k]), k
+    res = dock.dock_batch(h, ligs, orient, 360, mode=dock.DOCK_MODE_LEARNED, top_k=16,
+                          margin=-1.0, want_all=True)
+    assert (res["n_fallback"] == 0).all()
+    bad, band, flagged = _replay_learned(pocket, ligs, orient, 360, res)
+    print("band", band, "of", flagged, "flagged")
+    assert not bad, bad[:10]
+    assert band <= max(2, flagged // 2), (band, flagged)
+    h.close()
+
+
+def test_learned_mode_with_two_passes():
+    """passes = 2 in learned mode: fallback everywhere equals the plain
+    two-pass sweep; without fallback both passes' choices replay."""
+    _torch()
+    pocket, h, net = _proposal_pocket()
+    ligs = synth.ligands(learned.LIGAND_RECIPE, count=10, seed=4, stream=synth.STREAM_EVAL)
+    orient = synth.orientations(learned.LEARN_CONFIG)
+    plain = dock.dock_batch(h, ligs, orient, 256, passes=2, want_all=True)
+    lrn = dock.dock_batch(h, ligs, orient, 256, passes=2, mode=dock.DOCK_MODE_LEARNED, top_k=16,
+                          margin=3.0e38, want_all=True)
+    for k in ("best_score", "best_orient", "angle_idx", "xyz", "all_scores", "all_angle_idx"):
+        assert np.array_equal(plain[k], lrn[k]), k
+    res = dock.dock_batch(h, ligs, orient, 256, passes=2, mode=dock.DOCK_MODE_LEARNED, top_k=16,
+                          margin=-1.0, want_all=True)
+    assert (res["n_fallback"] == 0).all()
+    bad, band, flagged = _replay_learned(pocket, ligs, orient, 256, res, passes=2)
+    assert not bad, bad[:10]
+    assert band <= max(2, flagged // 2), (band, flagged)
     h.close()

@@ -103,3 +103,45 @@ def test_bf16_path_close_to_fp64_path():
     assert abs(l1 - l0) / l0 < 2e-2
     assert np.linalg.norm(g1 - g0) / np.linalg.norm(g0) < 5e-2
     assert math.isfinite(l1)
+
+
+def _fp32_forward(theta, x):
+    """An FP32 evaluation of the BF16 network written independently of the
+    reference: float32 matrix products (BLAS sgemm accumulation order),
+    float32 erf, BF16 rounding by torch's own conversion."""
+    def bf(v):
+        return torch.tensor(np.asarray(v, np.float32)).to(torch.bfloat16).to(torch.float32).numpy()
+    from scipy.special import erf
+    a = bf(x)
+    at = 0
+    for li, (o, i) in enumerate(om.SIZES):
+        W = bf(theta[at:at + o * i].reshape(o, i))
+        at += o * i
+        b = np.asarray(theta[at:at + o], np.float32)
+        at += o
+        z = (a @ W.T + b).astype(np.float32)
+        if li == 3:
+            return z
+        g = (np.float32(0.5) * z * (np.float32(1) + erf(z * np.float32(0.70710678)).astype(np.float32))).astype(np.float32)
+        a = bf(g)
+
+
+def test_forward_tolerance_holds_an_fp32_evaluation():
+    """The element-wise bar of the GPU forward pass: one BF16 step at the
+    output's scale, 2^-7 rms(y), per element.  Both sides round every hidden
+    activation to BF16 at the same points; where an FP32 and the FP64 value
+    straddle a rounding boundary the two round apart by one BF16 step, which
+    moves the outputs by |w| ulp(a), far below the bar.  An independent FP32
+    evaluation lands inside it on every element; a planted error of a few
+    steps on one element does not."""
+    rng = np.random.default_rng(7)
+    for seed in (3, 4, 5):
+        theta = om.init_params(seed) + rng.normal(scale=0.02, size=om.N_PARAMS)
+        x = om.bf16_round(rng.normal(size=(256, 64)))
+        y, _ = om.forward(theta, x, bf16=True)
+        y32 = _fp32_forward(theta, x).astype(np.float64)
+        tol = 2.0 ** -7 * float(np.sqrt(np.mean(y * y)))
+        assert (np.abs(y32 - y) <= tol).all(), float(np.abs(y32 - y).max() / tol)
+        bad = y32.copy()
+        bad[3, 17] += 3 * tol
+        assert (np.abs(bad - y) > tol).sum() == 1

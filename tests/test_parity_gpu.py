@@ -495,3 +495,48 @@ def test_async_and_graph_replay_match_sync(pockets):
         # unrelated eager work between replays
         x = torch.randn(1000, 1000, device="cuda:0")
         (x @ x).sum().item()
+
+
+def test_full_c3_batch_autotuned_graph_sampled_replay(pockets):
+    """The whole uneven batch (100,000 ligands x 128 orientations x 128 steps)
+    as the benchmark runs it: autotuned launch, replayed HIP graph.  Sampled
+    items are replayed by the reference; every ligand's best orientation is
+    its own argmax; the result equals an eager launch's."""
+    import torch
+    p, h = pockets(3)
+    ligs = synth.ligands(3)
+    orient = synth.orientations(3)
+    L, O, S = ligs.n_ligands, 128, 128
+    tune = dock.dock_autotune(h, ligs, orient, S, sample_ligands=2000, seed=1)
+    print(f"[gpu] full uneven batch, autotuned to {dock.dock_get_launch(h)} over {len(tune)} mappings",
+          flush=True)
+    d, od, out = _device_batch(ligs, orient, S, torch)
+    ws = torch.empty(dock.dock_workspace_size(L, d["total_rot"], O, S), dtype=torch.uint8, device="cuda:0")
+    st = torch.cuda.Stream()
+    mx = int(np.diff(ligs.atom_offset).max())
+    names = ("best_score", "best_orient", "angle_idx", "xyz", "all_scores", "all_angle_idx", "status")
+    dock.dock_batch_async(h, d, od, S, out, dock.make_params(max_atoms=mx), workspace=ws, stream=st)
+    st.synchronize()
+    eager = {k: out[k].cpu().numpy() for k in names}
+    for k in names:
+        out[k].fill_(0)
+    torch.cuda.synchronize()
+    gprm = dock.make_params(max_atoms=mx, flags=dock.DOCK_FLAG_GRAPH)
+    for _ in range(2):  # capture, then a replay
+        dock.dock_batch_async(h, d, od, S, out, gprm, workspace=ws, stream=st)
+        st.synchronize()
+    res = {k: out[k].cpu().numpy() for k in names}
+    for k in names:
+        assert np.array_equal(res[k], eager[k]), k
+    assert (res["status"] == 0).all()
+    res["xyz"] = res["xyz"].reshape(-1, 3)
+    s = res["all_scores"]
+    assert np.array_equal(res["best_orient"], np.argmax(s, axis=1))
+    assert np.array_equal(res["best_score"], s[np.arange(L), res["best_orient"]])
+    rng = np.random.default_rng(31)
+    pick = rng.choice(L, 40, replace=False)
+    rep = check_batch(p, ligs, orient, S, res, ligands=pick, orients=rng.choice(O, 2, replace=False))
+    print(rep.summary())
+    assert rep.ok(), rep.summary()
+    rep.assert_rare()
+    dock.dock_set_launch(h, 0, 0, 16)
