@@ -328,15 +328,35 @@ int dock_set_launch(dock_pocket *p, int waves_per_block, int blocks_per_cu,
 int dock_get_launch(dock_pocket *p, int *waves_per_block, int *blocks_per_cu,
                     int *items_per_claim);
 
+/* Grouped mapping of the plain sweep (paper §4.1 explores gang / worker /
+ * vector mappings per function; here the mapping follows the ligand's size).
+ * Ligands of at most atoms16 atoms are docked four orientations per wave, one
+ * 16-lane group per (ligand, orientation) item; ligands of at most atoms32
+ * atoms two per wave in 32-lane groups; larger ones one per wave.  The items
+ * of one wave share the ligand's topology, so the per-step bookkeeping that
+ * leaves most of a 64-lane wave idle on a small ligand (clash arcs of a few
+ * kept pairs, applying the chosen angle, reductions) serves several items.
+ * Each size class is a contiguous range of the cost-sorted order, docked by
+ * its own persistent kernel.  0 disables a class; atoms16 <= 64,
+ * atoms32 <= 128 and atoms32 > atoms16 unless 0 (DOCK_E_LIMIT /
+ * DOCK_E_INVAL).  Applies to plain pruned sweeps in cost order (not with
+ * DOCK_FLAG_NO_LPT or DOCK_FLAG_DIRECT_BUMP, nor learned mode).  Results are
+ * bitwise identical under every mapping.  A new handle starts at (48, 96). */
+int dock_set_group_mapping(dock_pocket *p, int atoms16, int atoms32);
+int dock_get_group_mapping(dock_pocket *p, int *atoms16, int *atoms32);
+
 /* One measured mapping of dock_autotune. */
 typedef struct {
   int32_t waves_per_block, blocks_per_cu, items_per_claim;
   float sweep_ms;
+  int32_t group16_atoms, group32_atoms;  /* dock_set_group_mapping's bounds */
 } dock_tune_entry;
 
-/* Autotuner: time the sweep kernel for every candidate launch mapping on a
- * seeded subset of sample_ligands ligands of this (host) batch, keep the
- * fastest on the handle, and report each timing in entries[0..*n_entries).
+/* Autotuner: time the sweep for every candidate mapping (waves per block
+ * 1, 2, 4 x claim caps 4, 16, 32, 64 x group bounds (0, 0), (40, 80),
+ * (48, 96), (56, 112)) on a seeded subset of sample_ligands ligands of this
+ * (host) batch, keep the fastest on the handle (dock_set_launch and
+ * dock_set_group_mapping), and report each timing in entries[0..*n_entries).
  * Same validation and errors as dock_batch. */
 int dock_autotune(dock_pocket *p, const dock_ligands *ligs, const float *orient,
                   int n_orient, int angle_steps, const dock_params *prm,

@@ -11,7 +11,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB_PATH = os.path.join(PKG, "libdock.so")
 
-SOURCES = ["sweep_kernels.hip", "sweep_pruned.hip", "align.hip", "learned.hip", "mlp.hip", "mlp_abi.hip",
+SOURCES = ["sweep_kernels.hip", "sweep_pruned.hip", "sweep_group.hip", "align.hip", "learned.hip", "mlp.hip", "mlp_abi.hip",
            "probe.hip", "dock_abi.hip", "hybrid.hip"]
 # host-only C++ (the hybrid path's CPU sweep), compiled by the host compiler
 HOST_SOURCES = ["cpu_sweep.cpp"]

@@ -60,7 +60,10 @@ struct dock_pocket {
   hipEvent_t ev_align[2] = {nullptr, nullptr};  // alignment start/end
   bool align_timed = false;
   unsigned long long *h_work = nullptr;  // pinned copy of the sweep's two work counters
-  LaunchPlan plan{0, 0, 16};
+  // grouped classes on by default: (48, 96) measured fastest on the
+  // 100,000-ligand uneven batch (165 -> 125 ms) and the 10,000-ligand batch
+  // (20.2 -> 18.2 ms) among the bounds the autotuner tries
+  LaunchPlan plan{0, 0, 16, 48, 96};
   void *scratch = nullptr;    // this device's copy of the static workspace
   std::vector<float> host_grid;  // host copy of the grid, made on first use (hybrid calls)
   HybridCache hybrid;            // the hybrid entry point's streams and buffers
@@ -374,9 +377,14 @@ int enqueue_batch(dock_pocket *p, const dock_ligands *ligs, const float *orient,
   A.emit_x = emit_x;
   A.emit_t = emit_t;
   A.emit_mask = emit_mask;
-  int32_t *counts = A.small + 64, *cursor = A.small + 64 + kLptBuckets;
+  int32_t *counts = A.small + 64, *cursor = A.small + 64 + kSortBuckets;
   bool lpt = !(prm->flags & DOCK_FLAG_NO_LPT) && !learned;
-  hipError_t e = enqueue_prepare(A, max_atoms, learned ? max_rot : DOCK_MAX_ROT, lpt,
+  // size classes for the grouped mappings: plain pruned sweeps in LPT order
+  LaunchPlan plan = p->plan;
+  if (!lpt || emit_x || (prm->flags & DOCK_FLAG_DIRECT_BUMP)) plan.group16_atoms = plan.group32_atoms = 0;
+  const int c16 = min(plan.group16_atoms, max_atoms);
+  const int c32 = max(c16, min(plan.group32_atoms, max_atoms));
+  hipError_t e = enqueue_prepare(A, max_atoms, learned ? max_rot : DOCK_MAX_ROT, lpt, c16, c32,
                                  (int32_t *)(base + w.bucket), counts, cursor,
                                  A.small + 1, st);
   if (e != hipSuccess) return hip_fail(e, "prepare kernels");
@@ -474,7 +482,7 @@ int enqueue_batch(dock_pocket *p, const dock_ligands *ligs, const float *orient,
   if (mode == kSweepDirect)
     e = enqueue_sweep(A, maxn, p->plan, p->n_cu, st);
   else
-    e = enqueue_sweep_pruned(A, max_atoms, p->plan, p->n_cu, st);
+    e = enqueue_sweep_pruned(A, max_atoms, plan, p->n_cu, st);
   if (e != hipSuccess) return hip_fail(e, "sweep kernel");
   if (timed) {
     if (ev && (e = hipEventRecord(p->ev_ring[p->ring_next][1], st)) != hipSuccess)
@@ -590,7 +598,29 @@ int dock_set_launch(dock_pocket *p, int waves_per_block, int blocks_per_cu,
   if (blocks_per_cu < 0) return fail(DOCK_E_INVAL, "blocks_per_cu must be >= 0");
   if (items_per_claim < 1 || items_per_claim > 64)
     return fail(DOCK_E_INVAL, "items_per_claim must be in [1, 64]");
-  p->plan = LaunchPlan{waves_per_block, blocks_per_cu, items_per_claim};
+  p->plan = LaunchPlan{waves_per_block, blocks_per_cu, items_per_claim, p->plan.group16_atoms,
+                       p->plan.group32_atoms};
+  return DOCK_OK;
+}
+
+int dock_set_group_mapping(dock_pocket *p, int atoms16, int atoms32) {
+  g_last_error.clear();
+  if (!p) return fail(DOCK_E_INVAL, "NULL pocket");
+  if (atoms16 < 0 || atoms16 > kGroupMaxAtoms16 || atoms32 < 0 || atoms32 > kGroupMaxAtoms32)
+    return fail(DOCK_E_LIMIT, "group bounds (%d, %d) outside [0, %d] x [0, %d]", atoms16, atoms32,
+                kGroupMaxAtoms16, kGroupMaxAtoms32);
+  if (atoms32 != 0 && atoms32 <= atoms16)
+    return fail(DOCK_E_INVAL, "the 32-lane class must hold larger ligands than the 16-lane class");
+  p->plan.group16_atoms = atoms16;
+  p->plan.group32_atoms = atoms32;
+  return DOCK_OK;
+}
+
+int dock_get_group_mapping(dock_pocket *p, int *atoms16, int *atoms32) {
+  g_last_error.clear();
+  if (!p || !atoms16 || !atoms32) return fail(DOCK_E_INVAL, "NULL argument");
+  *atoms16 = p->plan.group16_atoms;
+  *atoms32 = p->plan.group32_atoms;
   return DOCK_OK;
 }
 
@@ -668,12 +698,15 @@ int dock_autotune(dock_pocket *p, const dock_ligands *ligs, const float *orient,
   tp.flags |= DOCK_FLAG_TIME_SWEEP;
   const int waves[] = {1, 2, 4};
   const int claims[] = {4, 16, 32, 64};
+  // size classes docked in groups: none, and three (16-lane, 32-lane) bounds
+  const int groups[][2] = {{0, 0}, {40, 80}, {48, 96}, {56, 112}};
   LaunchPlan best_plan = p->plan;
   float best_ms = 0.0f;
   int n = 0;
-  for (int w : waves)
+  for (const auto &gm : groups)
+   for (int w : waves)
     for (int c : claims) {
-      p->plan = LaunchPlan{w, 0, c};
+      p->plan = LaunchPlan{w, 0, c, gm[0], gm[1]};
       float ms_sum = 0.0f;
       for (int rep = 0; rep < 3; ++rep) {
         rc = dock_batch(p, &sub, orient, n_orient, angle_steps, &tp, &res);
@@ -687,11 +720,11 @@ int dock_autotune(dock_pocket *p, const dock_ligands *ligs, const float *orient,
         if (rep > 0) ms_sum += ms;  // first run warms caches
       }
       const float ms = ms_sum / 2.0f;
-      if (entries && n < max_entries) entries[n] = dock_tune_entry{w, 0, c, ms};
+      if (entries && n < max_entries) entries[n] = dock_tune_entry{w, 0, c, ms, gm[0], gm[1]};
       ++n;
       if (best_ms == 0.0f || ms < best_ms) {
         best_ms = ms;
-        best_plan = LaunchPlan{w, 0, c};
+        best_plan = LaunchPlan{w, 0, c, gm[0], gm[1]};
       }
     }
   p->plan = best_plan;

@@ -8,12 +8,23 @@
 
 namespace dock {
 
-constexpr int kLptBuckets = 128;
+constexpr int kLptBuckets = 128;  // cost buckets per size class
+// Size classes of the plain sweep: ligands of at most group16 atoms are docked
+// four orientations per wave (16-lane groups), those of at most group32 two
+// per wave (32-lane groups), the rest one per wave; each class is a
+// contiguous range of the cost-sorted ligand order with its own kernel.
+constexpr int kClasses = 3;
+constexpr int kGroupMaxAtoms16 = 64;   // largest ligands the 16-lane class may take
+constexpr int kGroupMaxAtoms32 = 128;  // and the 32-lane class
 // small integer block at the head of the workspace:
-//   [0] work-queue counter, [1] rejected-ligand count,
-//   [4, 6) 64-bit count of executed (pair, angle) bump tests,
-//   [64, 64+B) bucket counts, [64+B, 64+2B) bucket cursors
-constexpr int kSmallInts = 64 + 2 * kLptBuckets;
+//   [0] work-queue counter of the one-item-per-wave sweep, [1] rejected-
+//   ligand count, [4, 8) 64-bit work counters (kept pairs, evaluations),
+//   [8 + c] first and [12 + c] end slot of size class c in the order,
+//   [16 + c] work-queue counter of class c's grouped sweep,
+//   [64, 64+B) bucket counts, [64+B, 64+2B) bucket cursors, B = 3 x 128
+constexpr int kClassBegin = 8, kClassEnd = 12, kClassQueue = 16;
+constexpr int kSortBuckets = kClasses * kLptBuckets;
+constexpr int kSmallInts = 64 + 2 * kSortBuckets;
 // pruned sweep: margin (A^2) added to r_bump^2 when dropping the pairs whose
 // distance lower bound shows they cannot clash
 constexpr float kPruneMargin = 1e-3f;
@@ -91,17 +102,30 @@ struct LaunchPlan {
   int waves_per_block;  // 1, 2 or 4; 0: the one with the most resident waves
   int blocks_per_cu;    // 0 = as many as occupancy allows
   int items_per_claim;  // 1 .. 64
+  int group16_atoms;    // size class docked in 16-lane groups: n <= this (0: none)
+  int group32_atoms;    // size class docked in 32-lane groups: n <= this (0: none)
 };
 
 // max_rot: ligands with more rotamers get status DOCK_E_LIMIT (at most 255).
-hipError_t enqueue_prepare(const SweepArgs &A, int max_atoms, int max_rot, bool lpt, int32_t *bucket_of,
-                           int32_t *counts, int32_t *cursor, int32_t *n_bad,
-                           hipStream_t st);
+// With lpt, ligands are ordered by size class (class bounds c16, c32: atoms
+// of the 16- and 32-lane classes, 0 for none) and, within a class, by cost;
+// the class ranges go to A.small[kClassBegin/kClassEnd + c].  Without, the
+// order is the input order and every ligand is in the last class.
+hipError_t enqueue_prepare(const SweepArgs &A, int max_atoms, int max_rot, bool lpt, int c16,
+                           int c32, int32_t *bucket_of, int32_t *counts, int32_t *cursor,
+                           int32_t *n_bad, hipStream_t st);
 hipError_t enqueue_fill_i32(int32_t *p, int n, int32_t v, hipStream_t st);
 hipError_t enqueue_sweep(const SweepArgs &A, int maxn, const LaunchPlan &plan, int n_cu,
                          hipStream_t st);
+// The plain pruned sweep: with grouped classes (plan.group16/32_atoms, LPT
+// order) one grouped kernel per class, then the one-item-per-wave kernel on
+// the last class.
 hipError_t enqueue_sweep_pruned(const SweepArgs &A, int max_atoms, const LaunchPlan &plan,
                                 int n_cu, hipStream_t st);
+// Grouped sweep of size class cls (G lanes per item, 64 / G items of one
+// ligand per wave); nmax: the class's most atoms.
+hipError_t enqueue_sweep_group(const SweepArgs &A, int G, int cls, int nmax,
+                               const LaunchPlan &plan, int n_cu, hipStream_t st);
 hipError_t enqueue_finalize(const SweepArgs &A, const FinalOut &F, int maxn, SweepMode mode,
                             hipStream_t st);
 hipError_t enqueue_align(const AlignArgs &A, int maxn, hipStream_t st);

@@ -76,9 +76,7 @@ __device__ __forceinline__ void write_step_inputs(const LearnedArgs &A, const Wa
 
 __device__ __forceinline__ void finish_item(const LearnedArgs &A, const WaveLds &W,
                                             const ItemInfo &I, int lane) {
-  float total = 0.0f;
-  for (int i = lane; i < I.n; i += kWave) total += W.X[i].w;
-  total = wave_sum(total);
+  const float total = pose_total(W, I.n, lane);
   if (lane == 0) {
     if (A.sw.all_scores) A.sw.all_scores[(size_t)I.l * A.sw.n_orient + I.o] = total;
     atomicMax(A.sw.keys + I.l, (unsigned long long)best_key(total, (uint32_t)I.o));

@@ -147,27 +147,29 @@ __device__ __forceinline__ RotState rotamer_setup(const WaveLds &W, int n, const
   R.m = T.m;
   R.xa = W.X[T.ra];
   R.u = bond_axis(R.xa, W.X[T.rb]);
-  // one pass over the atoms: static list, static score (per-lane partial
-  // sums in atom order, then a fixed butterfly), cylindrical coordinates
+  // one pass over the atoms: static list, static score (the mapping-
+  // independent chunked sum of chunk_sum_wave), cylindrical coordinates
   int q = 0;
   float cst = 0.0f;
   for (int base = 0; base < n; base += kWave) {
     const int i = base + lane;
     bool st = false;
+    float v = 0.0f;
     if (i < n) {
       const float4 xi = W.X[i];
       const bool moving = W.mov[i] != 0;
-      if (!moving) cst += xi.w;
+      if (!moving) v = xi.w;
       st = !moving && i != T.ra && i != T.rb;
       const Cyl c = cyl_of(xi, R.xa, R.u);
       W.C[i] = make_float4(c.rx, c.ry, c.rz, c.z);
     }
+    cst = chunk_sum_wave(cst, v, base, n);
     const uint64_t mask = wave_ballot(st);
     if (st) W.Q[lanes_before(mask, q)] = (int16_t)i;
     q += __popcll(mask);
   }
   R.q = q;
-  R.cst = wave_sum(cst);
+  R.cst = cst;
   wave_lds_sync();
   return R;
 }
@@ -248,44 +250,52 @@ __device__ __forceinline__ float arc_acos(float c) {
 // R = |(2A, 2B)|, beta = atan2(2B, 2A), c = (D' - r^2) / R: an open arc of
 // half-width acos(c) around beta.  Each lane takes one pair and marks the
 // angle steps inside its arc.
+// The clash arc of one pair with cylindrical coordinates ci (moving) and cj
+// (static) about the axis u, marked into BM (every launch mapping marks its
+// kept pairs through this function).
+__device__ __forceinline__ void mark_pair_arc(uint32_t *BM, const float4 &ci, const float4 &cj,
+                                              const float3 &u, float r2, int S,
+                                              float steps_per_rad) {
+  const float dz = ci.w - cj.w;
+  const float a_ = fmaf(ci.x, cj.x, fmaf(ci.y, cj.y, ci.z * cj.z));
+  const float cx = ci.y * cj.z - ci.z * cj.y;
+  const float cy = ci.z * cj.x - ci.x * cj.z;
+  const float cz = ci.x * cj.y - ci.y * cj.x;
+  const float b_ = fmaf(u.x, cx, fmaf(u.y, cy, u.z * cz));
+  const float rho2i = fmaf(ci.x, ci.x, fmaf(ci.y, ci.y, ci.z * ci.z));
+  const float rho2j = fmaf(cj.x, cj.x, fmaf(cj.y, cj.y, cj.z * cj.z));
+  const float A2 = 2.0f * a_, B2 = 2.0f * b_;
+  const float D = fmaf(dz, dz, rho2i + rho2j) - r2;
+  const float RR = fmaf(A2, A2, B2 * B2);
+  // |D| >= R: the sign of D decides (compared squared, no square root);
+  // past these tests RR > D^2 >= 0, so the arc's R is positive
+  if (D >= 0.0f && D * D >= RR) return;  // never closer than r_bump
+  if (D < 0.0f && D * D >= RR) {          // closer than r_bump at every angle
+    mark_steps(BM, 0, S, S);
+    return;
+  }
+  const float half = arc_acos(__builtin_amdgcn_fmed3f(D * __builtin_amdgcn_rsqf(RR), -1.0f, 1.0f));
+  const float beta = arc_atan2(B2, A2);
+  const int klo = (int)floorf((beta - half) * steps_per_rad) + 1;
+  const int khi = (int)ceilf((beta + half) * steps_per_rad) - 1;
+  const int len = khi - klo + 1;
+  if (len <= 0) return;
+  if (len >= S) {
+    mark_steps(BM, 0, S, S);
+    return;
+  }
+  // klo lies in (-S, S/2 + 1]: one wrap either way replaces an integer modulo
+  int lo = klo < 0 ? klo + S : klo;
+  lo = lo >= S ? lo - S : lo;
+  mark_steps(BM, lo, len, S);
+}
+
 __device__ __forceinline__ void mark_kept_pairs(const WaveLds &W, const RotState &R, float r2,
                                                 int cnt, int S, int lane) {
   const float steps_per_rad = (float)S * 0.15915494309189535f;  // S / (2 pi)
   for (int e = lane; e < cnt; e += kWave) {
     const int ij = W.PI[e];
-    const float4 ci = W.C[ij >> 16], cj = W.C[ij & 0xFFFF];
-    const float dz = ci.w - cj.w;
-    const float a_ = fmaf(ci.x, cj.x, fmaf(ci.y, cj.y, ci.z * cj.z));
-    const float cx = ci.y * cj.z - ci.z * cj.y;
-    const float cy = ci.z * cj.x - ci.x * cj.z;
-    const float cz = ci.x * cj.y - ci.y * cj.x;
-    const float b_ = fmaf(R.u.x, cx, fmaf(R.u.y, cy, R.u.z * cz));
-    const float rho2i = fmaf(ci.x, ci.x, fmaf(ci.y, ci.y, ci.z * ci.z));
-    const float rho2j = fmaf(cj.x, cj.x, fmaf(cj.y, cj.y, cj.z * cj.z));
-    const float A2 = 2.0f * a_, B2 = 2.0f * b_;
-    const float D = fmaf(dz, dz, rho2i + rho2j) - r2;
-    const float RR = fmaf(A2, A2, B2 * B2);
-    // |D| >= R: the sign of D decides (compared squared, no square root);
-    // past these tests RR > D^2 >= 0, so the arc's R is positive
-    if (D >= 0.0f && D * D >= RR) continue;  // never closer than r_bump
-    if (D < 0.0f && D * D >= RR) {           // closer than r_bump at every angle
-      mark_steps(W.BM, 0, S, S);
-      continue;
-    }
-    const float half = arc_acos(__builtin_amdgcn_fmed3f(D * __builtin_amdgcn_rsqf(RR), -1.0f, 1.0f));
-    const float beta = arc_atan2(B2, A2);
-    const int klo = (int)floorf((beta - half) * steps_per_rad) + 1;
-    const int khi = (int)ceilf((beta + half) * steps_per_rad) - 1;
-    const int len = khi - klo + 1;
-    if (len <= 0) continue;
-    if (len >= S) {
-      mark_steps(W.BM, 0, S, S);
-      continue;
-    }
-    // klo lies in (-S, S/2 + 1]: one wrap either way replaces an integer modulo
-    int lo = klo < 0 ? klo + S : klo;
-    lo = lo >= S ? lo - S : lo;
-    mark_steps(W.BM, lo, len, S);
+    mark_pair_arc(W.BM, W.C[ij >> 16], W.C[ij & 0xFFFF], R.u, r2, S, steps_per_rad);
   }
 }
 
@@ -611,6 +621,16 @@ __device__ __forceinline__ float rotamer_feature(const WaveLds &W, const RotStat
   const float py = R.xa.y + lx * ey + ly * fy + lz * u.y;
   const float pz = R.xa.z + lx * ez + ly * fz + lz * u.z;
   return fmaxf(voxel_value(G, px, py, pz), -1.0f);
+}
+
+// Final score of the pose in LDS: the chunked sum of every atom's value.
+__device__ __forceinline__ float pose_total(const WaveLds &W, int n, int lane) {
+  float total = 0.0f;
+  for (int base = 0; base < n; base += kWave) {
+    const int i = base + lane;
+    total = chunk_sum_wave(total, i < n ? W.X[i].w : 0.0f, base, n);
+  }
+  return total;
 }
 
 // Stage the rigid starting pose (orientation T) of a ligand in LDS.

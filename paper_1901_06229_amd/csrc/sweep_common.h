@@ -291,6 +291,36 @@ __device__ __forceinline__ float wave_sum(float v) {
   }));
 }
 
+// Sum of the 16 lanes of each DPP row in a fixed butterfly (pairs, quads,
+// half-rows, rows); every lane of the row gets the same bits (IEEE addition
+// is commutative).  All lanes of the row must be active.
+__device__ __forceinline__ float row_sum16(float v) {
+  auto add = [](uint32_t a, uint32_t b) {
+    return __float_as_uint(__uint_as_float(a) + __uint_as_float(b));
+  };
+  uint32_t u = __float_as_uint(v);
+  u = add(u, dpp_move<0xB1, 0xF>(0u, u));   // quad_perm [1,0,3,2]
+  u = add(u, dpp_move<0x4E, 0xF>(0u, u));   // quad_perm [2,3,0,1]
+  u = add(u, dpp_move<0x141, 0xF>(0u, u));  // row_half_mirror
+  u = add(u, dpp_move<0x140, 0xF>(0u, u));  // row_mirror
+  return __uint_as_float(u);
+}
+
+// Sum over the atoms of a ligand in the order every launch mapping uses, so
+// the static score and the final score are the same bits whichever mapping
+// docks the item: chunks of 16 consecutive atoms are each summed by
+// row_sum16 (atom 16 c + r in row lane r, absent atoms as +0), and the chunk
+// sums are added one after the other in chunk order, starting from +0.
+// This is the 64-lane form: lane i holds the value of atom base + i of the
+// current block of 64 atoms; returns acc plus the block's chunks below n.
+__device__ __forceinline__ float chunk_sum_wave(float acc, float v, int base, int n) {
+  const float rs = row_sum16(v);
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+    if (base + 16 * r < n) acc += lane_bcast(rs, 16 * r);
+  return acc;
+}
+
 // Order LDS traffic between lanes of one wave (no cross-wave barrier).
 __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");

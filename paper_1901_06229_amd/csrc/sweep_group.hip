@@ -1,0 +1,451 @@
+// Grouped mapping of the pruned sweep for small ligands: a wave docks 64 / G
+// orientations of one ligand at once, one G-lane group per (ligand,
+// orientation) item (G = 16 or 32).
+//
+// Why: a rotamer step of a small ligand leaves most of a 64-lane wave idle
+// in its per-step work -- the clash arcs of ~14 kept pairs, the application
+// of the chosen angle to ~7 moving atoms, the reductions, a partly filled
+// score tile.  The items of one ligand share its topology (atom count,
+// rotamers, moving and static lists), so groups of one wave run the same
+// loops in lockstep and only their data differ: each group keeps its own
+// pose, bump bits, kept pairs and compacted steps; the moving / static lists
+// are built once per wave.  Per item, that divides the per-step work by the
+// number of groups where it fits in G lanes.
+//
+// Every result is bitwise the one-item-per-wave kernel's: the same functions
+// place atoms, test and arc pairs, index voxels and key angles; scores add
+// the moving atoms in list order onto the static score, and the static and
+// final scores use the mapping-independent chunked atom sum.
+#include <hip/hip_runtime.h>
+
+#include "dock_internal.h"
+#include "sweep_common.h"
+#include "rotamer_step.h"
+
+namespace dock {
+
+// Scratch sizes of one group (entries): kept-pair list, compacted steps of a
+// chunk of steps (also the chunk length).
+template <int G> constexpr int kGroupPairCap = 4 * G;
+template <int G> constexpr int kGroupChunk = 8 * G;
+constexpr int kGroupScoreTiles = 2;  // compacted G-step tiles scored per pass
+
+__host__ __device__ inline int round16(int b) { return (b + 15) / 16 * 16; }
+
+// LDS of one wave: the shared lists, then one region per group.
+//   shared: Q, M (int16 [nmax]), mov (uint8 [nmax])
+//   group:  X (float4 [nmax]) pose, x y z and voxel value
+//           ZR (float2 [nmax]) axial coordinate and |r| about the bond axis
+//           scratch: kept pairs (int [4G]) during the bump test, then the
+//                    moving atoms' voxel-unit bases (float [9][G]) and the
+//                    compacted steps of a chunk (int16 [8G])
+//           BM (uint32 [(S + 31) / 32]) bump bits
+//           MZ (float2 [nmax]) the moving atoms' (z, |r|) in list order
+template <int G>
+__host__ __device__ inline int group_shared_bytes(int nmax) { return round16(nmax * 5); }
+template <int G>
+__host__ __device__ inline int group_scratch_bytes() {
+  const int pairs = kGroupPairCap<G> * 4, score = 9 * G * 4 + kGroupChunk<G> * 2;
+  return round16(pairs > score ? pairs : score);
+}
+template <int G>
+__host__ __device__ inline int group_region_bytes(int nmax, int S) {
+  return nmax * 16 + nmax * 8 + group_scratch_bytes<G>() + round16(4 * ((S + 31) / 32)) + nmax * 8;
+}
+template <int G>
+__host__ __device__ inline int group_wave_bytes(int nmax, int S) {
+  return group_shared_bytes<G>(nmax) + (kWave / G) * group_region_bytes<G>(nmax, S);
+}
+
+template <int G>
+struct GroupLds {
+  int16_t *Q, *M;
+  uint8_t *mov;
+  float4 *X;
+  float2 *ZR, *MZ;
+  int *PI;
+  float *B;
+  int16_t *CK;
+  uint32_t *BM;
+  __device__ GroupLds(char *wave_base, int nmax, int S, int gid) {
+    Q = (int16_t *)wave_base;
+    M = Q + nmax;
+    mov = (uint8_t *)(M + nmax);
+    char *g = wave_base + group_shared_bytes<G>(nmax) + gid * group_region_bytes<G>(nmax, S);
+    X = (float4 *)g;
+    ZR = (float2 *)(X + nmax);
+    char *scr = (char *)(ZR + nmax);
+    PI = (int *)scr;
+    B = (float *)scr;
+    CK = (int16_t *)(scr + 9 * G * 4);
+    BM = (uint32_t *)(scr + group_scratch_bytes<G>());
+    MZ = (float2 *)((char *)BM + round16(4 * ((S + 31) / 32)));
+  }
+};
+
+// Lane bookkeeping of a G-lane group.
+template <int G>
+struct Grp {
+  static constexpr int NG = kWave / G;
+  static constexpr uint32_t kLow = G == 32 ? 0xFFFFFFFFu : ((1u << G) - 1u);
+  int gid, gl, gbase;
+  uint32_t below;  // group lanes below this one
+  __device__ explicit Grp(int lane)
+      : gid(lane / G), gl(lane % G), gbase(lane / G * G), below((1u << (lane % G)) - 1u) {}
+  // this group's bits of a wave ballot (bit i: group lane i)
+  __device__ __forceinline__ uint32_t bits(uint64_t ballot) const {
+    return (uint32_t)(ballot >> gbase) & kLow;
+  }
+};
+
+// Sum over each group's lanes in the chunked order (see chunk_sum_wave):
+// the group's 16-lane rows are its chunks, added in row order.  acc and the
+// result are the same in all lanes of a group.
+template <int G>
+__device__ __forceinline__ float chunk_sum_group(float acc, float v, int base, int n, int gl) {
+  const float rs = row_sum16(v);
+  if constexpr (G == 16) {
+    return acc + rs;  // one chunk, below n whenever the loop runs
+  } else {
+    // the other row's sum (rows 2g and 2g + 1 swap: bitmask swizzle, xor 16)
+    const float other = __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(rs), 0x401F));
+    const bool lo = gl < 16;
+    acc += lo ? rs : other;
+    if (base + 16 < n) acc += lo ? other : rs;
+    return acc;
+  }
+}
+
+// Maximum of a 32-bit value over each group (all of its lanes get it).
+template <int G>
+__device__ __forceinline__ uint32_t group_max_u32(uint32_t v) {
+  auto mx = [](uint32_t a, uint32_t b) { return a > b ? a : b; };
+  v = mx(v, dpp_move<0xB1, 0xF>(0u, v));
+  v = mx(v, dpp_move<0x4E, 0xF>(0u, v));
+  v = mx(v, dpp_move<0x141, 0xF>(0u, v));
+  v = mx(v, dpp_move<0x140, 0xF>(0u, v));
+  if constexpr (G == 32) v = mx(v, (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x401F));
+  return v;
+}
+
+template <int G>
+__device__ __forceinline__ uint64_t group_max_u64(uint64_t v) {
+  const uint32_t hi = group_max_u32<G>((uint32_t)(v >> 32));
+  const uint32_t lo = group_max_u32<G>((uint32_t)(v >> 32) == hi ? (uint32_t)v : 0u);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// Scores of the lane's TC compacted steps kk (-1: none) -- static score plus
+// the moving atoms' values in list order, as rotamer_scores computes them.
+template <int G, int TC>
+__device__ __forceinline__ void group_scores(const GroupLds<G> &W, const Grp<G> &g, int m,
+                                             float cst, float4 xa, float3 u, const GridView &GV,
+                                             const GridScaled &GS, __amdgpu_buffer_rsrc_t grsrc,
+                                             const float (&cc)[TC], const float (&ss)[TC],
+                                             float (&score)[TC]) {
+#pragma unroll
+  for (int t = 0; t < TC; ++t) score[t] = cst;
+  for (int c0 = 0; c0 < m; c0 += G) {
+    if (c0 + g.gl < m) {
+      const Cyl c = cyl_of(W.X[W.M[c0 + g.gl]], xa, u);
+      const VoxBasis vb = voxel_basis(rot_basis(c, xa, u), GV);
+      float *B = W.B + g.gl;
+      B[0 * G] = vb.px, B[1 * G] = vb.py, B[2 * G] = vb.pz;
+      B[3 * G] = vb.ex, B[4 * G] = vb.ey, B[5 * G] = vb.ez;
+      B[6 * G] = vb.fx, B[7 * G] = vb.fy, B[8 * G] = vb.fz;
+    }
+    wave_lds_sync();
+    const int cnt = min(G, m - c0);
+    auto gather = [&](int tt, float(&v)[TC]) {
+      const float *B = W.B + tt;  // group-uniform address: broadcast reads
+      const VoxBasis vb{B[0 * G], B[1 * G], B[2 * G], B[3 * G], B[4 * G],
+                        B[5 * G], B[6 * G], B[7 * G], B[8 * G]};
+      uint32_t off[TC];
+#pragma unroll
+      for (int t = 0; t < TC; ++t) off[t] = basis_voxel_offset(GS, vb, cc[t], ss[t]);
+#pragma unroll
+      for (int t = 0; t < TC; ++t) v[t] = grid_load(grsrc, off[t]);
+      __builtin_amdgcn_sched_barrier(0);
+    };
+    auto accumulate = [&](const float(&v)[TC]) {
+#pragma unroll
+      for (int t = 0; t < TC; ++t) score[t] += v[t];
+    };
+    float va[TC], vb[TC];
+    gather(0, va);
+    int tt = 1;
+    for (; tt + 1 < cnt; tt += 2) {
+      gather(tt, vb);
+      accumulate(va);
+      gather(tt + 1, va);
+      accumulate(vb);
+    }
+    if (tt < cnt) {
+      gather(tt, vb);
+      accumulate(va);
+      accumulate(vb);
+    } else {
+      accumulate(va);
+    }
+    wave_lds_sync();
+  }
+}
+
+template <int G, int WAVES>
+__global__ void __launch_bounds__(WAVES *kWave)
+    sweep_group_kernel(SweepArgs args, int nmax, int cls) {
+  (void)args;
+  const SweepArgs &A = *(const SweepArgs *)__builtin_amdgcn_kernarg_segment_ptr();
+  constexpr int NG = kWave / G;
+  extern __shared__ float4 dyn_lds[];
+  const int wv = threadIdx.x / kWave;
+  const int lane = threadIdx.x % kWave;
+  const Grp<G> g(lane);
+  const int S = A.S;
+  const GroupLds<G> W((char *)dyn_lds + (size_t)wv * group_wave_bytes<G>(nmax, S), nmax, S, g.gid);
+  const GridView GV = A.grid;
+  const GridScaled GS = grid_scaled(GV);
+  const __amdgpu_buffer_rsrc_t grsrc = grid_rsrc(GV);
+  const int O = A.n_orient;
+  const float r2 = A.r2;
+  const float thr = r2 + kPruneMargin;
+  const float steps_per_rad = (float)S * 0.15915494309189535f;  // S / (2 pi)
+  const int words = (S + 31) / 32;
+  uint64_t kept_pairs = 0, evals = 0;  // this group's work counters
+
+  const int cb = A.small[kClassBegin + cls], ce = A.small[kClassEnd + cls];
+  const int upl = (O + NG - 1) / NG;  // units (NG orientations) per ligand
+  WorkQueue queue(A.small + kClassQueue + cls, (ce - cb) * upl, A.claim, (int)gridDim.x * WAVES);
+  for (int unit; queue.next(lane, unit);) {
+    const int slot = cb + unit / upl;
+    const int o_first = (unit - (slot - cb) * upl) * NG;
+    const int o_mine = o_first + g.gid;
+    const bool active = o_mine < O;
+    const int o = active ? o_mine : o_first;  // an idle group repeats the first one's item
+    const int l = A.order[slot];
+    if (A.status[l] != 0) continue;
+    const int a0 = A.lig.atom_offset[l];
+    const int n = A.lig.atom_offset[l + 1] - a0;
+    const int r0 = A.lig.rot_offset[l];
+    const int R = A.lig.rot_offset[l + 1] - r0;
+    {
+      const float *T = A.orient + 12 * ((size_t)l * A.orient_stride + o);
+      const float *xyz = A.lig.xyz + 3 * (size_t)a0;
+      for (int i = g.gl; i < n; i += G) {
+        const float3 x = orient_point(T, xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2]);
+        W.X[i] = make_float4(x.x, x.y, x.z, voxel_value(GV, x.x, x.y, x.z));
+      }
+    }
+    wave_lds_sync();
+    int16_t *kout = A.kstar + ((size_t)r0 * O + (size_t)o * R) * A.passes;
+    const int steps = R * A.passes;
+    int kreg = -1;  // group lane s holds the choice of step s (mod G) until written out
+    int step = 0;
+    for (int pass = 0; pass < A.passes; ++pass) {
+      for (int r = 0; r < R; ++r, ++step) {
+        const int rot = r0 + r;
+        const int ra = A.lig.rot_axis[2 * rot], rb = A.lig.rot_axis[2 * rot + 1];
+        const int ms = A.lig.move_offset[rot];
+        const int m = A.lig.move_offset[rot + 1] - ms;
+        // moving flags and list, static list: once per wave (shared topology)
+        for (int i = lane; i < n; i += kWave) W.mov[i] = 0;
+        wave_lds_sync();
+        for (int t = lane; t < m; t += kWave) {
+          const int i = A.lig.move_atoms[ms + t];
+          W.mov[i] = 1;
+          W.M[t] = (int16_t)i;
+        }
+        wave_lds_sync();
+        int q = 0;
+        for (int base = 0; base < n; base += kWave) {
+          const int i = base + lane;
+          const bool st = i < n && W.mov[i] == 0 && i != ra && i != rb;
+          const uint64_t mask = wave_ballot(st);
+          if (st) W.Q[lanes_before(mask, q)] = (int16_t)i;
+          q += __popcll(mask);
+        }
+        // per group: axis, (z, |r|) of every atom, static score
+        const float4 xa = W.X[ra];
+        const float3 u = bond_axis(xa, W.X[rb]);
+        float cst = 0.0f;
+        for (int base = 0; base < n; base += G) {
+          const int i = base + g.gl;
+          float v = 0.0f;
+          if (i < n) {
+            const float4 xi = W.X[i];
+            const Cyl c = cyl_of(xi, xa, u);
+            W.ZR[i] = make_float2(c.z, cyl_radius(make_float4(c.rx, c.ry, c.rz, c.z)));
+            if (W.mov[i] == 0) v = xi.w;
+          }
+          cst = chunk_sum_group<G>(cst, v, base, n, g.gl);
+        }
+        for (int w = g.gl; w < words; w += G) W.BM[w] = 0u;
+        wave_lds_sync();
+        for (int t = g.gl; t < m; t += G) W.MZ[t] = W.ZR[W.M[t]];
+        // the current pose's score (step 0): static score, then the moving
+        // atoms' values in list order
+        float s0 = cst;
+        for (int t = 0; t < m; ++t) s0 += W.X[W.M[t]].w;
+        wave_lds_sync();
+
+        // bump bits: pairs whose cylinder bound does not clear r_bump, then
+        // their clash arcs (pairs packed as moving-list position << 16 | j)
+        int np = 0;  // this group's kept pairs in the list
+        auto flush = [&]() {
+          wave_lds_sync();
+          const int most = (int)__builtin_amdgcn_readfirstlane((int)wave_max_u32((uint32_t)np));
+          for (int e0 = 0; e0 < most; e0 += G) {
+            const int e = e0 + g.gl;
+            if (e < np) {
+              const int pk = W.PI[e];
+              const int i = W.M[pk >> 16], j = pk & 0xFFFF;
+              const Cyl ci = cyl_of(W.X[i], xa, u), cj = cyl_of(W.X[j], xa, u);
+              mark_pair_arc(W.BM, make_float4(ci.rx, ci.ry, ci.rz, ci.z),
+                            make_float4(cj.rx, cj.ry, cj.rz, cj.z), u, r2, S, steps_per_rad);
+            }
+          }
+          if (active) kept_pairs += (uint64_t)np;
+          np = 0;
+          wave_lds_sync();
+        };
+        for (int jb = 0; jb < q; jb += G) {
+          const bool jin = jb + g.gl < q;
+          const int j = jin ? W.Q[jb + g.gl] : 0;
+          const float2 zrj = W.ZR[j];
+          const float zj = zrj.x, rj = jin ? zrj.y : __builtin_inff();
+          for (int t = 0; t < m; ++t) {
+            const float2 mz = W.MZ[t];  // group-uniform address: a broadcast read
+            const float dz = mz.x - zj;
+            const float dr = mz.y - rj;
+            const float lb = fmaf(dr, dr, dz * dz);
+            const uint32_t gb = g.bits(__builtin_amdgcn_fcmpf(lb, thr, 4));
+            if ((gb >> g.gl) & 1u) W.PI[np + __popc(gb & g.below)] = (t << 16) | j;
+            np += __popc(gb);
+            if (wave_ballot(np > kGroupPairCap<G> - G) != 0ull) flush();
+          }
+        }
+        flush();
+
+        // non-bumping steps, compacted per chunk and scored
+        uint64_t best = 0ull;
+        for (int c0 = 0; c0 < S; c0 += kGroupChunk<G>) {
+          int nv = 0;
+#pragma unroll
+          for (int w = 0; w < kGroupChunk<G> / G; ++w) {
+            const int k = c0 + w * G + g.gl;
+            const bool valid = k < S && ((W.BM[k >> 5] >> (k & 31)) & 1u) == 0u;
+            const uint32_t gb = g.bits(wave_ballot(valid));
+            if (valid) W.CK[nv + __popc(gb & g.below)] = (int16_t)k;
+            nv += __popc(gb);
+          }
+          wave_lds_sync();
+          if (active) evals += (uint64_t)m * (uint64_t)nv;
+          const int most = (int)__builtin_amdgcn_readfirstlane((int)wave_max_u32((uint32_t)nv));
+          for (int p0 = 0; p0 < most; p0 += kGroupScoreTiles * G) {
+            float cc[kGroupScoreTiles], ss[kGroupScoreTiles], score[kGroupScoreTiles];
+            int kk[kGroupScoreTiles];
+#pragma unroll
+            for (int t = 0; t < kGroupScoreTiles; ++t) {
+              const int jj = p0 + t * G + g.gl;
+              kk[t] = jj < nv ? W.CK[jj] : -1;
+              const float2 cs = A.cs[kk[t] > 0 ? kk[t] : 0];
+              cc[t] = cs.x;
+              ss[t] = cs.y;
+            }
+            group_scores<G, kGroupScoreTiles>(W, g, m, cst, xa, u, GV, GS, grsrc, cc, ss, score);
+#pragma unroll
+            for (int t = 0; t < kGroupScoreTiles; ++t) {
+              if (kk[t] == 0) score[t] = s0;
+              const uint64_t key = kk[t] >= 0 ? best_key(score[t], (uint32_t)kk[t]) : 0ull;
+              best = key > best ? key : best;
+            }
+          }
+          wave_lds_sync();
+        }
+        best = group_max_u64<G>(best);
+        const int kb = best ? (int)key_index(best) : -1;
+        if (g.gl == (step & (G - 1))) kreg = kb;
+        if ((step & (G - 1)) == G - 1 && active) kout[(step & ~(G - 1)) + g.gl] = (int16_t)kreg;
+        // apply the group's chosen angle (the voxel value from the scoring
+        // expression, as rotamer_apply)
+        if (kb > 0) {
+          const float2 cs = A.cs[kb];
+          for (int t = g.gl; t < m; t += G) {
+            const int i = W.M[t];
+            const Cyl c = cyl_of(W.X[i], xa, u);
+            const RotBasis bs = rot_basis(c, xa, u);
+            const float3 y = rot_apply(bs, cs.x, cs.y);
+            const uint32_t off = basis_voxel_offset(GS, voxel_basis(bs, GV), cs.x, cs.y);
+            W.X[i] = make_float4(y.x, y.y, y.z, GV.grid[off >> 2]);
+          }
+        }
+        wave_lds_sync();
+      }
+    }
+    if ((step & (G - 1)) != 0 && g.gl < (step & (G - 1)) && active)
+      kout[(step & ~(G - 1)) + g.gl] = (int16_t)kreg;
+    float total = 0.0f;
+    for (int base = 0; base < n; base += G) {
+      const int i = base + g.gl;
+      total = chunk_sum_group<G>(total, i < n ? W.X[i].w : 0.0f, base, n, g.gl);
+    }
+    if (g.gl == 0 && active) {
+      if (A.all_scores) A.all_scores[(size_t)l * O + o] = total;
+      atomicMax(A.keys + l, (unsigned long long)best_key(total, (uint32_t)o));
+    }
+    wave_lds_sync();
+  }
+  if (g.gl == 0 && A.work) {
+    atomicAdd(A.work, (unsigned long long)kept_pairs);
+    atomicAdd(A.work + 1, (unsigned long long)evals);
+  }
+}
+
+template <int G, int WAVES>
+static hipError_t launch_group(const SweepArgs &A, int cls, int nmax, const LaunchPlan &plan,
+                               int n_cu, hipStream_t st, int *waves_per_cu) {
+  const size_t shmem = (size_t)WAVES * group_wave_bytes<G>(nmax, A.S);
+  *waves_per_cu = 0;
+  if (shmem > 65536) return hipSuccess;
+  int occ = 0;
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, sweep_group_kernel<G, WAVES>,
+                                                              WAVES * kWave, shmem);
+  if (e != hipSuccess) return e;
+  if (occ < 1) return hipSuccess;
+  const int bpc = plan.blocks_per_cu > 0 && plan.blocks_per_cu < occ ? plan.blocks_per_cu : occ;
+  *waves_per_cu = bpc * WAVES;
+  if (!st) return hipSuccess;  // query only
+  hipLaunchKernelGGL((sweep_group_kernel<G, WAVES>), dim3((unsigned)(bpc * n_cu)),
+                     dim3(WAVES * kWave), shmem, st, A, nmax, cls);
+  return hipGetLastError();
+}
+
+template <int G>
+static hipError_t enqueue_group_t(const SweepArgs &A, int cls, int nmax, const LaunchPlan &plan,
+                                  int n_cu, hipStream_t st) {
+  const int w = plan.waves_per_block;
+  int n1 = 0, n2 = 0, n4 = 0;
+  hipError_t e = hipSuccess;
+  if (w == 4) return launch_group<G, 4>(A, cls, nmax, plan, n_cu, st, &n4);
+  if (w == 2) return launch_group<G, 2>(A, cls, nmax, plan, n_cu, st, &n2);
+  if (w == 1) return launch_group<G, 1>(A, cls, nmax, plan, n_cu, st, &n1);
+  if (w != 0) return hipErrorInvalidValue;
+  // automatic: the block size with the most resident waves (up to 6 per SIMD)
+  if ((e = launch_group<G, 4>(A, cls, nmax, plan, n_cu, nullptr, &n4)) != hipSuccess) return e;
+  if ((e = launch_group<G, 2>(A, cls, nmax, plan, n_cu, nullptr, &n2)) != hipSuccess) return e;
+  if ((e = launch_group<G, 1>(A, cls, nmax, plan, n_cu, nullptr, &n1)) != hipSuccess) return e;
+  n4 = min(n4, 24), n2 = min(n2, 24), n1 = min(n1, 24);
+  if (n4 >= n2 && n4 >= n1 && n4 > 0) return launch_group<G, 4>(A, cls, nmax, plan, n_cu, st, &n4);
+  if (n2 >= n1 && n2 > 0) return launch_group<G, 2>(A, cls, nmax, plan, n_cu, st, &n2);
+  if (n1 > 0) return launch_group<G, 1>(A, cls, nmax, plan, n_cu, st, &n1);
+  return hipErrorInvalidValue;  // not even one wave fits
+}
+
+hipError_t enqueue_sweep_group(const SweepArgs &A, int G, int cls, int nmax,
+                               const LaunchPlan &plan, int n_cu, hipStream_t st) {
+  if (G == 16) return enqueue_group_t<16>(A, cls, nmax, plan, n_cu, st);
+  if (G == 32) return enqueue_group_t<32>(A, cls, nmax, plan, n_cu, st);
+  return hipErrorInvalidValue;
+}
+
+}  // namespace dock

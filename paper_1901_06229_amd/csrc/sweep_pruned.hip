@@ -56,10 +56,13 @@ __global__ void __launch_bounds__(WAVES *kWave)
   constexpr bool emit = EMIT;  // profile emission: S == 256, TG == 4
   uint64_t kept_pairs = 0, evals = 0;  // work counters of this wave
 
-  WorkQueue queue(A.queue, A.n_items, A.claim, (int)gridDim.x * WAVES);
+  // the last size class: slots [cb, ce) of the cost order (all of them when
+  // no grouped class is in use)
+  const int cb = A.small[kClassBegin + kClasses - 1], ce = A.small[kClassEnd + kClasses - 1];
+  WorkQueue queue(A.queue, (ce - cb) * O, A.claim, (int)gridDim.x * WAVES);
   for (int item; queue.next(lane, item);) {
-    const int slot = item / O;
-    const int o = item - slot * O;
+    const int slot = cb + item / O;
+    const int o = item - (slot - cb) * O;
     const int l = A.order[slot];
     if (A.status[l] != 0) continue;
     const int a0 = A.lig.atom_offset[l];
@@ -145,9 +148,7 @@ __global__ void __launch_bounds__(WAVES *kWave)
       }
     }
     if ((step & 63) != 0 && lane < (step & 63)) kout[(step & ~63) + lane] = (int16_t)kreg;
-    float total = 0.0f;
-    for (int i = lane; i < n; i += kWave) total += W.X[i].w;
-    total = wave_sum(total);
+    const float total = pose_total(W, n, lane);
     if (lane == 0) {
       if (A.all_scores) A.all_scores[(size_t)l * O + o] = total;
       atomicMax(A.keys + l, (unsigned long long)best_key(total, (uint32_t)o));
@@ -242,8 +243,19 @@ static hipError_t launch_pruned_tg(const SweepArgs &A, int nmax, const LaunchPla
 hipError_t enqueue_sweep_pruned(const SweepArgs &A, int max_atoms, const LaunchPlan &plan,
                                 int n_cu, hipStream_t st) {
   if (A.n_items <= 0) return hipSuccess;
-  const int nmax = (max_atoms + 15) / 16 * 16;
   const int T = (A.S + kWave - 1) / kWave;
+  if (!A.emit_x) {
+    // grouped classes first (their kernels find their ranges in A.small)
+    const int c16 = min(plan.group16_atoms, max_atoms);
+    const int c32 = min(plan.group32_atoms, max_atoms);
+    hipError_t e = hipSuccess;
+    if (c16 > 0) e = enqueue_sweep_group(A, 16, 0, (c16 + 15) / 16 * 16, plan, n_cu, st);
+    if (e == hipSuccess && c32 > c16)
+      e = enqueue_sweep_group(A, 32, 1, (c32 + 15) / 16 * 16, plan, n_cu, st);
+    if (e != hipSuccess) return e;
+    if (max_atoms <= max(c16, c32)) return hipSuccess;  // the last class is empty
+  }
+  const int nmax = (max_atoms + 15) / 16 * 16;
   if (A.emit_x) {  // profile emission: S == 256 (checked by the caller)
     if (T != 4) return hipErrorInvalidValue;
     int bpc = 0;

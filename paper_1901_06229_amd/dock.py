@@ -48,7 +48,8 @@ class dock_results(ctypes.Structure):
 
 class dock_tune_entry(ctypes.Structure):
     _fields_ = [("waves_per_block", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
-                ("items_per_claim", ctypes.c_int32), ("sweep_ms", ctypes.c_float)]
+                ("items_per_claim", ctypes.c_int32), ("sweep_ms", ctypes.c_float),
+                ("group16_atoms", ctypes.c_int32), ("group32_atoms", ctypes.c_int32)]
 
 
 class dock_hybrid_opts(ctypes.Structure):
@@ -136,6 +137,11 @@ def load_library(path: str = None):
     lib.dock_set_launch.restype = c.c_int
     lib.dock_get_launch.argtypes = [_P, c.POINTER(c.c_int), c.POINTER(c.c_int), c.POINTER(c.c_int)]
     lib.dock_get_launch.restype = c.c_int
+    for name in ("dock_set_group_mapping",):
+        getattr(lib, name).argtypes = [_P, c.c_int, c.c_int]
+        getattr(lib, name).restype = c.c_int
+    lib.dock_get_group_mapping.argtypes = [_P, c.POINTER(c.c_int), c.POINTER(c.c_int)]
+    lib.dock_get_group_mapping.restype = c.c_int
     lib.dock_autotune.argtypes = [_P, c.POINTER(dock_ligands), _P, c.c_int, c.c_int,
                                   c.POINTER(dock_params), c.c_int, c.c_uint64,
                                   c.POINTER(dock_tune_entry), c.c_int, c.POINTER(c.c_int)]
@@ -404,13 +410,29 @@ def dock_autotune(pocket: Pocket, ligs, orient, angle_steps: int, sample_ligands
     dl, keep = _host_ligands(ligs)
     orient = _c(orient, np.float32).reshape(-1, 12)
     prm = make_params(**param_kw)
-    entries = (dock_tune_entry * 64)()
+    entries = (dock_tune_entry * 256)()
     n = ctypes.c_int()
     _check(lib.dock_autotune(pocket.handle, ctypes.byref(dl), _np_ptr(orient), orient.shape[0],
                              int(angle_steps), ctypes.byref(prm), int(sample_ligands), int(seed),
-                             entries, 64, ctypes.byref(n)), "dock_autotune")
+                             entries, 256, ctypes.byref(n)), "dock_autotune")
     return [dict(waves_per_block=e.waves_per_block, blocks_per_cu=e.blocks_per_cu,
-                 items_per_claim=e.items_per_claim, sweep_ms=e.sweep_ms) for e in entries[:n.value]]
+                 items_per_claim=e.items_per_claim, sweep_ms=e.sweep_ms,
+                 group16_atoms=e.group16_atoms, group32_atoms=e.group32_atoms)
+            for e in entries[:n.value]]
+
+
+def dock_set_group_mapping(pocket: Pocket, atoms16: int = 0, atoms32: int = 0):
+    """Size classes docked 4 (<= atoms16 atoms) and 2 (<= atoms32) orientations
+    per wave; 0 disables a class."""
+    _check(load_library().dock_set_group_mapping(pocket.handle, int(atoms16), int(atoms32)),
+           "dock_set_group_mapping")
+
+
+def dock_get_group_mapping(pocket: Pocket):
+    a, b = ctypes.c_int(), ctypes.c_int()
+    _check(load_library().dock_get_group_mapping(pocket.handle, ctypes.byref(a), ctypes.byref(b)),
+           "dock_get_group_mapping")
+    return int(a.value), int(b.value)
 
 
 def _tptr(t):

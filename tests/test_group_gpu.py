@@ -1,0 +1,143 @@
+"""Grouped mapping of the plain sweep (dock_set_group_mapping): several
+orientations of one small ligand per wave in 16- or 32-lane groups.
+
+Results must be bitwise those of the one-item-per-wave mapping on every
+output, whatever the class bounds; the grouped runs are also replayed by the
+FP64 reference like every other GPU result.
+"""
+import numpy as np
+import pytest
+
+from paper_1901_06229_amd import dock, synth
+from tests.checker import check_batch
+
+pytestmark = pytest.mark.gpu
+
+NAMES = ("best_score", "best_orient", "angle_idx", "xyz", "all_scores", "all_angle_idx", "status")
+MAPPINGS = [(0, 0), (32, 64), (40, 80), (48, 96), (64, 128), (0, 96), (48, 0)]
+
+
+@pytest.fixture(scope="module")
+def pockets():
+    cache = {}
+
+    def get(cfg):
+        if cfg not in cache:
+            p = synth.pocket(cfg)
+            cache[cfg] = (p, dock.dock_init_pocket(p.grid, p.origin, p.spacing))
+        return cache[cfg]
+    yield get
+    for _, h in cache.values():
+        dock.dock_set_group_mapping(h, 0, 0)
+        h.close()
+
+
+def _run(h, ligs, orient, S, mapping, **kw):
+    dock.dock_set_group_mapping(h, *mapping)
+    print(f"[group] mapping {mapping}: {ligs.n_ligands} ligands x {orient.shape[0]} orientations, "
+          f"S={S} {kw}", flush=True)
+    return dock.dock_batch(h, ligs, orient, S, want_all=True, **kw)
+
+
+def _same(a, b, what):
+    for k in NAMES:
+        assert np.array_equal(np.asarray(a[k]), np.asarray(b[k])), (what, k)
+
+
+def test_grouped_results_are_bitwise_the_single_item_ones(pockets):
+    """Uneven ligands (8-150 atoms), an orientation count that leaves idle
+    groups in a ligand's last wave (22 = 5 x 4 + 2), every class bound."""
+    p, h = pockets(3)
+    ligs = synth.ligands(3, count=400, first=300)
+    orient = synth.orientations(3, 22)
+    ref = _run(h, ligs, orient, 128, (0, 0))
+    for mp in MAPPINGS[1:]:
+        _same(_run(h, ligs, orient, 128, mp), ref, mp)
+
+
+@pytest.mark.parametrize("S", [1, 7, 16, 17, 33, 127, 128, 129, 255, 257, 360])
+def test_grouped_step_counts(pockets, S):
+    """Step counts around the 16- and 32-step tiles, the 128- and 256-step
+    compaction chunks and the 32-bit mask words."""
+    p, h = pockets(2)
+    ligs = synth.ligands(2, count=24, first=900)
+    orient = synth.orientations(2, 9)
+    ref = _run(h, ligs, orient, S, (0, 0))
+    got = _run(h, ligs, orient, S, (64, 128))
+    _same(got, ref, S)
+
+
+def test_grouped_parity_with_reference(pockets):
+    """Grouped runs replayed item by item by the FP64 reference."""
+    p, h = pockets(3)
+    ligs = synth.ligands(3, count=60, first=4000)
+    orient = synth.orientations(3, 12)
+    res = _run(h, ligs, orient, 128, (48, 96))
+    rep = check_batch(p, ligs, orient, 128, res, orients=[0, 3, 7, 11])
+    print(rep.summary())
+    assert rep.ok(), rep.summary()
+    rep.assert_rare()
+    p1, h1 = pockets(1)
+    res = _run(h1, synth.ligands(1), synth.orientations(1), 64, (64, 0))
+    rep = check_batch(p1, synth.ligands(1), synth.orientations(1), 64, res)
+    assert rep.ok(), rep.summary()
+
+
+def test_grouped_passes_and_class_limits(pockets):
+    """Two passes, and ligands at exactly the class bounds (64 atoms in the
+    16-lane class, 128 in the 32-lane class), next to larger ones."""
+    p, h = pockets(3)
+    all_ligs = synth.ligands(3, count=3000)
+    n = np.diff(all_ligs.atom_offset)
+    pick = []
+    for lo, hi in ((60, 64), (120, 128), (129, 150), (8, 20)):
+        pick += list(np.flatnonzero((n >= lo) & (n <= hi))[:4])
+    ligs = all_ligs.subset(pick)
+    print("atoms", np.diff(ligs.atom_offset).tolist(), flush=True)
+    orient = synth.orientations(3, 10)
+    ref = _run(h, ligs, orient, 128, (0, 0), passes=2)
+    _same(_run(h, ligs, orient, 128, (64, 128), passes=2), ref, "passes 2")
+    rep = check_batch(p, ligs, orient, 128, _run(h, ligs, orient, 128, (64, 128), passes=2),
+                      passes=2, orients=[0, 9])
+    assert rep.ok(), rep.summary()
+
+
+def test_grouped_async_graph_replay(pockets):
+    """Device-array calls, eager and as a replayed HIP graph, with the grouped
+    mapping: equal to the synchronous one-item-per-wave call."""
+    import torch
+    from tests.test_parity_gpu import _device_batch
+    p, h = pockets(3)
+    ligs = synth.ligands(3, count=500, first=7000)
+    orient = synth.orientations(3, 16)
+    ref = _run(h, ligs, orient, 128, (0, 0))
+    dock.dock_set_group_mapping(h, 40, 80)
+    d, od, out = _device_batch(ligs, orient, 128, torch)
+    ws = torch.empty(dock.dock_workspace_size(ligs.n_ligands, d["total_rot"], 16, 128),
+                     dtype=torch.uint8, device="cuda:0")
+    st = torch.cuda.Stream()
+    mx = int(np.diff(ligs.atom_offset).max())
+    names = NAMES[:-1]
+    for flags in (0, dock.DOCK_FLAG_GRAPH, dock.DOCK_FLAG_GRAPH):
+        for k in names:
+            out[k].fill_(0)
+        torch.cuda.synchronize()
+        dock.dock_batch_async(h, d, od, 128, out, dock.make_params(max_atoms=mx, flags=flags),
+                              workspace=ws, stream=st)
+        st.synchronize()
+        got = {k: out[k].cpu().numpy() for k in names}
+        got["xyz"] = got["xyz"].reshape(-1, 3)
+        for k in names:
+            assert np.array_equal(np.asarray(ref[k]).reshape(got[k].shape), got[k]), (flags, k)
+
+
+def test_group_mapping_arguments(pockets):
+    p, h = pockets(1)
+    for a, b, code in ((65, 0, dock.DOCK_E_LIMIT), (0, 129, dock.DOCK_E_LIMIT),
+                       (48, 40, dock.DOCK_E_INVAL), (-1, 0, dock.DOCK_E_LIMIT)):
+        with pytest.raises(dock.DockError) as e:
+            dock.dock_set_group_mapping(h, a, b)
+        assert e.value.code == code
+    dock.dock_set_group_mapping(h, 32, 64)
+    assert dock.dock_get_group_mapping(h) == (32, 64)
+    dock.dock_set_group_mapping(h, 0, 0)
