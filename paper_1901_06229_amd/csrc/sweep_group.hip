@@ -27,30 +27,38 @@ namespace dock {
 // Scratch sizes of one group (entries): kept-pair list, compacted steps of a
 // chunk of steps (also the chunk length).
 template <int G> constexpr int kGroupPairCap = 4 * G;
-template <int G> constexpr int kGroupChunk = 8 * G;
+template <int G> constexpr int kGroupChunk = 4 * G;
 constexpr int kGroupScoreTiles = 2;  // compacted G-step tiles scored per pass
 
 __host__ __device__ inline int round16(int b) { return (b + 15) / 16 * 16; }
 
-// LDS of one wave: the shared lists, then one region per group.
-//   shared: Q, M (int16 [nmax]), mov (uint8 [nmax])
+// LDS of one wave: the shared lists, then one region per group.  LDS
+// bounds how many waves a compute unit holds, and these kernels run faster
+// with every wave added (latency-bound), so the regions are kept small.
+//   shared: Q, M (int16 [nmax]) static and moving lists of the step,
+//           slot (int16 [nmax]) an atom's entry in ZRc: moving atom t -> t,
+//           static atom Q[p] -> m + p, axis atoms -1
 //   group:  X (float4 [nmax]) pose, x y z and voxel value
-//           ZR (float2 [nmax]) axial coordinate and |r| about the bond axis
+//           ZRc (float2 [nmax]) axial coordinate and |r| about the bond axis
+//           of the moving atoms (in list order), then of the static ones
 //           scratch: kept pairs (int [4G]) during the bump test, then the
 //                    moving atoms' voxel-unit bases (float [9][G]) and the
-//                    compacted steps of a chunk (int16 [8G])
+//                    compacted steps of a chunk (int16 [4G])
 //           BM (uint32 [(S + 31) / 32]) bump bits
-//           MZ (float2 [nmax]) the moving atoms' (z, |r|) in list order
 template <int G>
-__host__ __device__ inline int group_shared_bytes(int nmax) { return round16(nmax * 5); }
+__host__ __device__ inline int group_shared_bytes(int nmax) { return round16(nmax * 6); }
 template <int G>
-__host__ __device__ inline int group_scratch_bytes() {
-  const int pairs = kGroupPairCap<G> * 4, score = 9 * G * 4 + kGroupChunk<G> * 2;
-  return round16(pairs > score ? pairs : score);
+__host__ __device__ constexpr int group_scratch_bytes() {
+  return (((kGroupPairCap<G> * 4 > 9 * G * 4 + kGroupChunk<G> * 2)
+               ? kGroupPairCap<G> * 4
+               : 9 * G * 4 + kGroupChunk<G> * 2) + 15) / 16 * 16;
 }
+// the scratch also holds the moving atoms' values (m < class atoms) for s0
+static_assert(group_scratch_bytes<16>() >= 4 * kGroupMaxAtoms16, "scratch too small");
+static_assert(group_scratch_bytes<32>() >= 4 * kGroupMaxAtoms32, "scratch too small");
 template <int G>
 __host__ __device__ inline int group_region_bytes(int nmax, int S) {
-  return nmax * 16 + nmax * 8 + group_scratch_bytes<G>() + round16(4 * ((S + 31) / 32)) + nmax * 8;
+  return nmax * 16 + nmax * 8 + group_scratch_bytes<G>() + round16(4 * ((S + 31) / 32));
 }
 template <int G>
 __host__ __device__ inline int group_wave_bytes(int nmax, int S) {
@@ -59,10 +67,9 @@ __host__ __device__ inline int group_wave_bytes(int nmax, int S) {
 
 template <int G>
 struct GroupLds {
-  int16_t *Q, *M;
-  uint8_t *mov;
+  int16_t *Q, *M, *slot;
   float4 *X;
-  float2 *ZR, *MZ;
+  float2 *ZRc;
   int *PI;
   float *B;
   int16_t *CK;
@@ -70,16 +77,15 @@ struct GroupLds {
   __device__ GroupLds(char *wave_base, int nmax, int S, int gid) {
     Q = (int16_t *)wave_base;
     M = Q + nmax;
-    mov = (uint8_t *)(M + nmax);
+    slot = M + nmax;
     char *g = wave_base + group_shared_bytes<G>(nmax) + gid * group_region_bytes<G>(nmax, S);
     X = (float4 *)g;
-    ZR = (float2 *)(X + nmax);
-    char *scr = (char *)(ZR + nmax);
+    ZRc = (float2 *)(X + nmax);
+    char *scr = (char *)(ZRc + nmax);
     PI = (int *)scr;
     B = (float *)scr;
     CK = (int16_t *)(scr + 9 * G * 4);
     BM = (uint32_t *)(scr + group_scratch_bytes<G>());
-    MZ = (float2 *)((char *)BM + round16(4 * ((S + 31) / 32)));
   }
 };
 
@@ -247,24 +253,29 @@ __global__ void __launch_bounds__(WAVES *kWave)
         const int ra = A.lig.rot_axis[2 * rot], rb = A.lig.rot_axis[2 * rot + 1];
         const int ms = A.lig.move_offset[rot];
         const int m = A.lig.move_offset[rot + 1] - ms;
-        // moving flags and list, static list: once per wave (shared topology)
-        for (int i = lane; i < n; i += kWave) W.mov[i] = 0;
+        // moving list, static list and slots: once per wave (shared topology)
+        for (int i = lane; i < n; i += kWave) W.slot[i] = -1;
         wave_lds_sync();
         for (int t = lane; t < m; t += kWave) {
           const int i = A.lig.move_atoms[ms + t];
-          W.mov[i] = 1;
+          W.slot[i] = (int16_t)t;
           W.M[t] = (int16_t)i;
         }
         wave_lds_sync();
         int q = 0;
         for (int base = 0; base < n; base += kWave) {
           const int i = base + lane;
-          const bool st = i < n && W.mov[i] == 0 && i != ra && i != rb;
+          const bool st = i < n && W.slot[i] < 0 && i != ra && i != rb;
           const uint64_t mask = wave_ballot(st);
-          if (st) W.Q[lanes_before(mask, q)] = (int16_t)i;
+          if (st) {
+            const int pos = lanes_before(mask, q);
+            W.Q[pos] = (int16_t)i;
+            W.slot[i] = (int16_t)(m + pos);
+          }
           q += __popcll(mask);
         }
-        // per group: axis, (z, |r|) of every atom, static score
+        wave_lds_sync();
+        // per group: axis, (z, |r|) of the moving and static atoms, static score
         const float4 xa = W.X[ra];
         const float3 u = bond_axis(xa, W.X[rb]);
         float cst = 0.0f;
@@ -273,19 +284,26 @@ __global__ void __launch_bounds__(WAVES *kWave)
           float v = 0.0f;
           if (i < n) {
             const float4 xi = W.X[i];
-            const Cyl c = cyl_of(xi, xa, u);
-            W.ZR[i] = make_float2(c.z, cyl_radius(make_float4(c.rx, c.ry, c.rz, c.z)));
-            if (W.mov[i] == 0) v = xi.w;
+            const int sl = W.slot[i];
+            if (sl >= 0) {
+              const Cyl c = cyl_of(xi, xa, u);
+              W.ZRc[sl] = make_float2(c.z, cyl_radius(make_float4(c.rx, c.ry, c.rz, c.z)));
+            }
+            if (sl < 0 || sl >= m) v = xi.w;  // everything that does not move
           }
           cst = chunk_sum_group<G>(cst, v, base, n, g.gl);
         }
         for (int w = g.gl; w < words; w += G) W.BM[w] = 0u;
+        // the moving atoms' current values, in list order, into the scratch
+        // (free until the pair list fills it): read in parallel, added below
+        float *mval = (float *)W.PI;
+        for (int t = g.gl; t < m; t += G) mval[t] = W.X[W.M[t]].w;
         wave_lds_sync();
-        for (int t = g.gl; t < m; t += G) W.MZ[t] = W.ZR[W.M[t]];
         // the current pose's score (step 0): static score, then the moving
-        // atoms' values in list order
+        // atoms' values in list order (independent broadcast reads)
         float s0 = cst;
-        for (int t = 0; t < m; ++t) s0 += W.X[W.M[t]].w;
+#pragma unroll 4
+        for (int t = 0; t < m; ++t) s0 += mval[t];
         wave_lds_sync();
 
         // bump bits: pairs whose cylinder bound does not clear r_bump, then
@@ -311,10 +329,11 @@ __global__ void __launch_bounds__(WAVES *kWave)
         for (int jb = 0; jb < q; jb += G) {
           const bool jin = jb + g.gl < q;
           const int j = jin ? W.Q[jb + g.gl] : 0;
-          const float2 zrj = W.ZR[j];
+          const float2 zrj = W.ZRc[jin ? m + jb + g.gl : 0];
           const float zj = zrj.x, rj = jin ? zrj.y : __builtin_inff();
+#pragma unroll 2
           for (int t = 0; t < m; ++t) {
-            const float2 mz = W.MZ[t];  // group-uniform address: a broadcast read
+            const float2 mz = W.ZRc[t];  // group-uniform address: a broadcast read
             const float dz = mz.x - zj;
             const float dr = mz.y - rj;
             const float lb = fmaf(dr, dr, dz * dz);
