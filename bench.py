@@ -61,8 +61,9 @@ ALIGN_ROTATIONS = 64
 
 # Sources of the sweep kernel: the HBM traffic measured by the FETCH_SIZE /
 # WRITE_SIZE counters is reported only while these are unchanged.
-KERNEL_SOURCES = ("sweep_pruned.hip", "rotamer_step.h", "sweep_common.h", "dock_internal.h")
-TRAFFIC_FILES = {cfg: os.path.join(ROOT, "profiles", f"sweep_pruned_c{cfg}_traffic.md") for cfg in (2, 3, 5)}
+KERNEL_SOURCES = ("sweep_pruned.hip", "sweep_group.hip", "rotamer_step.h", "sweep_common.h",
+                  "dock_internal.h")
+TRAFFIC_FILES = {cfg: os.path.join(ROOT, "profiles", f"sweep_c{cfg}_traffic.md") for cfg in (2, 3, 5)}
 
 WORKLOADS = {
     1: "C1: 64^3 pocket @0.5A, 1 ligand (32 atoms, 4 rotamers), 8 orientations, 64 steps",
@@ -148,6 +149,25 @@ def gather_probe(grid_floats, blocks=4096, iters=256):
         dock.dock_probe_gather(buf, out, log2, blocks, iters)
         ms = min(dock.dock_probe_gather(buf, out, log2, blocks, iters) for _ in range(3))
         res[name] = {"bytes": 4 << log2, "gathers_per_s": round(blocks * 256 * iters / (ms / 1e3), 1)}
+    return res
+
+
+def valu_probe(blocks=8192, iters=4096):
+    """Sustained VALU issue rate of the part (the library's probe kernel):
+    FP32 FMA chains, and the sweep's per-evaluation instruction mix, in
+    lane-ops per second; best of three runs each."""
+    import torch
+    from paper_1901_06229_amd import dock
+    out = torch.empty(blocks * 256, device="cuda:0")
+    res = {}
+    for name, kind, ops in (("fma", 0, 1), ("eval_mix", 1, 16)):
+        dock.dock_probe_valu(out, kind, blocks, iters)
+        ms = min(dock.dock_probe_valu(out, kind, blocks, iters) for _ in range(3))
+        res[name] = round(blocks * 256 * 8 * iters * ops / (ms / 1e3) / 1e12, 2)
+    res["unit"] = "T lane-ops/s"
+    res["note"] = ("issue-rate ceilings measured on this part: independent FP32 FMA chains, and the "
+                   "sweep's 16-instruction evaluation (6 FMA, 3 clamps, 3 conversions, 2 24-bit "
+                   "multiply-adds, conversion, add); packed FP32 is not used")
     return res
 
 
@@ -491,7 +511,10 @@ def plain_leg(cfg, steps, warmup, bump="pruned", waves=0, claim=16, autotune=0, 
                      "unit": "TOP/s", "frac": round(achieved / VALU_PEAK_TOPS, 4),
                      "traffic": measured_traffic(cfg) if (bump == "pruned" and L == preset["n_ligands"])
                      else None,
-                     "kernel": "sweep_pruned_kernel" if bump == "pruned" else "sweep_kernel",
+                     "kernel": (("sweep_group_kernel<16>, sweep_group_kernel<32>, sweep_pruned_kernel "
+                                 "(one launch per size class, timed together)")
+                                if bump == "pruned" and any(launch[k] for k in ("group16_atoms", "group32_atoms"))
+                                else "sweep_pruned_kernel" if bump == "pruned" else "sweep_kernel"),
                      "kernel_ms": round(1e3 * mean_s, 3),
                      **({"timed": "around each replayed graph (preparation, sweep, finalize)"}
                         if graph else {}),
@@ -717,6 +740,8 @@ def main():
     }
     if "end_to_end" in head:
         line["end_to_end"] = head["end_to_end"]
+    line["roofline"]["valu_probe"] = probe = valu_probe()
+    line["roofline"]["frac_of_probe_fma"] = round(line["roofline"]["achieved"] / probe["fma"], 4)
     line["paper_context"] = {
         "note": "the paper (arXiv 1901.06229) prints no throughput for this path and no workload "
                 "sizes (1500 unpublished ligands); its figures are context, not comparable",

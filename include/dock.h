@@ -314,6 +314,20 @@ int dock_last_sweep_work(dock_pocket *p, uint64_t *kept_pairs, uint64_t *atom_an
 int dock_probe_gather(const float *buf, int log2_floats, int blocks, int iters, float *out,
                       float *ms, void *stream);
 
+/* VALU issue probe (benchmark instrumentation, not part of the docking path):
+ * blocks x 256 threads each run 8 independent dependency chains for iters
+ * iterations and write one sum each to out[blocks * 256] (device memory).
+ * kind 0: one FP32 FMA per chain and iteration (a = b = 1, so each sum is
+ * exactly 8 iters + 8 (tid & 7) + 28 while below 2^24); kind 1: the sweep's
+ * per-evaluation instruction mix, 16 VALU instructions per chain and
+ * iteration (6 FMAs, 3 clamps, 3 conversions, 2 24-bit multiply-adds, a
+ * conversion and an add).  Lane operations per second = blocks * 256 * 8 *
+ * iters * (1 or 16) / (ms / 1000).  Runs on `stream`, waits for it and
+ * stores the kernel's duration in *ms.  Limits: kind 0 or 1 (DOCK_E_INVAL),
+ * 1 <= blocks <= 2^20, 1 <= iters <= 2^20 (DOCK_E_LIMIT); NULL or host
+ * pointers: DOCK_E_INVAL. */
+int dock_probe_valu(int kind, int blocks, int iters, float *out, float *ms, void *stream);
+
 /* Launch mapping of the sweep kernel for calls on this handle (the knobs the
  * autotuner turns): waves_per_block in {1, 2, 4}, each wave working on its
  * own (ligand, orientation) items, or 0 (the default) for the block size that

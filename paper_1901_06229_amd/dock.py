@@ -129,6 +129,8 @@ def load_library(path: str = None):
     lib.dock_probe_gather.restype = c.c_int
     lib.dock_probe_gather.argtypes = [_P, c.c_int, c.c_int, c.c_int, _P, c.POINTER(c.c_float), _P]
     lib.dock_last_sweep_ms.restype = c.c_int
+    lib.dock_probe_valu.restype = c.c_int
+    lib.dock_probe_valu.argtypes = [c.c_int, c.c_int, c.c_int, _P, c.POINTER(c.c_float), _P]
     lib.dock_sweep_ms_history.argtypes = [_P, c.c_int, c.POINTER(c.c_float)]
     lib.dock_sweep_ms_history.restype = c.c_int
     lib.dock_last_sweep_work.argtypes = [_P, c.POINTER(c.c_uint64), c.POINTER(c.c_uint64)]
@@ -366,6 +368,16 @@ def dock_probe_gather(buf, out, log2_floats: int, blocks: int, iters: int, strea
     st = None if stream is None else ctypes.c_void_p(stream.cuda_stream)
     _check(load_library().dock_probe_gather(_tptr(buf), int(log2_floats), int(blocks), int(iters),
                                             _tptr(out), ctypes.byref(ms), st), "dock_probe_gather")
+    return float(ms.value)
+
+
+def dock_probe_valu(out, kind: int, blocks: int, iters: int, stream=None) -> float:
+    """VALU issue probe (kind 0: FP32 FMA chains; 1: the sweep's evaluation
+    mix); out: device tensor of blocks * 256 floats.  Returns the kernel's ms."""
+    ms = ctypes.c_float()
+    st = None if stream is None else ctypes.c_void_p(stream.cuda_stream)
+    _check(load_library().dock_probe_valu(int(kind), int(blocks), int(iters), _tptr(out),
+                                          ctypes.byref(ms), st), "dock_probe_valu")
     return float(ms.value)
 
 
