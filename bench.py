@@ -561,21 +561,22 @@ def plain_leg(cfg, steps, warmup, bump="pruned", waves=0, claim=16, autotune=0, 
     return res, ctx
 
 
-def oracle_check(ctx, gpu_best, budget_s=10.0):
+def oracle_check(ctx, gpu_best, budget_s=16.0):
     """Per-ligand best-score error of GPU runs against the FP64 reference on
     the first ligands of the batch (as many as fit the time budget)."""
     import oracle
     from paper_1901_06229_amd import synth
     threads = min(16, cpu_info()["allowed"] or 1)
     ligs = ctx["ligs"]
-    n, ref, t_used = 1, None, 0.0
+    # one ligand per thread at the least (the reference runs one thread per ligand)
+    n, ref, t_used = min(threads, ligs.n_ligands), None, 0.0
     while True:
         sub = ligs.subset(range(n))
         t0 = time.perf_counter()
         ref = oracle.dock_batch(ctx["pocket"], sub, ctx["orient"], ctx["S"], r_bump=synth.R_BUMP,
                                 n_threads=threads).best_score
         t_used = time.perf_counter() - t0
-        if t_used >= budget_s / 2 or n * 2 > ligs.n_ligands or n >= threads:
+        if t_used >= budget_s / 2 or n * 2 > ligs.n_ligands:
             break
         n *= 2
     out = {"ligands": n, "seconds": round(t_used, 1)}
