@@ -353,9 +353,12 @@ int dock_get_launch(dock_pocket *p, int *waves_per_block, int *blocks_per_cu,
  * Each size class is a contiguous range of the cost-sorted order, docked by
  * its own persistent kernel.  0 disables a class; atoms16 <= 64,
  * atoms32 <= 128 and atoms32 > atoms16 unless 0 (DOCK_E_LIMIT /
- * DOCK_E_INVAL).  Applies to plain pruned sweeps in cost order (not with
- * DOCK_FLAG_NO_LPT or DOCK_FLAG_DIRECT_BUMP, nor learned mode).  Results are
- * bitwise identical under every mapping.  A new handle starts at (48, 96). */
+ * DOCK_E_INVAL).  Applies to plain pruned sweeps in cost order with at most
+ * DOCK_GROUP_MAX_STEPS angle steps (not with DOCK_FLAG_NO_LPT or
+ * DOCK_FLAG_DIRECT_BUMP, nor learned mode; above that step count scoring
+ * dominates a rotamer step and one item per wave scores it faster).  Results
+ * are bitwise identical under every mapping.  A new handle starts at (48, 96). */
+#define DOCK_GROUP_MAX_STEPS 2048
 int dock_set_group_mapping(dock_pocket *p, int atoms16, int atoms32);
 int dock_get_group_mapping(dock_pocket *p, int *atoms16, int *atoms32);
 

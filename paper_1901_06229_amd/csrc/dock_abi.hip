@@ -381,7 +381,8 @@ int enqueue_batch(dock_pocket *p, const dock_ligands *ligs, const float *orient,
   bool lpt = !(prm->flags & DOCK_FLAG_NO_LPT) && !learned;
   // size classes for the grouped mappings: plain pruned sweeps in LPT order
   LaunchPlan plan = p->plan;
-  if (!lpt || emit_x || (prm->flags & DOCK_FLAG_DIRECT_BUMP)) plan.group16_atoms = plan.group32_atoms = 0;
+  if (!lpt || emit_x || (prm->flags & DOCK_FLAG_DIRECT_BUMP) || S > DOCK_GROUP_MAX_STEPS)
+    plan.group16_atoms = plan.group32_atoms = 0;
   const int c16 = min(plan.group16_atoms, max_atoms);
   const int c32 = max(c16, min(plan.group32_atoms, max_atoms));
   hipError_t e = enqueue_prepare(A, max_atoms, learned ? max_rot : DOCK_MAX_ROT, lpt, c16, c32,

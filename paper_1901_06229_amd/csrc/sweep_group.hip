@@ -18,17 +18,22 @@
 // final scores use the mapping-independent chunked atom sum.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "dock_internal.h"
 #include "sweep_common.h"
 #include "rotamer_step.h"
 
 namespace dock {
 
-// Scratch sizes of one group (entries): kept-pair list, compacted steps of a
-// chunk of steps (also the chunk length).
+// Scratch sizes of one group (entries): kept-pair list, ring of compacted
+// steps; steps compacted per append (the chunk).
 template <int G> constexpr int kGroupPairCap = 4 * G;
-template <int G> constexpr int kGroupChunk = 4 * G;
-constexpr int kGroupScoreTiles = 2;  // compacted G-step tiles scored per pass
+template <int G> constexpr int kGroupRing = 4 * G;
+template <int G> constexpr int kGroupChunk = 2 * G;
+constexpr int kGroupScoreTiles = 2;  // compacted G-step tiles scored per full pass
+static_assert(kGroupChunk<16> + kGroupScoreTiles * 16 <= kGroupRing<16>, "ring too small");
+static_assert(kGroupChunk<32> + kGroupScoreTiles * 32 <= kGroupRing<32>, "ring too small");
 
 __host__ __device__ inline int round16(int b) { return (b + 15) / 16 * 16; }
 
@@ -43,15 +48,15 @@ __host__ __device__ inline int round16(int b) { return (b + 15) / 16 * 16; }
 //           of the moving atoms (in list order), then of the static ones
 //           scratch: kept pairs (int [4G]) during the bump test, then the
 //                    moving atoms' voxel-unit bases (float [9][G]) and the
-//                    compacted steps of a chunk (int16 [4G])
+//                    ring of compacted steps (int16 [4G])
 //           BM (uint32 [(S + 31) / 32]) bump bits
 template <int G>
 __host__ __device__ inline int group_shared_bytes(int nmax) { return round16(nmax * 6); }
 template <int G>
 __host__ __device__ constexpr int group_scratch_bytes() {
-  return (((kGroupPairCap<G> * 4 > 9 * G * 4 + kGroupChunk<G> * 2)
+  return (((kGroupPairCap<G> * 4 > 9 * G * 4 + kGroupRing<G> * 2)
                ? kGroupPairCap<G> * 4
-               : 9 * G * 4 + kGroupChunk<G> * 2) + 15) / 16 * 16;
+               : 9 * G * 4 + kGroupRing<G> * 2) + 15) / 16 * 16;
 }
 // the scratch also holds the moving atoms' values (m < class atoms) for s0
 static_assert(group_scratch_bytes<16>() >= 4 * kGroupMaxAtoms16, "scratch too small");
@@ -345,42 +350,56 @@ __global__ void __launch_bounds__(WAVES *kWave)
         }
         flush();
 
-        // non-bumping steps, compacted per chunk and scored
+        // non-bumping steps: compacted 2G steps at a time into a ring of 4G
+        // entries per group and scored in passes of kGroupScoreTiles x G
+        // entries as soon as one group has that many unread, so passes stay
+        // full across chunks; what is left at the end (< 2G entries) takes
+        // one pass of one or two tiles.  Passes run wave-wide; each group
+        // reads its own next entries.  Unread entries stay below 2G after a
+        // pass and below 4G after an append, so the ring never overwrites them.
         uint64_t best = 0ull;
+        int nv = 0;       // entries this group has appended (same in its lanes)
+        int rd = 0;       // entries this group has scored
+        int most = 0;     // the wave's largest unread count
+        auto pass = [&](auto tiles) {
+          constexpr int TC = decltype(tiles)::value;
+          float cc[TC], ss[TC], score[TC];
+          int kk[TC];
+#pragma unroll
+          for (int t = 0; t < TC; ++t) {
+            const int jj = rd + t * G + g.gl;
+            kk[t] = jj < nv ? W.CK[jj & (kGroupRing<G> - 1)] : -1;
+            const float2 cs = A.cs[kk[t] > 0 ? kk[t] : 0];
+            cc[t] = cs.x;
+            ss[t] = cs.y;
+          }
+          group_scores<G, TC>(W, g, m, cst, xa, u, GV, GS, grsrc, cc, ss, score);
+#pragma unroll
+          for (int t = 0; t < TC; ++t) {
+            if (kk[t] == 0) score[t] = s0;
+            const uint64_t key = kk[t] >= 0 ? best_key(score[t], (uint32_t)kk[t]) : 0ull;
+            best = key > best ? key : best;
+          }
+          rd = min(nv, rd + TC * G);
+        };
         for (int c0 = 0; c0 < S; c0 += kGroupChunk<G>) {
-          int nv = 0;
+          const int nv0 = nv;
 #pragma unroll
           for (int w = 0; w < kGroupChunk<G> / G; ++w) {
             const int k = c0 + w * G + g.gl;
             const bool valid = k < S && ((W.BM[k >> 5] >> (k & 31)) & 1u) == 0u;
             const uint32_t gb = g.bits(wave_ballot(valid));
-            if (valid) W.CK[nv + __popc(gb & g.below)] = (int16_t)k;
+            if (valid) W.CK[(nv + __popc(gb & g.below)) & (kGroupRing<G> - 1)] = (int16_t)k;
             nv += __popc(gb);
           }
           wave_lds_sync();
-          if (active) evals += (uint64_t)m * (uint64_t)nv;
-          const int most = (int)__builtin_amdgcn_readfirstlane((int)wave_max_u32((uint32_t)nv));
-          for (int p0 = 0; p0 < most; p0 += kGroupScoreTiles * G) {
-            float cc[kGroupScoreTiles], ss[kGroupScoreTiles], score[kGroupScoreTiles];
-            int kk[kGroupScoreTiles];
-#pragma unroll
-            for (int t = 0; t < kGroupScoreTiles; ++t) {
-              const int jj = p0 + t * G + g.gl;
-              kk[t] = jj < nv ? W.CK[jj] : -1;
-              const float2 cs = A.cs[kk[t] > 0 ? kk[t] : 0];
-              cc[t] = cs.x;
-              ss[t] = cs.y;
-            }
-            group_scores<G, kGroupScoreTiles>(W, g, m, cst, xa, u, GV, GS, grsrc, cc, ss, score);
-#pragma unroll
-            for (int t = 0; t < kGroupScoreTiles; ++t) {
-              if (kk[t] == 0) score[t] = s0;
-              const uint64_t key = kk[t] >= 0 ? best_key(score[t], (uint32_t)kk[t]) : 0ull;
-              best = key > best ? key : best;
-            }
-          }
-          wave_lds_sync();
+          if (active) evals += (uint64_t)m * (uint64_t)(nv - nv0);
+          most = (int)__builtin_amdgcn_readfirstlane((int)wave_max_u32((uint32_t)(nv - rd)));
+          if (most >= kGroupScoreTiles * G) pass(std::integral_constant<int, kGroupScoreTiles>{});
         }
+        most = (int)__builtin_amdgcn_readfirstlane((int)wave_max_u32((uint32_t)(nv - rd)));
+        if (most > G) pass(std::integral_constant<int, kGroupScoreTiles>{});
+        else if (most > 0) pass(std::integral_constant<int, 1>{});
         best = group_max_u64<G>(best);
         const int kb = best ? (int)key_index(best) : -1;
         if (g.gl == (step & (G - 1))) kreg = kb;

@@ -22,6 +22,7 @@ DOCK_FLAG_DIRECT_BUMP = 4
 DOCK_FLAG_GRAPH = 8
 DOCK_MAX_ATOMS, DOCK_MAX_ROT, DOCK_MAX_STEPS = 256, 255, 4096
 DOCK_STATIC_SCRATCH_BYTES = 64 << 20
+DOCK_GROUP_MAX_STEPS = 2048
 
 _P = ctypes.c_void_p
 

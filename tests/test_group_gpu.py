@@ -55,10 +55,11 @@ def test_grouped_results_are_bitwise_the_single_item_ones(pockets):
         _same(_run(h, ligs, orient, 128, mp), ref, mp)
 
 
-@pytest.mark.parametrize("S", [1, 7, 16, 17, 33, 127, 128, 129, 255, 257, 360])
+@pytest.mark.parametrize("S", [1, 7, 16, 17, 33, 127, 128, 129, 255, 257, 360, 2048])
 def test_grouped_step_counts(pockets, S):
-    """Step counts around the 16- and 32-step tiles, the 128- and 256-step
-    compaction chunks and the 32-bit mask words."""
+    """Step counts around the 16- and 32-step tiles, the 32- and 64-step
+    compaction chunks, the rings of 64 and 128 compacted steps, the 32-bit
+    mask words and the largest step count the grouped mapping takes."""
     p, h = pockets(2)
     ligs = synth.ligands(2, count=24, first=900)
     orient = synth.orientations(2, 9)
