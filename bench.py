@@ -32,9 +32,11 @@ METRIC = "ligands/sec on 1 MI355X (plain vs learned proposal at ≤0.5% score lo
 
 # MI355X FP32 vector rate: 256 CUs x 128 lanes x 2.4 GHz = 78.6 T lane-ops/s
 # (the 157.3 TFLOP/s spec figure, an FMA counted as one lane-op instead of two
-# flops).  Plain FP32 FMA/add chains reach about 51-55 T on the part under
-# load; clamp, conversion and integer multiply-add about 34-36 T.
+# flops).  That rate needs packed FP32 instructions, which this library does
+# not use; the VALU probe measures what plain FP32 sustains (about 37 T).
 VALU_PEAK_TOPS = 256 * 128 * 2.4e9 / 1e12
+# dense BF16 matrix-core rate (published, no sparsity)
+MFMA_BF16_PEAK = 2.5e15
 # Lane-operation counts (VALU instructions per lane) of the sweep's units,
 # taken from the loop bodies of the compiled gfx950 kernels:
 #   direct kernel, per angle: 8 per cross pair (3 sub, mul, 2 fma, cmp, or),
@@ -296,10 +298,61 @@ def learned_comparison(n_eval=10_000, n_val=2_000, n_train=156_250, epochs=10, t
     res = compare(256)
     if fine_steps:
         res["fine_steps"] = compare(fine_steps)
+    res["bound"] = learned_bound(h, batches["eval"], n_eval, net, stream,
+                                 (256,) + ((fine_steps,) if fine_steps else ()))
     h.close()
     res["training"] = {k: v for k, v in hist.items() if k not in ("train_loss", "val_loss")} | {
         "final_val_mse": hist.get("val_loss", [None])[-1], "seconds": round(t_train, 2)}
     return res, net
+
+
+def learned_bound(h, batch, n_eval, net, stream, steps_list, proposals=16, reps=10):
+    """Inputs of the speed bound on any learned proposal for the evaluation
+    batch: the plain sweep at each step count and at `proposals` steps (a
+    rotamer step that tests and scores only that many angles), and the MLP
+    over every item once per rotamer step, measured and at the MFMA peak."""
+    import torch
+    from paper_1901_06229_amd import dock
+    ligs, d, od, out = batch
+    n_rot = int(np.diff(ligs.rot_offset).max())
+    rows = n_eval * od.shape[0]
+
+    def sweep_ms(S):
+        ws = torch.empty(dock.dock_workspace_size(ligs.n_ligands, d["total_rot"], 8, S),
+                         dtype=torch.uint8, device="cuda")
+        prm = dock.make_params(max_atoms=32, max_rot=4, flags=dock.DOCK_FLAG_TIME_SWEEP)
+        ms = []
+        for i in range(reps + 2):
+            dock.dock_batch_async(h, d, od, S, out, prm, workspace=ws, stream=stream)
+            stream.synchronize()
+            if i >= 2:
+                ms.append(dock.dock_last_sweep_ms(h))
+        return float(np.median(ms))
+
+    x = torch.zeros(rows, 64, dtype=torch.bfloat16, device="cuda")
+    y = torch.empty(rows, 256, dtype=torch.float32, device="cuda")
+    for _ in range(3):
+        net.forward(x, y, stream=stream)
+    stream.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        net.forward(x, y, stream=stream)
+    stream.synchronize()
+    mlp_ms = (time.perf_counter() - t0) / reps * 1e3 * n_rot
+    mlp_flop = 2.0 * rows * n_rot * (64 * 256 + 3 * 256 * 256)
+    mlp_peak_ms = mlp_flop / MFMA_BF16_PEAK * 1e3
+    small = sweep_ms(proposals)
+    res = {"note": f"sweep ms (HIP events, median of {reps}) on the evaluation batch; a learned call needs "
+                   f"the MLP on every item at each of {n_rot} rotamer steps plus at least a rotamer step "
+                   f"that tests and scores {proposals} angles",
+           f"plain_sweep_ms_{proposals}_steps": round(small, 4),
+           "mlp_ms_measured": round(mlp_ms, 4), "mlp_ms_at_peak": round(mlp_peak_ms, 4)}
+    for S in steps_list:
+        full = sweep_ms(S)
+        res[f"S{S}"] = {"plain_sweep_ms": round(full, 4),
+                        "bound_no_fallback_measured_mlp": round(full / (small + mlp_ms), 3),
+                        "bound_no_fallback_peak_mlp": round(full / (small + mlp_peak_ms), 3)}
+    return res
 
 
 def learned_side_by_side(h, ligs, orient, d, orient_d, S, out, stream, steps, warmup, max_atoms,

@@ -64,79 +64,201 @@ __device__ __forceinline__ float gelu_grad_f(float z) {
          z * __expf(-0.5f * z * z) * 0.39894228040143268f;
 }
 
-constexpr int kTile = 64;  // output tile edge
-constexpr int kKs = 32;    // K step staged in LDS
+constexpr int kTile = 64;   // output tile edge
+constexpr int kKc = 256;    // K staged in LDS at once (the whole K of every product but the
+                            // weight gradients of large batches)
+// A staged panel row holds k in 16-byte chunks of 8; chunk j of row r is
+// stored at chunk j ^ ((r / 8) mod 8), so the rows 8 apart that one wave
+// writes in a transposing stage (and the 32 rows an operand read spans) fall
+// on different LDS banks, while each 8-value operand stays contiguous.
+__device__ __forceinline__ int swz(int r, int k) { return (((k >> 3) ^ ((r >> 3) & 7)) << 3) | (k & 7); }
+
+// A 64 x kc panel ([row][k], k contiguous) staged into LDS in two steps, so
+// that both operands' loads are in flight before either is written: every
+// thread loads up to 8 16-byte chunks, then writes them.  T: the source is
+// stored [k][row] (64 contiguous rows per k), else [row][k] with kc a power
+// of two.  Loads are unconditional (a thread past the panel re-reads its
+// last chunk); only the LDS writes are predicated.
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+struct Panel {
+  u32x4 v[8];
+};
+
+template <bool T>
+__device__ __forceinline__ void load_panel(Panel &p, const uint16_t *src, int ld, int r0, int k0,
+                                           int kc, int tid) {
+  const int nch = 8 * kc;
+  const int lg = __builtin_ctz((unsigned)kc) - 3, per = 1 << lg;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const int e = min(tid + 256 * i, nch - 1);
+    if (!T) {
+      const int r = e >> lg, c = (e & (per - 1)) * 8;
+      p.v[i] = *(const u32x4 *)(src + (size_t)(r0 + r) * ld + k0 + c);
+    } else {
+      const int kr = e >> 3, c = (e & 7) * 8;
+      p.v[i] = *(const u32x4 *)(src + (size_t)(k0 + kr) * ld + r0 + c);
+    }
+  }
+}
+
+template <bool T>
+__device__ __forceinline__ void store_panel(const Panel &p, uint16_t (*s)[kKc], int kc,
+                                            int tid) {
+  const int nch = 8 * kc;
+  const int lg = __builtin_ctz((unsigned)kc) - 3, per = 1 << lg;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const int e = tid + 256 * i;
+    if (e < nch) {
+      if (!T) {
+        const int r = e >> lg, c = (e & (per - 1)) * 8;
+        *(u32x4 *)&s[r][swz(r, c)] = p.v[i];
+      } else {
+        const int kr = e >> 3, c = (e & 7) * 8;
+        const uint16_t *h = (const uint16_t *)&p.v[i];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) s[c + q][swz(c + q, kr)] = h[q];
+      }
+    }
+  }
+}
 
 // C[m][n] = sum_k opA[m][k] * opB[k][n]
 //   opA[m][k] = TA ? A[k * lda + m] : A[m * lda + k]
 //   opB[k][n] = TB ? B[n * ldb + k] : B[k * ldb + n]
-// K range [k0, k1) (split-K); M, N, K multiples of 64 / 64 / 32.
+// One 64 x 64 output tile (column tile bx, row tile by) over the K range
+// of split bz, staged 256 at a time; M, N multiples of 64, the K of a split
+// a multiple of 16.  tile_id numbers the tile for the per-tile loss.
+struct GemmLds {
+  uint16_t sA[kTile][kKc];  // [m][k], swizzled
+  uint16_t sB[kTile][kKc];  // [n][k], swizzled
+  float sRed[256];
+};
+
 template <bool TA, bool TB, int EPI>
-__global__ void __launch_bounds__(256) gemm_bf16_kernel(GemmArgs g) {
-  __shared__ __attribute__((aligned(16))) uint16_t sA[kTile][kKs + 8];  // [m][k]
-  __shared__ __attribute__((aligned(16))) uint16_t sB[kTile][kKs + 8];  // [n][k]
+__device__ __forceinline__ void gemm_tile(const GemmArgs &g, GemmLds &L, int bx, int by, int bz,
+                                          int tile_id) {
+  auto &sA = L.sA;
+  auto &sB = L.sB;
+  float *sRed = L.sRed;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6;
-  const int m0 = blockIdx.y * kTile, n0 = blockIdx.x * kTile;
-  const int split = blockIdx.z;
+  const int m0 = by * kTile, n0 = bx * kTile;
+  const int split = bz;
   const int kb = g.k_per_split * split, ke = kb + g.k_per_split;
   const int wm = (wv >> 1) * 32, wn = (wv & 1) * 32;
+  // weight gradients: the first column of blocks also sums its rows of opA
+  // (the bias gradient), thread t over k = t mod 4 of row t / 4
+  const bool bias_sum = EPI == kEpiWgrad && bx == 0;
   f32x16 acc;
 #pragma unroll
   for (int j = 0; j < 16; ++j) acc[j] = 0.0f;
+  float bsum = 0.0f;
 
-  for (int k0 = kb; k0 < ke; k0 += kKs) {
-    // stage A tile: 64 x 32
-    if (!TA) {  // rows of 32 contiguous k: thread -> (row, 8-wide chunk)
-      const int r = tid >> 2, c = (tid & 3) * 8;
-      const uint4 v = *(const uint4 *)(g.A + (size_t)(m0 + r) * g.lda + k0 + c);
-      *(uint4 *)&sA[r][c] = v;
-    } else {  // storage [k][m]: 32 rows of 64 contiguous m
-      const int kr = tid >> 3, c = (tid & 7) * 8;
-      const uint4 v = *(const uint4 *)(g.A + (size_t)(k0 + kr) * g.lda + m0 + c);
-      const uint16_t *e = (const uint16_t *)&v;
+  for (int k0 = kb; k0 < ke; k0 += kKc) {
+    const int kc = min(kKc, ke - k0);
+    {
+      Panel pa, pb;
+      load_panel<TA>(pa, g.A, g.lda, m0, k0, kc, tid);
+      load_panel<!TB>(pb, g.B, g.ldb, n0, k0, kc, tid);
+      // keep the loads here (not sunk next to their predicated writes), so
+      // all of them are in flight together
 #pragma unroll
-      for (int q = 0; q < 8; ++q) sA[c + q][kr] = e[q];
-    }
-    if (TB) {  // storage [n][k]
-      const int r = tid >> 2, c = (tid & 3) * 8;
-      const uint4 v = *(const uint4 *)(g.B + (size_t)(n0 + r) * g.ldb + k0 + c);
-      *(uint4 *)&sB[r][c] = v;
-    } else {  // storage [k][n]
-      const int kr = tid >> 3, c = (tid & 7) * 8;
-      const uint4 v = *(const uint4 *)(g.B + (size_t)(k0 + kr) * g.ldb + n0 + c);
-      const uint16_t *e = (const uint16_t *)&v;
-#pragma unroll
-      for (int q = 0; q < 8; ++q) sB[c + q][kr] = e[q];
+      for (int i = 0; i < 8; ++i) asm volatile("" ::"v"(pa.v[i]), "v"(pb.v[i]));
+      store_panel<TA>(pa, sA, kc, tid);
+      store_panel<!TB>(pb, sB, kc, tid);
     }
     __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < kKs; kk += 16) {
+#pragma unroll 4
+    for (int kk = 0; kk < kc; kk += 16) {
       const int koff = kk + (lane >> 5) * 8;
-      const bf16x8 a = *(const bf16x8 *)&sA[wm + (lane & 31)][koff];
-      const bf16x8 b = *(const bf16x8 *)&sB[wn + (lane & 31)][koff];
+      const int ra = wm + (lane & 31), rb = wn + (lane & 31);
+      const bf16x8 a = *(const bf16x8 *)&sA[ra][swz(ra, koff)];
+      const bf16x8 b = *(const bf16x8 *)&sB[rb][swz(rb, koff)];
       acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
     }
+    if (bias_sum)
+      for (int k = tid & 3; k < kc; k += 4) bsum += bf2f(sA[tid >> 2][swz(tid >> 2, k)]);
     __syncthreads();
   }
 
+  float *dst = g.Cf + (EPI == kEpiWgrad ? (size_t)split * g.split_stride : 0);
+  if (bias_sum) {
+    // bias gradient (stored after the weight matrix): the four partial sums
+    // of a row added in order
+    sRed[tid] = bsum;
+    __syncthreads();
+    if (tid < kTile) {
+      const float *q = sRed + 4 * tid;
+      dst[(size_t)256 * g.ldc + m0 + tid] = ((q[0] + q[1]) + q[2]) + q[3];
+    }
+  }
   const int col = n0 + wn + (lane & 31);
+  float l2 = 0.0f;
+  // operands of the epilogue loaded up front (the targets share their type
+  // with the BF16 output, so the compiler would not move their loads ahead
+  // of the stores)
+  float ep[16];
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    const int row = m0 + wm + (j >> 2) * 8 + (lane >> 5) * 4 + (j & 3);
+    const size_t at = (size_t)row * g.ldc + col;
+    if (EPI == kEpiBiasMse) ep[j] = bf2f(g.target[at]);
+    if (EPI == kEpiGeluGrad) ep[j] = g.aux[at];
+  }
 #pragma unroll
   for (int j = 0; j < 16; ++j) {
     const int row = m0 + wm + (j >> 2) * 8 + (lane >> 5) * 4 + (j & 3);
     const size_t at = (size_t)row * g.ldc + col;
     float v = acc[j];
-    if (EPI == kEpiStore) {
-      g.Cf[(size_t)split * g.split_stride + at] = v;
+    if (EPI == kEpiWgrad) {
+      dst[at] = v;
     } else if (EPI == kEpiBiasGelu) {
       v += g.bias[col];
       g.Cf[at] = v;                    // pre-activation, kept for the backward pass
       g.Cb[at] = f2bf(gelu_f(v));      // activation, BF16
-    } else if (EPI == kEpiBias) {
-      g.Cf[at] = v + g.bias[col];
+    } else if (EPI == kEpiBiasMse) {   // dZ = bf16(2 (Y - T) scale), Y = output + bias
+      const float d = (v + g.bias[col]) - ep[j];
+      g.Cb[at] = f2bf(2.0f * d * g.scale);
+      l2 += d * d;
     } else if (EPI == kEpiGeluGrad) {  // dZ_prev = bf16(dA * gelu'(Z_prev))
-      g.Cb[at] = f2bf(v * gelu_grad_f(g.aux[at]));
+      g.Cb[at] = f2bf(v * gelu_grad_f(ep[j]));
     }
+  }
+  if (EPI == kEpiBiasMse) {
+    // squared error of the tile: fixed-order tree over the block
+    sRed[tid] = l2;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if (tid < w) sRed[tid] += sRed[tid + w];
+      __syncthreads();
+    }
+    if (tid == 0) g.block_loss[tile_id] = sRed[0];
+  }
+}
+
+template <bool TA, bool TB, int EPI>
+__global__ void __launch_bounds__(256) gemm_bf16_kernel(GemmArgs g) {
+  __shared__ __attribute__((aligned(16))) GemmLds L;
+  gemm_tile<TA, TB, EPI>(g, L, blockIdx.x, blockIdx.y, blockIdx.z,
+                         blockIdx.y * gridDim.x + blockIdx.x);
+}
+
+// One backward step of a layer in one launch: the first w_tiles blocks are
+// the weight / bias gradient tiles (w: wx column tiles x 4 row tiles x
+// splits), the rest the tiles of dZ of the layer below (d: dx column tiles
+// per 64 rows).  Both read the layer's dZ only.
+__global__ void __launch_bounds__(256) backward_kernel(GemmArgs w, GemmArgs d, int wx, int splits,
+                                                       int dx) {
+  __shared__ __attribute__((aligned(16))) GemmLds L;
+  const int b = blockIdx.x, w_tiles = wx * 4 * splits;
+  if (b < w_tiles) {
+    const int bz = b / (wx * 4), r = b - bz * wx * 4;
+    gemm_tile<true, false, kEpiWgrad>(w, L, r % wx, r / wx, bz, 0);
+  } else {
+    const int t = b - w_tiles;
+    gemm_tile<false, false, kEpiGeluGrad>(d, L, t % dx, t / dx, 0, 0);
   }
 }
 
@@ -149,16 +271,26 @@ static hipError_t gemm_t(const GemmArgs &g, int M, int N, int splits, hipStream_
 
 hipError_t gemm_bf16(const GemmArgs &g, bool ta, bool tb, int epi, int M, int N, int splits,
                      hipStream_t st) {
-  if (M % kTile || N % kTile || g.k_per_split % kKs || splits < 1) return hipErrorInvalidValue;
+  if (M % kTile || N % kTile || g.k_per_split % 16 || g.k_per_split < 16 || splits < 1)
+    return hipErrorInvalidValue;
 #define DOCK_GEMM(TA, TB, E) \
   if (ta == TA && tb == TB && epi == E) return gemm_t<TA, TB, E>(g, M, N, splits, st);
   DOCK_GEMM(false, true, kEpiBiasGelu)
-  DOCK_GEMM(false, true, kEpiBias)
-  DOCK_GEMM(false, true, kEpiStore)
-  DOCK_GEMM(false, false, kEpiGeluGrad)
-  DOCK_GEMM(true, false, kEpiStore)
+  DOCK_GEMM(false, true, kEpiBiasMse)
 #undef DOCK_GEMM
   return hipErrorInvalidValue;
+}
+
+hipError_t backward_layer(const GemmArgs &w, int in, int splits, const GemmArgs *d, int M,
+                          hipStream_t st) {
+  if (in % kTile || w.k_per_split % 16 || w.k_per_split < 16 || splits < 1 ||
+      (d && (M % kTile || d->k_per_split % 16 || d->k_per_split < 16)))
+    return hipErrorInvalidValue;
+  const int wx = in / kTile, dx = in / kTile;
+  const int blocks = wx * 4 * splits + (d ? dx * (M / kTile) : 0);
+  hipLaunchKernelGGL(backward_kernel, dim3((unsigned)blocks), dim3(256), 0, st, w,
+                     d ? *d : GemmArgs{}, wx, splits, dx);
+  return hipGetLastError();
 }
 
 // ---------------------------------------------------------------- fused inference
@@ -281,27 +413,6 @@ __global__ void f32_to_bf16_kernel(const float *x, uint16_t *y, int64_t n) {
   if (i < n) y[i] = f2bf(x[i]);
 }
 
-// dZ_out = bf16(2 (Y - T) / (M N)); loss partial sums per block (deterministic
-// second pass sums the blocks in order).
-__global__ void mse_grad_kernel(const float *Y, const uint16_t *T, int64_t n, float scale,
-                                uint16_t *dZ, float *block_loss) {
-  __shared__ float red[256];
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  float l = 0.0f;
-  if (i < n) {
-    const float d = Y[i] - bf2f(T[i]);
-    dZ[i] = f2bf(2.0f * d * scale);
-    l = d * d;
-  }
-  red[threadIdx.x] = l;
-  __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) block_loss[blockIdx.x] = red[0];
-}
-
 // One block: strided per-thread sums, then a tree (fixed order).
 __global__ void sum_blocks_kernel(const float *part, int n, float scale, float *out) {
   __shared__ float red[256];
@@ -316,19 +427,9 @@ __global__ void sum_blocks_kernel(const float *part, int n, float scale, float *
   if (threadIdx.x == 0) *out = red[0] * scale;
 }
 
-// Column sums of a BF16 [M][N] matrix over a chunk of 64 rows per block
-// (bias gradients); the chunks are then summed in order.
-__global__ void colsum_bf16_kernel(const uint16_t *dZ, int M, int N, float *part) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  const int r0 = blockIdx.y * 64;
-  if (c >= N) return;
-  float s = 0.0f;
-  for (int r = r0; r < r0 + 64 && r < M; ++r) s += bf2f(dZ[(size_t)r * N + c]);
-  part[(size_t)blockIdx.y * N + c] = s;
-}
-
-// Sum of split-K partial products, fixed order.
-__global__ void reduce_splits_kernel(const float *part, int splits, int64_t n, float *out) {
+// Gradient = sum of the split-K partial gradients (each a whole parameter
+// vector), in split order.
+__global__ void reduce_grads_kernel(const float *part, int splits, int64_t n, float *out) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   float s = 0.0f;
@@ -359,29 +460,16 @@ hipError_t launch_f32_to_bf16(const float *x, uint16_t *y, int64_t n, hipStream_
   return hipGetLastError();
 }
 
-hipError_t launch_mse_grad(const float *Y, const uint16_t *T, int64_t n, float scale,
-                           uint16_t *dZ, float *block_loss, float *loss_out, hipStream_t st) {
-  const unsigned nb = (unsigned)((n + 255) / 256);
-  hipLaunchKernelGGL(mse_grad_kernel, dim3(nb), dim3(256), 0, st, Y, T, n, scale, dZ,
-                     block_loss);
-  hipLaunchKernelGGL(sum_blocks_kernel, dim3(1), dim3(256), 0, st, block_loss, (int)nb, scale,
+hipError_t launch_sum_blocks(const float *block_loss, int n, float scale, float *loss_out,
+                             hipStream_t st) {
+  hipLaunchKernelGGL(sum_blocks_kernel, dim3(1), dim3(256), 0, st, block_loss, n, scale,
                      loss_out);
   return hipGetLastError();
 }
 
-hipError_t launch_colsum(const uint16_t *dZ, int M, int N, float *part, float *out,
-                         hipStream_t st) {
-  const int chunks = (M + 63) / 64;
-  hipLaunchKernelGGL(colsum_bf16_kernel, dim3((N + 255) / 256, chunks), dim3(256), 0, st, dZ, M,
-                     N, part);
-  hipLaunchKernelGGL(reduce_splits_kernel, dim3((N + 255) / 256), dim3(256), 0, st, part,
-                     chunks, (int64_t)N, out);
-  return hipGetLastError();
-}
-
-hipError_t launch_reduce_splits(const float *part, int splits, int64_t n, float *out,
-                                hipStream_t st) {
-  hipLaunchKernelGGL(reduce_splits_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
+hipError_t launch_reduce_grads(const float *part, int splits, int64_t n, float *out,
+                               hipStream_t st) {
+  hipLaunchKernelGGL(reduce_grads_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
                      part, splits, n, out);
   return hipGetLastError();
 }

@@ -28,9 +28,9 @@ struct dock_mlp {
   uint16_t *wb = nullptr;                                         // BF16 copy
   // activations for up to `rows` rows
   int rows = 0;
-  float *z1 = nullptr, *z2 = nullptr, *z3 = nullptr, *y = nullptr;
+  float *z1 = nullptr, *z2 = nullptr, *z3 = nullptr;
   uint16_t *a1 = nullptr, *a2 = nullptr, *a3 = nullptr, *dz0 = nullptr, *dz1 = nullptr;
-  float *part = nullptr;  // split-K partials
+  float *part = nullptr;  // split-K partial gradients [kMaxGradSplits][kMlpParams]
   float *block_loss = nullptr, *loss = nullptr;
   float *h_loss = nullptr;  // pinned
   std::mutex mu;
@@ -38,14 +38,16 @@ struct dock_mlp {
 
 namespace {
 
+constexpr int kMaxGradSplits = 64;
+
 hipError_t alloc(void **p, size_t bytes) { return hipMalloc(p, bytes < 256 ? 256 : bytes); }
 
 void free_rows(dock_mlp *n) {
-  for (void *p : {(void *)n->z1, (void *)n->z2, (void *)n->z3, (void *)n->y, (void *)n->a1,
+  for (void *p : {(void *)n->z1, (void *)n->z2, (void *)n->z3, (void *)n->a1,
                   (void *)n->a2, (void *)n->a3, (void *)n->dz0, (void *)n->dz1,
                   (void *)n->part, (void *)n->block_loss})
     if (p) (void)hipFree(p);
-  n->z1 = n->z2 = n->z3 = n->y = nullptr;
+  n->z1 = n->z2 = n->z3 = nullptr;
   n->a1 = n->a2 = n->a3 = n->dz0 = n->dz1 = nullptr;
   n->part = n->block_loss = nullptr;
   n->rows = 0;
@@ -62,14 +64,13 @@ int ensure_rows(dock_mlp *n, int M) {
   A((void **)&n->z1, f);
   A((void **)&n->z2, f);
   A((void **)&n->z3, f);
-  A((void **)&n->y, f);
   A((void **)&n->a1, h);
   A((void **)&n->a2, h);
   A((void **)&n->a3, h);
   A((void **)&n->dz0, h);
   A((void **)&n->dz1, h);
-  A((void **)&n->part, sizeof(float) * 64 * 256 * 256);
-  A((void **)&n->block_loss, sizeof(float) * ((size_t)M * 256 / 256 + 1));
+  A((void **)&n->part, sizeof(float) * kMaxGradSplits * kMlpParams);
+  A((void **)&n->block_loss, sizeof(float) * ((size_t)M / 16 + 1));
   if (e != hipSuccess) {
     free_rows(n);
     return abi_fail(DOCK_E_NOMEM, "MLP activation buffers for %d rows: %s", M,
@@ -79,58 +80,54 @@ int ensure_rows(dock_mlp *n, int M) {
   return DOCK_OK;
 }
 
-// Weight gradient dW[out][in] = dZ^T[out][M] . A[M][in], split over M.
-hipError_t weight_grad(const uint16_t *dZ, const uint16_t *A, int M, int in, float *part,
-                       float *dW, hipStream_t st) {
-  int splits = M / 256;
-  if (splits < 1) splits = 1;
-  if (splits > 64) splits = 64;
-  while (M % (splits * 32)) --splits;
-  GemmArgs g{};
-  g.A = dZ;  // storage [M][256] read as [k=M][m=out]
-  g.lda = 256;
-  g.B = A;   // storage [M][in] read as [k=M][n=in]
-  g.ldb = in;
-  g.ldc = in;
-  g.k_per_split = M / splits;
-  g.split_stride = (int64_t)256 * in;
-  g.Cf = part;
-  hipError_t e = gemm_bf16(g, true, false, kEpiStore, 256, in, splits, st);
-  if (e != hipSuccess) return e;
-  return launch_reduce_splits(part, splits, (int64_t)256 * in, dW, st);
+// Split-K count of the weight gradients of M rows: about 256 rows per split
+// (one staged panel), the rows of a split a multiple of 16, at most 64.
+int grad_splits(int M) {
+  const int s0 = min(kMaxGradSplits, (M + 255) / 256);
+  for (int s = s0; s <= kMaxGradSplits; ++s)
+    if (M % (16 * s) == 0) return s;
+  for (int s = s0; s > 1; --s)
+    if (M % (16 * s) == 0) return s;
+  return 1;
 }
 
-}  // namespace
-
-namespace dock {
-
-hipError_t mlp_forward(const uint16_t *x, int M, const uint16_t *wb, const float *bias_src,
-                       float *z1, uint16_t *a1, float *z2, uint16_t *a2, float *z3,
-                       uint16_t *a3, float *y, hipStream_t st) {
-  const uint16_t *in[4] = {x, a1, a2, a3};
+// Training forward pass of M rows: layers 1-3 keep pre-activations (FP32)
+// and activations (BF16); layer 4's epilogue turns its output straight into
+// the MSE gradient dz0 and per-tile squared errors (the output itself is not
+// stored).
+hipError_t train_forward(dock_mlp *n, const uint16_t *x, const uint16_t *t, int M,
+                         hipStream_t st) {
+  const uint16_t *in[4] = {x, n->a1, n->a2, n->a3};
   const int kin[4] = {64, 256, 256, 256};
   const int64_t woff[4] = {kMlpW1, kMlpW2, kMlpW3, kMlpW4};
   const int64_t boff[4] = {kMlpB1, kMlpB2, kMlpB3, kMlpB4};
-  float *zs[4] = {z1, z2, z3, y};
-  uint16_t *as[4] = {a1, a2, a3, nullptr};
+  float *zs[3] = {n->z1, n->z2, n->z3};
+  uint16_t *as[3] = {n->a1, n->a2, n->a3};
   for (int l = 0; l < 4; ++l) {
     GemmArgs g{};
     g.A = in[l];
     g.lda = kin[l];
-    g.B = wb + woff[l];  // storage [out][in]
+    g.B = n->wb + woff[l];  // storage [out][in]
     g.ldb = kin[l];
     g.ldc = 256;
     g.k_per_split = kin[l];
-    g.Cf = zs[l];
-    g.Cb = as[l];
-    g.bias = bias_src + boff[l];
-    hipError_t e = gemm_bf16(g, false, true, l < 3 ? kEpiBiasGelu : kEpiBias, M, 256, 1, st);
+    g.bias = n->w + boff[l];
+    if (l < 3) {
+      g.Cf = zs[l];
+      g.Cb = as[l];
+    } else {
+      g.Cb = n->dz0;
+      g.target = t;
+      g.scale = 1.0f / ((float)M * 256.0f);
+      g.block_loss = n->block_loss;
+    }
+    hipError_t e = gemm_bf16(g, false, true, l < 3 ? kEpiBiasGelu : kEpiBiasMse, M, 256, 1, st);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
 }
 
-}  // namespace dock
+}  // namespace
 
 extern "C" {
 
@@ -200,8 +197,6 @@ int dock_mlp_forward(dock_mlp *n, const uint16_t *x_bf16, int M, float *y, void 
   if (rc == DOCK_OK) rc = abi_check_device(y, "y");
   if (rc) return rc;
   std::lock_guard<std::mutex> lk(n->mu);
-  rc = ensure_rows(n, M);
-  if (rc) return rc;
   hipStream_t st = (hipStream_t)stream;
   hipError_t e = mlp_infer(x_bf16, M, n->wb, n->w, y, st);
   return e == hipSuccess ? DOCK_OK : abi_fail(DOCK_E_DEVICE, "mlp forward: %s", hipGetErrorString(e));
@@ -219,23 +214,30 @@ int dock_mlp_loss_grad(dock_mlp *n, const uint16_t *x_bf16, const uint16_t *t_bf
   rc = ensure_rows(n, M);
   if (rc) return rc;
   hipStream_t st = (hipStream_t)stream;
-  hipError_t e = mlp_forward(x_bf16, M, n->wb, n->w, n->z1, n->a1, n->z2, n->a2, n->z3, n->a3,
-                             n->y, st);
-  const int64_t nel = (int64_t)M * 256;
-  if (e == hipSuccess)
-    e = launch_mse_grad(n->y, t_bf16, nel, 1.0f / (float)nel, n->dz0, n->block_loss, n->loss, st);
-  // backward: layer 4 .. 1
+  hipError_t e = train_forward(n, x_bf16, t_bf16, M, st);
+  if (e == hipSuccess && loss_out)
+    e = launch_sum_blocks(n->block_loss, M / 16, 1.0f / ((float)M * 256.0f), n->loss, st);
+  // backward, layer 4 .. 1: the weight and bias gradients of a layer (split
+  // over the rows; the splits summed once at the end), then dZ of the layer
+  // below through the GELU derivative
+  const int splits = grad_splits(M);
   const uint16_t *acts[4] = {x_bf16, n->a1, n->a2, n->a3};
   const float *pre[4] = {nullptr, n->z1, n->z2, n->z3};
   const int kin[4] = {64, 256, 256, 256};
   const int64_t woff[4] = {kMlpW1, kMlpW2, kMlpW3, kMlpW4};
-  const int64_t boff[4] = {kMlpB1, kMlpB2, kMlpB3, kMlpB4};
   uint16_t *dz = n->dz0, *dz_next = n->dz1;
   for (int l = 3; l >= 0 && e == hipSuccess; --l) {
-    e = weight_grad(dz, acts[l], M, kin[l], n->part, n->g + woff[l], st);
-    if (e == hipSuccess) e = launch_colsum(dz, M, 256, n->part, n->g + boff[l], st);
-    if (l > 0 && e == hipSuccess) {
-      GemmArgs g{};
+    GemmArgs w{};
+    w.A = dz;  // storage [M][256] read as [k = row][m = out]
+    w.lda = 256;
+    w.B = acts[l];  // storage [M][in] read as [k = row][n = in]
+    w.ldb = kin[l];
+    w.ldc = kin[l];
+    w.k_per_split = M / splits;
+    w.split_stride = kMlpParams;
+    w.Cf = (splits > 1 ? n->part : n->g) + woff[l];
+    GemmArgs g{};
+    if (l > 0) {
       g.A = dz;  // [M][256]
       g.lda = 256;
       g.B = n->wb + woff[l];  // W_l storage [out=256][in] = [k][n]
@@ -244,12 +246,13 @@ int dock_mlp_loss_grad(dock_mlp *n, const uint16_t *x_bf16, const uint16_t *t_bf
       g.k_per_split = 256;
       g.Cb = dz_next;
       g.aux = pre[l];
-      e = gemm_bf16(g, false, false, kEpiGeluGrad, M, kin[l], 1, st);
-      uint16_t *t = dz;
-      dz = dz_next;
-      dz_next = t;
     }
+    e = backward_layer(w, kin[l], splits, l > 0 ? &g : nullptr, M, st);
+    uint16_t *t = dz;
+    dz = dz_next;
+    dz_next = t;
   }
+  if (e == hipSuccess && splits > 1) e = launch_reduce_grads(n->part, splits, kMlpParams, n->g, st);
   if (e == hipSuccess && grad_out)
     e = hipMemcpyAsync(grad_out, n->g, sizeof(float) * kMlpParams, hipMemcpyDeviceToDevice, st);
   if (e == hipSuccess && loss_out) {
