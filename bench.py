@@ -298,19 +298,24 @@ def learned_comparison(n_eval=10_000, n_val=2_000, n_train=156_250, epochs=10, t
     res = compare(256)
     if fine_steps:
         res["fine_steps"] = compare(fine_steps)
-    res["bound"] = learned_bound(h, batches["eval"], n_eval, net, stream,
-                                 (256,) + ((fine_steps,) if fine_steps else ()))
+    fallback = {256: res["fallback_rate"]}
+    if fine_steps:
+        fallback[fine_steps] = res["fine_steps"]["fallback_rate"]
+    res["bound"] = learned_bound(h, batches["eval"], n_eval, net, stream, fallback)
     h.close()
     res["training"] = {k: v for k, v in hist.items() if k not in ("train_loss", "val_loss")} | {
         "final_val_mse": hist.get("val_loss", [None])[-1], "seconds": round(t_train, 2)}
     return res, net
 
 
-def learned_bound(h, batch, n_eval, net, stream, steps_list, proposals=16, reps=10):
-    """Inputs of the speed bound on any learned proposal for the evaluation
-    batch: the plain sweep at each step count and at `proposals` steps (a
-    rotamer step that tests and scores only that many angles), and the MLP
-    over every item once per rotamer step, measured and at the MFMA peak."""
+def learned_bound(h, batch, n_eval, net, stream, fallback, proposals=16, reps=10):
+    """Speed bound on any learned proposal for the evaluation batch: the plain
+    sweep at each step count S and at `proposals` steps (a rotamer step that
+    tests and scores only that many angles), and the MLP over every item once
+    per rotamer step, measured and at the MFMA peak.  Without fallback a
+    learned call costs at least MLP + sweep(proposals); with a fallback rate
+    f (the one the comparison measured at S) at least MLP + f sweep(S) +
+    (1 - f) sweep(proposals)."""
     import torch
     from paper_1901_06229_amd import dock
     ligs, d, od, out = batch
@@ -347,11 +352,17 @@ def learned_bound(h, batch, n_eval, net, stream, steps_list, proposals=16, reps=
                    f"that tests and scores {proposals} angles",
            f"plain_sweep_ms_{proposals}_steps": round(small, 4),
            "mlp_ms_measured": round(mlp_ms, 4), "mlp_ms_at_peak": round(mlp_peak_ms, 4)}
-    for S in steps_list:
+    for S, f in fallback.items():
         full = sweep_ms(S)
+        with_fb = f * full + (1.0 - f) * small
         res[f"S{S}"] = {"plain_sweep_ms": round(full, 4),
                         "bound_no_fallback_measured_mlp": round(full / (small + mlp_ms), 3),
-                        "bound_no_fallback_peak_mlp": round(full / (small + mlp_peak_ms), 3)}
+                        "bound_no_fallback_peak_mlp": round(full / (small + mlp_peak_ms), 3),
+                        "fallback_rate": round(f, 3),
+                        "bound_at_fallback_measured_mlp": round(full / (with_fb + mlp_ms), 3),
+                        "bound_at_fallback_peak_mlp": round(full / (with_fb + mlp_peak_ms), 3),
+                        "break_even_fallback_measured_mlp": round(
+                            max(0.0, (full - small - mlp_ms) / (full - small)) if full > small else 0.0, 3)}
     return res
 
 
