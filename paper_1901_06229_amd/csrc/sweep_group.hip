@@ -26,71 +26,91 @@
 
 namespace dock {
 
-// Scratch sizes of one group (entries): kept-pair list, ring of compacted
-// steps; steps compacted per append (the chunk).
-template <int G> constexpr int kGroupPairCap = 4 * G;
+// Ring of compacted steps per group (entries), steps compacted per append
+// (the chunk), kept-pair list of the wave (entries).
 template <int G> constexpr int kGroupRing = 4 * G;
 template <int G> constexpr int kGroupChunk = 2 * G;
 constexpr int kGroupScoreTiles = 2;  // compacted G-step tiles scored per full pass
+constexpr int kWavePairCap = 512;
 static_assert(kGroupChunk<16> + kGroupScoreTiles * 16 <= kGroupRing<16>, "ring too small");
 static_assert(kGroupChunk<32> + kGroupScoreTiles * 32 <= kGroupRing<32>, "ring too small");
 
 __host__ __device__ inline int round16(int b) { return (b + 15) / 16 * 16; }
 
-// LDS of one wave: the shared lists, then one region per group.  LDS
-// bounds how many waves a compute unit holds, and these kernels run faster
-// with every wave added (latency-bound), so the regions are kept small.
-//   shared: Q, M (int16 [nmax]) static and moving lists of the step,
-//           slot (int16 [nmax]) an atom's entry in ZRc: moving atom t -> t,
-//           static atom Q[p] -> m + p, axis atoms -1
-//   group:  X (float4 [nmax]) pose, x y z and voxel value
-//           ZRc (float2 [nmax]) axial coordinate and |r| about the bond axis
-//           of the moving atoms (in list order), then of the static ones
-//           scratch: kept pairs (int [4G]) during the bump test, then the
-//                    moving atoms' voxel-unit bases (float [9][G]) and the
-//                    ring of compacted steps (int16 [4G])
-//           BM (uint32 [(S + 31) / 32]) bump bits
+// LDS of one wave.  LDS bounds how many waves a compute unit holds, and these
+// kernels run faster with every wave added (latency-bound), so it is kept
+// small.
+//   shared:  Q, M (int16 [nmax]) static and moving lists of the step,
+//            slot (int16 [nmax]) an atom's entry in ZRc: moving atom t -> t,
+//            static atom Q[p] -> m + p, axis atoms -1,
+//            AXU (float4 [NG][2]) each group's axis point and unit bond axis
+//   scratch: one block per group, contiguous: the moving atoms' voxel-unit
+//            bases (float [9][G]) and the ring of compacted steps (int16
+//            [4G]) while scoring; the moving atoms' values for the step-0
+//            score; during the bump test all of it is the wave's kept-pair
+//            list (int [kWavePairCap])
+//   groups:  X (float4 [nmax]) pose, x y z and voxel value
+//            ZRc (float2 [nmax]) axial coordinate and |r| about the bond axis
+//            of the moving atoms (in list order), then of the static ones
+//            BM (uint32 [(S + 31) / 32]) bump bits
 template <int G>
-__host__ __device__ inline int group_shared_bytes(int nmax) { return round16(nmax * 6); }
+__host__ __device__ inline int group_shared_bytes(int nmax) {
+  return round16(nmax * 6) + (kWave / G) * 32;
+}
 template <int G>
 __host__ __device__ constexpr int group_scratch_bytes() {
-  return (((kGroupPairCap<G> * 4 > 9 * G * 4 + kGroupRing<G> * 2)
-               ? kGroupPairCap<G> * 4
-               : 9 * G * 4 + kGroupRing<G> * 2) + 15) / 16 * 16;
+  return (9 * G * 4 + kGroupRing<G> * 2 + 15) / 16 * 16;
 }
-// the scratch also holds the moving atoms' values (m < class atoms) for s0
 static_assert(group_scratch_bytes<16>() >= 4 * kGroupMaxAtoms16, "scratch too small");
 static_assert(group_scratch_bytes<32>() >= 4 * kGroupMaxAtoms32, "scratch too small");
+static_assert((kWave / 16) * group_scratch_bytes<16>() >= 4 * kWavePairCap, "pair list");
+static_assert((kWave / 32) * group_scratch_bytes<32>() >= 4 * kWavePairCap, "pair list");
 template <int G>
 __host__ __device__ inline int group_region_bytes(int nmax, int S) {
-  return nmax * 16 + nmax * 8 + group_scratch_bytes<G>() + round16(4 * ((S + 31) / 32));
+  return nmax * 16 + nmax * 8 + round16(4 * ((S + 31) / 32));
 }
 template <int G>
 __host__ __device__ inline int group_wave_bytes(int nmax, int S) {
-  return group_shared_bytes<G>(nmax) + (kWave / G) * group_region_bytes<G>(nmax, S);
+  return group_shared_bytes<G>(nmax) +
+         (kWave / G) * (group_scratch_bytes<G>() + group_region_bytes<G>(nmax, S));
 }
 
 template <int G>
 struct GroupLds {
   int16_t *Q, *M, *slot;
+  float4 *AXU;    // [NG][2]
+  int *PL;        // the wave's kept-pair list
+  char *regions;  // group 0's region; group g's at + g * region
+  int region;
+  int nmax;
+  // this group's
   float4 *X;
   float2 *ZRc;
-  int *PI;
   float *B;
   int16_t *CK;
   uint32_t *BM;
-  __device__ GroupLds(char *wave_base, int nmax, int S, int gid) {
+  __device__ GroupLds(char *wave_base, int nmax_, int S, int gid) {
+    nmax = nmax_;
     Q = (int16_t *)wave_base;
     M = Q + nmax;
     slot = M + nmax;
-    char *g = wave_base + group_shared_bytes<G>(nmax) + gid * group_region_bytes<G>(nmax, S);
-    X = (float4 *)g;
-    ZRc = (float2 *)(X + nmax);
-    char *scr = (char *)(ZRc + nmax);
-    PI = (int *)scr;
+    AXU = (float4 *)(wave_base + round16(nmax * 6));
+    char *scr0 = wave_base + group_shared_bytes<G>(nmax);
+    PL = (int *)scr0;
+    char *scr = scr0 + gid * group_scratch_bytes<G>();
     B = (float *)scr;
     CK = (int16_t *)(scr + 9 * G * 4);
-    BM = (uint32_t *)(scr + group_scratch_bytes<G>());
+    regions = scr0 + (kWave / G) * group_scratch_bytes<G>();
+    region = group_region_bytes<G>(nmax, S);
+    X = group_X(gid);
+    ZRc = (float2 *)(X + nmax);
+    BM = group_BM(gid);
+  }
+  __device__ __forceinline__ float4 *group_X(int g) const {
+    return (float4 *)(regions + g * region);
+  }
+  __device__ __forceinline__ uint32_t *group_BM(int g) const {
+    return (uint32_t *)(regions + g * region + nmax * 24);
   }
 };
 
@@ -222,7 +242,8 @@ __global__ void __launch_bounds__(WAVES *kWave)
   const float thr = r2 + kPruneMargin;
   const float steps_per_rad = (float)S * 0.15915494309189535f;  // S / (2 pi)
   const int words = (S + 31) / 32;
-  uint64_t kept_pairs = 0, evals = 0;  // this group's work counters
+  uint64_t kept_pairs = 0;  // the wave's work counters: kept pairs (wave-uniform),
+  uint64_t evals = 0;       // evaluations of this group
 
   const int cb = A.small[kClassBegin + cls], ce = A.small[kClassEnd + cls];
   const int upl = (O + NG - 1) / NG;  // units (NG orientations) per ligand
@@ -301,7 +322,7 @@ __global__ void __launch_bounds__(WAVES *kWave)
         for (int w = g.gl; w < words; w += G) W.BM[w] = 0u;
         // the moving atoms' current values, in list order, into the scratch
         // (free until the pair list fills it): read in parallel, added below
-        float *mval = (float *)W.PI;
+        float *mval = W.B;
         for (int t = g.gl; t < m; t += G) mval[t] = W.X[W.M[t]].w;
         wave_lds_sync();
         // the current pose's score (step 0): static score, then the moving
@@ -311,23 +332,33 @@ __global__ void __launch_bounds__(WAVES *kWave)
         for (int t = 0; t < m; ++t) s0 += mval[t];
         wave_lds_sync();
 
-        // bump bits: pairs whose cylinder bound does not clear r_bump, then
-        // their clash arcs (pairs packed as moving-list position << 16 | j)
-        int np = 0;  // this group's kept pairs in the list
+        // bump bits: pairs whose cylinder bound does not clear r_bump go into
+        // the wave's pair list (packed group << 16 | moving-list position << 8
+        // | j); their clash arcs are then marked 64 pairs at a time, each
+        // lane into its pair's group
+        if (g.gl == 0) {
+          W.AXU[2 * g.gid] = xa;
+          W.AXU[2 * g.gid + 1] = make_float4(u.x, u.y, u.z, 0.0f);
+        }
+        int np = 0;  // pairs in the list (wave-uniform)
         auto flush = [&]() {
           wave_lds_sync();
-          const int most = (int)__builtin_amdgcn_readfirstlane((int)wave_max_u32((uint32_t)np));
-          for (int e0 = 0; e0 < most; e0 += G) {
-            const int e = e0 + g.gl;
+          for (int e0 = 0; e0 < np; e0 += kWave) {
+            const int e = e0 + lane;
+            bool counted = false;
             if (e < np) {
-              const int pk = W.PI[e];
-              const int i = W.M[pk >> 16], j = pk & 0xFFFF;
-              const Cyl ci = cyl_of(W.X[i], xa, u), cj = cyl_of(W.X[j], xa, u);
-              mark_pair_arc(W.BM, make_float4(ci.rx, ci.ry, ci.rz, ci.z),
-                            make_float4(cj.rx, cj.ry, cj.rz, cj.z), u, r2, S, steps_per_rad);
+              const int pk = W.PL[e];
+              const int pg = pk >> 16, i = W.M[(pk >> 8) & 0xFF], j = pk & 0xFF;
+              const float4 *Xg = W.group_X(pg);
+              const float4 pxa = W.AXU[2 * pg], pu4 = W.AXU[2 * pg + 1];
+              const float3 pu = make_float3(pu4.x, pu4.y, pu4.z);
+              const Cyl ci = cyl_of(Xg[i], pxa, pu), cj = cyl_of(Xg[j], pxa, pu);
+              mark_pair_arc(W.group_BM(pg), make_float4(ci.rx, ci.ry, ci.rz, ci.z),
+                            make_float4(cj.rx, cj.ry, cj.rz, cj.z), pu, r2, S, steps_per_rad);
+              counted = o_first + pg < O;  // pairs of idle groups are not work
             }
+            kept_pairs += (uint64_t)__popcll(wave_ballot(counted));
           }
-          if (active) kept_pairs += (uint64_t)np;
           np = 0;
           wave_lds_sync();
         };
@@ -336,16 +367,18 @@ __global__ void __launch_bounds__(WAVES *kWave)
           const int j = jin ? W.Q[jb + g.gl] : 0;
           const float2 zrj = W.ZRc[jin ? m + jb + g.gl : 0];
           const float zj = zrj.x, rj = jin ? zrj.y : __builtin_inff();
+          const int pj = (g.gid << 16) | j;
 #pragma unroll 2
           for (int t = 0; t < m; ++t) {
             const float2 mz = W.ZRc[t];  // group-uniform address: a broadcast read
             const float dz = mz.x - zj;
             const float dr = mz.y - rj;
             const float lb = fmaf(dr, dr, dz * dz);
-            const uint32_t gb = g.bits(__builtin_amdgcn_fcmpf(lb, thr, 4));
-            if ((gb >> g.gl) & 1u) W.PI[np + __popc(gb & g.below)] = (t << 16) | j;
-            np += __popc(gb);
-            if (wave_ballot(np > kGroupPairCap<G> - G) != 0ull) flush();
+            // the ballot is the compare's own lane mask (4: ordered less-than)
+            const uint64_t keep = __builtin_amdgcn_fcmpf(lb, thr, 4);
+            if (lb < thr) W.PL[lanes_before(keep, np)] = pj | (t << 8);
+            np += __popcll(keep);
+            if (np > kWavePairCap - kWave) flush();
           }
         }
         flush();
@@ -433,10 +466,8 @@ __global__ void __launch_bounds__(WAVES *kWave)
     }
     wave_lds_sync();
   }
-  if (g.gl == 0 && A.work) {
-    atomicAdd(A.work, (unsigned long long)kept_pairs);
-    atomicAdd(A.work + 1, (unsigned long long)evals);
-  }
+  if (lane == 0 && A.work) atomicAdd(A.work, (unsigned long long)kept_pairs);
+  if (g.gl == 0 && A.work) atomicAdd(A.work + 1, (unsigned long long)evals);
 }
 
 template <int G, int WAVES>
