@@ -147,6 +147,15 @@ __device__ __forceinline__ float chunk_sum_group(float acc, float v, int base, i
   }
 }
 
+// Maximum over the wave of a group-uniform value (one read per group).
+template <int G>
+__device__ __forceinline__ int group_wave_max(int v) {
+  int mx = __builtin_amdgcn_readlane(v, 0);
+#pragma unroll
+  for (int g = 1; g < kWave / G; ++g) mx = max(mx, __builtin_amdgcn_readlane(v, g * G));
+  return mx;
+}
+
 // Maximum of a 32-bit value over each group (all of its lanes get it).
 template <int G>
 __device__ __forceinline__ uint32_t group_max_u32(uint32_t v) {
@@ -168,24 +177,37 @@ __device__ __forceinline__ uint64_t group_max_u64(uint64_t v) {
 
 // Scores of the lane's TC compacted steps kk (-1: none) -- static score plus
 // the moving atoms' values in list order, as rotamer_scores computes them.
+// Voxel-unit rotation bases of moving atoms c0 .. c0 + G - 1 into the
+// group's B (one atom per lane).
+template <int G>
+__device__ __forceinline__ void group_bases(const GroupLds<G> &W, const Grp<G> &g, int m, int c0,
+                                            float4 xa, float3 u, const GridView &GV) {
+  if (c0 + g.gl < m) {
+    const Cyl c = cyl_of(W.X[W.M[c0 + g.gl]], xa, u);
+    const VoxBasis vb = voxel_basis(rot_basis(c, xa, u), GV);
+    float *B = W.B + g.gl;
+    B[0 * G] = vb.px, B[1 * G] = vb.py, B[2 * G] = vb.pz;
+    B[3 * G] = vb.ex, B[4 * G] = vb.ey, B[5 * G] = vb.ez;
+    B[6 * G] = vb.fx, B[7 * G] = vb.fy, B[8 * G] = vb.fz;
+  }
+}
+
+// cached: m <= G and B already holds the bases (written once per rotamer
+// step and kept across its passes).
 template <int G, int TC>
 __device__ __forceinline__ void group_scores(const GroupLds<G> &W, const Grp<G> &g, int m,
-                                             float cst, float4 xa, float3 u, const GridView &GV,
-                                             const GridScaled &GS, __amdgpu_buffer_rsrc_t grsrc,
+                                             bool cached, float cst, float4 xa, float3 u,
+                                             const GridView &GV, const GridScaled &GS,
+                                             __amdgpu_buffer_rsrc_t grsrc,
                                              const float (&cc)[TC], const float (&ss)[TC],
                                              float (&score)[TC]) {
 #pragma unroll
   for (int t = 0; t < TC; ++t) score[t] = cst;
   for (int c0 = 0; c0 < m; c0 += G) {
-    if (c0 + g.gl < m) {
-      const Cyl c = cyl_of(W.X[W.M[c0 + g.gl]], xa, u);
-      const VoxBasis vb = voxel_basis(rot_basis(c, xa, u), GV);
-      float *B = W.B + g.gl;
-      B[0 * G] = vb.px, B[1 * G] = vb.py, B[2 * G] = vb.pz;
-      B[3 * G] = vb.ex, B[4 * G] = vb.ey, B[5 * G] = vb.ez;
-      B[6 * G] = vb.fx, B[7 * G] = vb.fy, B[8 * G] = vb.fz;
+    if (!cached) {
+      group_bases<G>(W, g, m, c0, xa, u, GV);
+      wave_lds_sync();
     }
-    wave_lds_sync();
     const int cnt = min(G, m - c0);
     auto gather = [&](int tt, float(&v)[TC]) {
       const float *B = W.B + tt;  // group-uniform address: broadcast reads
@@ -242,6 +264,10 @@ __global__ void __launch_bounds__(WAVES *kWave)
   const float thr = r2 + kPruneMargin;
   const float steps_per_rad = (float)S * 0.15915494309189535f;  // S / (2 pi)
   const int words = (S + 31) / 32;
+  // bits of a 32-bit bump word below this lane's step, per G-step half
+  uint32_t below_bit[32 / G];
+#pragma unroll
+  for (int h = 0; h < 32 / G; ++h) below_bit[h] = (1u << (h * G + g.gl)) - 1u;
   uint64_t kept_pairs = 0;  // the wave's work counters: kept pairs (wave-uniform),
   uint64_t evals = 0;       // evaluations of this group
 
@@ -390,6 +416,10 @@ __global__ void __launch_bounds__(WAVES *kWave)
         // one pass of one or two tiles.  Passes run wave-wide; each group
         // reads its own next entries.  Unread entries stay below 2G after a
         // pass and below 4G after an append, so the ring never overwrites them.
+        // a step whose moving atoms fit one group computes their bases once
+        // (the pair list, which shared this scratch, is done)
+        const bool cached = m <= G;
+        if (cached) group_bases<G>(W, g, m, 0, xa, u, GV);
         uint64_t best = 0ull;
         int nv = 0;       // entries this group has appended (same in its lanes)
         int rd = 0;       // entries this group has scored
@@ -406,7 +436,7 @@ __global__ void __launch_bounds__(WAVES *kWave)
             cc[t] = cs.x;
             ss[t] = cs.y;
           }
-          group_scores<G, TC>(W, g, m, cst, xa, u, GV, GS, grsrc, cc, ss, score);
+          group_scores<G, TC>(W, g, m, cached, cst, xa, u, GV, GS, grsrc, cc, ss, score);
 #pragma unroll
           for (int t = 0; t < TC; ++t) {
             if (kk[t] == 0) score[t] = s0;
@@ -416,21 +446,31 @@ __global__ void __launch_bounds__(WAVES *kWave)
           rd = min(nv, rd + TC * G);
         };
         for (int c0 = 0; c0 < S; c0 += kGroupChunk<G>) {
-          const int nv0 = nv;
+          // one 32-bit bump word at a time (group-uniform, a broadcast read):
+          // its complement is the word's valid steps, in step order, so a
+          // lane's slot is the count of valid steps below its bit
 #pragma unroll
-          for (int w = 0; w < kGroupChunk<G> / G; ++w) {
-            const int k = c0 + w * G + g.gl;
-            const bool valid = k < S && ((W.BM[k >> 5] >> (k & 31)) & 1u) == 0u;
-            const uint32_t gb = g.bits(wave_ballot(valid));
-            if (valid) W.CK[(nv + __popc(gb & g.below)) & (kGroupRing<G> - 1)] = (int16_t)k;
-            nv += __popc(gb);
+          for (int wd = 0; wd < kGroupChunk<G> / 32; ++wd) {
+            const int s0 = c0 + 32 * wd;
+            if (s0 < S) {
+              uint32_t word = ~W.BM[s0 >> 5];
+              if (S - s0 < 32) word &= (1u << (S - s0)) - 1u;
+#pragma unroll
+              for (int h = 0; h < 32 / G; ++h) {
+                const int bit = h * G + g.gl;
+                if ((word >> bit) & 1u)
+                  W.CK[(nv + __popc(word & below_bit[h])) & (kGroupRing<G> - 1)] =
+                      (int16_t)(s0 + bit);
+              }
+              nv += __popc(word);
+            }
           }
           wave_lds_sync();
-          if (active) evals += (uint64_t)m * (uint64_t)(nv - nv0);
-          most = (int)__builtin_amdgcn_readfirstlane((int)wave_max_u32((uint32_t)(nv - rd)));
+          most = group_wave_max<G>(nv - rd);
           if (most >= kGroupScoreTiles * G) pass(std::integral_constant<int, kGroupScoreTiles>{});
         }
-        most = (int)__builtin_amdgcn_readfirstlane((int)wave_max_u32((uint32_t)(nv - rd)));
+        if (active) evals += (uint64_t)m * (uint64_t)nv;
+        most = group_wave_max<G>(nv - rd);
         if (most > G) pass(std::integral_constant<int, kGroupScoreTiles>{});
         else if (most > 0) pass(std::integral_constant<int, 1>{});
         best = group_max_u64<G>(best);
