@@ -394,17 +394,25 @@ __global__ void __launch_bounds__(WAVES *kWave)
           const float2 zrj = W.ZRc[jin ? m + jb + g.gl : 0];
           const float zj = zrj.x, rj = jin ? zrj.y : __builtin_inff();
           const int pj = (g.gid << 16) | j;
-#pragma unroll 2
-          for (int t = 0; t < m; ++t) {
-            const float2 mz = W.ZRc[t];  // group-uniform address: a broadcast read
+          // the ballot is the compare's own lane mask (4: ordered less-than)
+          auto test = [&](const float2 mz, int t) {
             const float dz = mz.x - zj;
             const float dr = mz.y - rj;
             const float lb = fmaf(dr, dr, dz * dz);
-            // the ballot is the compare's own lane mask (4: ordered less-than)
             const uint64_t keep = __builtin_amdgcn_fcmpf(lb, thr, 4);
             if (lb < thr) W.PL[lanes_before(keep, np)] = pj | (t << 8);
             np += __popcll(keep);
-            if (np > kWavePairCap - kWave) flush();
+          };
+          int t = 0;
+          for (; t + 1 < m; t += 2) {  // two moving atoms per turn, both reads first
+            const float2 mz0 = W.ZRc[t], mz1 = W.ZRc[t + 1];  // group-uniform: broadcasts
+            test(mz0, t);
+            test(mz1, t + 1);
+            if (np > kWavePairCap - 2 * kWave) flush();
+          }
+          if (t < m) {
+            test(W.ZRc[t], t);
+            if (np > kWavePairCap - 2 * kWave) flush();
           }
         }
         flush();
