@@ -371,7 +371,7 @@ typedef struct {
 
 /* Autotuner: time the sweep for every candidate mapping (waves per block
  * 1, 2, 4 x claim caps 4, 16, 32, 64 x group bounds (0, 0), (40, 80),
- * (48, 96), (56, 112)) on a seeded subset of sample_ligands ligands of this
+ * (48, 96), (56, 112), (64, 128)) on a seeded subset of sample_ligands ligands of this
  * (host) batch, keep the fastest on the handle (dock_set_launch and
  * dock_set_group_mapping), and report each timing in entries[0..*n_entries).
  * Same validation and errors as dock_batch. */

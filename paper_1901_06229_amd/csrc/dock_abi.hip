@@ -699,8 +699,8 @@ int dock_autotune(dock_pocket *p, const dock_ligands *ligs, const float *orient,
   tp.flags |= DOCK_FLAG_TIME_SWEEP;
   const int waves[] = {1, 2, 4};
   const int claims[] = {4, 16, 32, 64};
-  // size classes docked in groups: none, and three (16-lane, 32-lane) bounds
-  const int groups[][2] = {{0, 0}, {40, 80}, {48, 96}, {56, 112}};
+  // size classes docked in groups: none, and four (16-lane, 32-lane) bounds
+  const int groups[][2] = {{0, 0}, {40, 80}, {48, 96}, {56, 112}, {64, 128}};
   LaunchPlan best_plan = p->plan;
   float best_ms = 0.0f;
   int n = 0;
