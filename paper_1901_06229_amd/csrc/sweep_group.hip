@@ -8,9 +8,10 @@
 // score tile.  The items of one ligand share its topology (atom count,
 // rotamers, moving and static lists), so groups of one wave run the same
 // loops in lockstep and only their data differ: each group keeps its own
-// pose, bump bits, kept pairs and compacted steps; the moving / static lists
-// are built once per wave.  Per item, that divides the per-step work by the
-// number of groups where it fits in G lanes.
+// pose, bump bits and compacted steps; the moving / static lists and the
+// kept-pair list (pairs tagged with their group) are shared by the wave.
+// Per item, that divides the per-step work by the number of groups where it
+// fits in G lanes.
 //
 // Every result is bitwise the one-item-per-wave kernel's: the same functions
 // place atoms, test and arc pairs, index voxels and key angles; scores add
