@@ -19,6 +19,7 @@
 // final scores use the mapping-independent chunked atom sum.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <type_traits>
 
 #include "dock_internal.h"
@@ -533,8 +534,14 @@ static hipError_t launch_group(const SweepArgs &A, int cls, int nmax, const Laun
   const int bpc = plan.blocks_per_cu > 0 && plan.blocks_per_cu < occ ? plan.blocks_per_cu : occ;
   *waves_per_cu = bpc * WAVES;
   if (!st) return hipSuccess;  // query only
-  hipLaunchKernelGGL((sweep_group_kernel<G, WAVES>), dim3((unsigned)(bpc * n_cu)),
-                     dim3(WAVES * kWave), shmem, st, A, nmax, cls);
+  // no more waves than the batch has units (the class sizes are only known
+  // on the device; every ligand gives at most ceil(orientations / groups))
+  const int64_t units = (int64_t)A.lig.n_ligands * ((A.n_orient + kWave / G - 1) / (kWave / G));
+  int64_t grid = (int64_t)bpc * n_cu;
+  grid = std::min<int64_t>(grid, (units + WAVES - 1) / WAVES);
+  if (grid < 1) grid = 1;
+  hipLaunchKernelGGL((sweep_group_kernel<G, WAVES>), dim3((unsigned)grid), dim3(WAVES * kWave),
+                     shmem, st, A, nmax, cls);
   return hipGetLastError();
 }
 
