@@ -510,7 +510,7 @@ def test_full_c3_batch_autotuned_graph_sampled_replay(pockets):
     ligs = synth.ligands(3)
     orient = synth.orientations(3)
     L, O, S = ligs.n_ligands, 128, 128
-    tune = dock.dock_autotune(h, ligs, orient, S, sample_ligands=2000, seed=1)
+    tune = dock.dock_autotune(h, ligs, orient, S, sample_ligands=10000, seed=1)
     print(f"[gpu] full uneven batch, autotuned to {dock.dock_get_launch(h)} over {len(tune)} mappings",
           flush=True)
     d, od, out = _device_batch(ligs, orient, S, torch)
