@@ -142,3 +142,32 @@ def test_group_mapping_arguments(pockets):
     dock.dock_set_group_mapping(h, 32, 64)
     assert dock.dock_get_group_mapping(h) == (32, 64)
     dock.dock_set_group_mapping(h, 0, 0)
+
+
+def test_grouped_degenerate_ligands(pockets):
+    """One atom, no rotamers, an empty moving set, a three-atom chain and a
+    whole ligand, with 1 and 5 orientations (3 or 3 + 3 idle groups per
+    wave), bitwise equal to the one-item-per-wave mapping; the r_bump = 50
+    case where no angle is valid (k* = -1 everywhere) too."""
+    from tests.helpers import make_lig
+    p, h = pockets(1)
+    one = make_lig(np.array([[0.5, 0.2, -0.3]], np.float32), [])
+    xyz = np.array([[0, 0, 0], [1.5, 0, 0], [2.0, 1.4, 0], [3.5, 1.5, 0.3]], np.float32)
+    rigid = make_lig(xyz, [])
+    empty_move = make_lig(xyz, [(0, 1, [])])
+    chain = make_lig(xyz, [(1, 2, [3])])
+    whole = synth.ligands(1).ligand(0)
+    ligs = synth.Ligands.from_parts([one, rigid, empty_move, chain, whole])
+    for O in (1, 5):
+        orient = synth.orientations(1, O)
+        for S in (1, 16, 100):
+            ref = _run(h, ligs, orient, S, (0, 0))
+            for mp in ((64, 128), (0, 128)):
+                _same(_run(h, ligs, orient, S, mp), ref, (O, S, mp))
+        ref = _run(h, ligs, orient, 16, (0, 0), r_bump=50.0)
+        got = _run(h, ligs, orient, 16, (64, 128), r_bump=50.0)
+        _same(got, ref, (O, "r_bump 50"))
+        # every rotamer with moving atoms bumps at every angle; the one with
+        # an empty moving set (the first rotamer of the batch) cannot bump
+        ai = np.asarray(got["angle_idx"]).reshape(-1)
+        assert ai[0] == 0 and (ai[1:] == -1).all(), ai
