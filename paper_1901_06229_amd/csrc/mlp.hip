@@ -273,6 +273,8 @@ hipError_t gemm_bf16(const GemmArgs &g, bool ta, bool tb, int epi, int M, int N,
                      hipStream_t st) {
   if (M % kTile || N % kTile || g.k_per_split % 16 || g.k_per_split < 16 || splits < 1)
     return hipErrorInvalidValue;
+  // a panel stored [row][k] is staged with shifts: its K chunks are powers of two
+  if ((!ta || tb) && (g.k_per_split & (g.k_per_split - 1))) return hipErrorInvalidValue;
 #define DOCK_GEMM(TA, TB, E) \
   if (ta == TA && tb == TB && epi == E) return gemm_t<TA, TB, E>(g, M, N, splits, st);
   DOCK_GEMM(false, true, kEpiBiasGelu)
@@ -283,8 +285,10 @@ hipError_t gemm_bf16(const GemmArgs &g, bool ta, bool tb, int epi, int M, int N,
 
 hipError_t backward_layer(const GemmArgs &w, int in, int splits, const GemmArgs *d, int M,
                           hipStream_t st) {
+  // d stages its dZ panel [row][k] with shifts: a power-of-two K
   if (in % kTile || w.k_per_split % 16 || w.k_per_split < 16 || splits < 1 ||
-      (d && (M % kTile || d->k_per_split % 16 || d->k_per_split < 16)))
+      (d && (M % kTile || d->k_per_split % 16 || d->k_per_split < 16 ||
+             (d->k_per_split & (d->k_per_split - 1)))))
     return hipErrorInvalidValue;
   const int wx = in / kTile, dx = in / kTile;
   const int blocks = wx * 4 * splits + (d ? dx * (M / kTile) : 0);
