@@ -149,15 +149,6 @@ __device__ __forceinline__ float chunk_sum_group(float acc, float v, int base, i
   }
 }
 
-// Maximum over the wave of a group-uniform value (one read per group).
-template <int G>
-__device__ __forceinline__ int group_wave_max(int v) {
-  int mx = __builtin_amdgcn_readlane(v, 0);
-#pragma unroll
-  for (int g = 1; g < kWave / G; ++g) mx = max(mx, __builtin_amdgcn_readlane(v, g * G));
-  return mx;
-}
-
 // Maximum of a 32-bit value over each group (all of its lanes get it).
 template <int G>
 __device__ __forceinline__ uint32_t group_max_u32(uint32_t v) {
@@ -433,7 +424,6 @@ __global__ void __launch_bounds__(WAVES *kWave)
         uint64_t best = 0ull;
         int nv = 0;       // entries this group has appended (same in its lanes)
         int rd = 0;       // entries this group has scored
-        int most = 0;     // the wave's largest unread count
         auto pass = [&](auto tiles) {
           constexpr int TC = decltype(tiles)::value;
           float cc[TC], ss[TC], score[TC];
@@ -476,13 +466,12 @@ __global__ void __launch_bounds__(WAVES *kWave)
             }
           }
           wave_lds_sync();
-          most = group_wave_max<G>(nv - rd);
-          if (most >= kGroupScoreTiles * G) pass(std::integral_constant<int, kGroupScoreTiles>{});
+          if (wave_ballot(nv - rd >= kGroupScoreTiles * G) != 0ull)
+            pass(std::integral_constant<int, kGroupScoreTiles>{});
         }
         if (active) evals += (uint64_t)m * (uint64_t)nv;
-        most = group_wave_max<G>(nv - rd);
-        if (most > G) pass(std::integral_constant<int, kGroupScoreTiles>{});
-        else if (most > 0) pass(std::integral_constant<int, 1>{});
+        if (wave_ballot(nv - rd > G) != 0ull) pass(std::integral_constant<int, kGroupScoreTiles>{});
+        else if (wave_ballot(nv - rd > 0) != 0ull) pass(std::integral_constant<int, 1>{});
         best = group_max_u64<G>(best);
         const int kb = best ? (int)key_index(best) : -1;
         if (g.gl == (step & (G - 1))) kreg = kb;
@@ -496,7 +485,17 @@ __global__ void __launch_bounds__(WAVES *kWave)
             const Cyl c = cyl_of(W.X[i], xa, u);
             const RotBasis bs = rot_basis(c, xa, u);
             const float3 y = rot_apply(bs, cs.x, cs.y);
-            const uint32_t off = basis_voxel_offset(GS, voxel_basis(bs, GV), cs.x, cs.y);
+            // the voxel-unit basis: the one this lane stored for the step's
+            // passes when they were cached (the same values), else computed
+            VoxBasis vb;
+            if (cached) {
+              const float *B = W.B + g.gl;
+              vb = VoxBasis{B[0 * G], B[1 * G], B[2 * G], B[3 * G], B[4 * G],
+                            B[5 * G], B[6 * G], B[7 * G], B[8 * G]};
+            } else {
+              vb = voxel_basis(bs, GV);
+            }
+            const uint32_t off = basis_voxel_offset(GS, vb, cs.x, cs.y);
             W.X[i] = make_float4(y.x, y.y, y.z, GV.grid[off >> 2]);
           }
         }
