@@ -357,7 +357,7 @@ int dock_get_launch(dock_pocket *p, int *waves_per_block, int *blocks_per_cu,
  * DOCK_GROUP_MAX_STEPS angle steps (not with DOCK_FLAG_NO_LPT or
  * DOCK_FLAG_DIRECT_BUMP, nor learned mode; above that step count scoring
  * dominates a rotamer step and one item per wave scores it faster).  Results
- * are bitwise identical under every mapping.  A new handle starts at (48, 96). */
+ * are bitwise identical under every mapping.  A new handle starts at (64, 128). */
 #define DOCK_GROUP_MAX_STEPS 2048
 int dock_set_group_mapping(dock_pocket *p, int atoms16, int atoms32);
 int dock_get_group_mapping(dock_pocket *p, int *atoms16, int *atoms32);

@@ -60,10 +60,11 @@ struct dock_pocket {
   hipEvent_t ev_align[2] = {nullptr, nullptr};  // alignment start/end
   bool align_timed = false;
   unsigned long long *h_work = nullptr;  // pinned copy of the sweep's two work counters
-  // grouped classes on by default: (48, 96) measured fastest on the
-  // 100,000-ligand uneven batch (165 -> 125 ms) and the 10,000-ligand batch
-  // (20.2 -> 18.2 ms) among the bounds the autotuner tries
-  LaunchPlan plan{0, 0, 16, 48, 96};
+  // grouped classes on by default: (64, 128) measured fastest among the
+  // bounds the autotuner tries on the 100,000-ligand uneven batch (170 ms
+  // one item per wave -> 95 ms) and on the 10,000-ligand batch (20.3 ->
+  // 14.6 ms)
+  LaunchPlan plan{0, 0, 16, 64, 128};
   void *scratch = nullptr;    // this device's copy of the static workspace
   std::vector<float> host_grid;  // host copy of the grid, made on first use (hybrid calls)
   HybridCache hybrid;            // the hybrid entry point's streams and buffers

@@ -33,7 +33,10 @@ namespace dock {
 template <int G> constexpr int kGroupRing = 4 * G;
 template <int G> constexpr int kGroupChunk = 2 * G;
 constexpr int kGroupScoreTiles = 2;  // compacted G-step tiles scored per full pass
-constexpr int kWavePairCap = 512;
+constexpr int kWavePairCap = 384;
+// moving atoms whose voxel-unit bases a group holds at once (half its lanes:
+// LDS is what bounds the resident waves)
+template <int G> constexpr int kGroupBasisAtoms = G / 2;
 static_assert(kGroupChunk<16> + kGroupScoreTiles * 16 <= kGroupRing<16>, "ring too small");
 static_assert(kGroupChunk<32> + kGroupScoreTiles * 32 <= kGroupRing<32>, "ring too small");
 
@@ -47,7 +50,7 @@ __host__ __device__ inline int round16(int b) { return (b + 15) / 16 * 16; }
 //            static atom Q[p] -> m + p, axis atoms -1,
 //            AXU (float4 [NG][2]) each group's axis point and unit bond axis
 //   scratch: one block per group, contiguous: the moving atoms' voxel-unit
-//            bases (float [9][G]) and the ring of compacted steps (int16
+//            bases (float [9][G / 2]) and the ring of compacted steps (int16
 //            [4G]) while scoring; the moving atoms' values for the step-0
 //            score; during the bump test all of it is the wave's kept-pair
 //            list (int [kWavePairCap])
@@ -61,7 +64,7 @@ __host__ __device__ inline int group_shared_bytes(int nmax) {
 }
 template <int G>
 __host__ __device__ constexpr int group_scratch_bytes() {
-  return (9 * G * 4 + kGroupRing<G> * 2 + 15) / 16 * 16;
+  return (9 * kGroupBasisAtoms<G> * 4 + kGroupRing<G> * 2 + 15) / 16 * 16;
 }
 static_assert(group_scratch_bytes<16>() >= 4 * kGroupMaxAtoms16, "scratch too small");
 static_assert(group_scratch_bytes<32>() >= 4 * kGroupMaxAtoms32, "scratch too small");
@@ -101,7 +104,7 @@ struct GroupLds {
     PL = (int *)scr0;
     char *scr = scr0 + gid * group_scratch_bytes<G>();
     B = (float *)scr;
-    CK = (int16_t *)(scr + 9 * G * 4);
+    CK = (int16_t *)(scr + 9 * kGroupBasisAtoms<G> * 4);
     regions = scr0 + (kWave / G) * group_scratch_bytes<G>();
     region = group_region_bytes<G>(nmax, S);
     X = group_X(gid);
@@ -168,24 +171,25 @@ __device__ __forceinline__ uint64_t group_max_u64(uint64_t v) {
   return ((uint64_t)hi << 32) | lo;
 }
 
-// Scores of the lane's TC compacted steps kk (-1: none) -- static score plus
-// the moving atoms' values in list order, as rotamer_scores computes them.
-// Voxel-unit rotation bases of moving atoms c0 .. c0 + G - 1 into the
-// group's B (one atom per lane).
+// Voxel-unit rotation bases of moving atoms c0 .. c0 + GB - 1 into the
+// group's B (one atom per lane of the group's first GB lanes).
 template <int G>
 __device__ __forceinline__ void group_bases(const GroupLds<G> &W, const Grp<G> &g, int m, int c0,
                                             float4 xa, float3 u, const GridView &GV) {
-  if (c0 + g.gl < m) {
+  constexpr int GB = kGroupBasisAtoms<G>;
+  if (g.gl < GB && c0 + g.gl < m) {
     const Cyl c = cyl_of(W.X[W.M[c0 + g.gl]], xa, u);
     const VoxBasis vb = voxel_basis(rot_basis(c, xa, u), GV);
     float *B = W.B + g.gl;
-    B[0 * G] = vb.px, B[1 * G] = vb.py, B[2 * G] = vb.pz;
-    B[3 * G] = vb.ex, B[4 * G] = vb.ey, B[5 * G] = vb.ez;
-    B[6 * G] = vb.fx, B[7 * G] = vb.fy, B[8 * G] = vb.fz;
+    B[0 * GB] = vb.px, B[1 * GB] = vb.py, B[2 * GB] = vb.pz;
+    B[3 * GB] = vb.ex, B[4 * GB] = vb.ey, B[5 * GB] = vb.ez;
+    B[6 * GB] = vb.fx, B[7 * GB] = vb.fy, B[8 * GB] = vb.fz;
   }
 }
 
-// cached: m <= G and B already holds the bases (written once per rotamer
+// Scores of the lane's TC compacted steps kk (-1: none) -- static score plus
+// the moving atoms' values in list order, as rotamer_scores computes them.
+// cached: m <= GB and B already holds the bases (written once per rotamer
 // step and kept across its passes).
 template <int G, int TC>
 __device__ __forceinline__ void group_scores(const GroupLds<G> &W, const Grp<G> &g, int m,
@@ -196,16 +200,17 @@ __device__ __forceinline__ void group_scores(const GroupLds<G> &W, const Grp<G> 
                                              float (&score)[TC]) {
 #pragma unroll
   for (int t = 0; t < TC; ++t) score[t] = cst;
-  for (int c0 = 0; c0 < m; c0 += G) {
+  constexpr int GB = kGroupBasisAtoms<G>;
+  for (int c0 = 0; c0 < m; c0 += GB) {
     if (!cached) {
       group_bases<G>(W, g, m, c0, xa, u, GV);
       wave_lds_sync();
     }
-    const int cnt = min(G, m - c0);
+    const int cnt = min(GB, m - c0);
     auto gather = [&](int tt, float(&v)[TC]) {
       const float *B = W.B + tt;  // group-uniform address: broadcast reads
-      const VoxBasis vb{B[0 * G], B[1 * G], B[2 * G], B[3 * G], B[4 * G],
-                        B[5 * G], B[6 * G], B[7 * G], B[8 * G]};
+      const VoxBasis vb{B[0 * GB], B[1 * GB], B[2 * GB], B[3 * GB], B[4 * GB],
+                        B[5 * GB], B[6 * GB], B[7 * GB], B[8 * GB]};
       uint32_t off[TC];
 #pragma unroll
       for (int t = 0; t < TC; ++t) off[t] = basis_voxel_offset(GS, vb, cc[t], ss[t]);
@@ -417,9 +422,9 @@ __global__ void __launch_bounds__(WAVES *kWave)
         // one pass of one or two tiles.  Passes run wave-wide; each group
         // reads its own next entries.  Unread entries stay below 2G after a
         // pass and below 4G after an append, so the ring never overwrites them.
-        // a step whose moving atoms fit one group computes their bases once
+        // a step whose moving atoms fit the group's basis slots computes their bases once
         // (the pair list, which shared this scratch, is done)
-        const bool cached = m <= G;
+        const bool cached = m <= kGroupBasisAtoms<G>;
         if (cached) group_bases<G>(W, g, m, 0, xa, u, GV);
         uint64_t best = 0ull;
         int nv = 0;       // entries this group has appended (same in its lanes)
@@ -489,9 +494,10 @@ __global__ void __launch_bounds__(WAVES *kWave)
             // passes when they were cached (the same values), else computed
             VoxBasis vb;
             if (cached) {
+              constexpr int GB = kGroupBasisAtoms<G>;
               const float *B = W.B + g.gl;
-              vb = VoxBasis{B[0 * G], B[1 * G], B[2 * G], B[3 * G], B[4 * G],
-                            B[5 * G], B[6 * G], B[7 * G], B[8 * G]};
+              vb = VoxBasis{B[0 * GB], B[1 * GB], B[2 * GB], B[3 * GB], B[4 * GB],
+                            B[5 * GB], B[6 * GB], B[7 * GB], B[8 * GB]};
             } else {
               vb = voxel_basis(bs, GV);
             }
