@@ -247,14 +247,14 @@ static unsigned grid_for(int n_items, int n_cu) {
 hipError_t enqueue_learned_begin(const LearnedArgs &A, int n_cu, hipStream_t st) {
   if (A.sw.n_items <= 0) return hipSuccess;
   hipLaunchKernelGGL(learned_begin_kernel, dim3(grid_for(A.sw.n_items, n_cu)), dim3(kWave),
-                     wave_lds_bytes(A.nmax, false, kLearnedTiles), st, A);
+                     wave_lds_bytes(A.nmax, false, kLearnedTiles, A.sw.S), st, A);
   return hipGetLastError();
 }
 
 hipError_t enqueue_learned_step(const LearnedArgs &A, int step, int n_cu, hipStream_t st) {
   if (A.sw.n_items <= 0) return hipSuccess;
   hipLaunchKernelGGL(learned_step_kernel, dim3(grid_for(A.sw.n_items, n_cu)), dim3(kWave),
-                     wave_lds_bytes(A.nmax, false, kLearnedTiles), st, A, step);
+                     wave_lds_bytes(A.nmax, false, kLearnedTiles, A.sw.S), st, A, step);
   return hipGetLastError();
 }
 

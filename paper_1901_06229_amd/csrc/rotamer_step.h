@@ -28,22 +28,20 @@ namespace dock {
 constexpr int kPairCap = 128;  // LDS pair-list entries per wave
 
 // Most compacted tiles scored in one pass for a group of TG tiles: two (fewer
-// live registers, 6 waves per SIMD instead of 4) except for 6-tile groups
-// (257-384 steps), which score all six in one pass.  Measured on gfx950: two-
+// live registers, 6 waves per SIMD instead of 4).  Measured on gfx950: two-
 // tile passes take 4096 steps over 32-atom ligands from 4.02 M to 4.23 M
-// ligands/s end to end, but slow 360 steps over 100-250-atom ligands (LDS
-// already limits residency) from 53.1 to 55.9 ms.  Results are the same
-// either way.
+// ligands/s end to end.  Results are the same either way.
 template <int TG>
-constexpr int kMaxScoreTiles = TG == 6 ? 6 : (TG < 2 ? TG : 2);
+constexpr int kMaxScoreTiles = TG < 2 ? TG : 2;
 
 __host__ __device__ inline int wave_head_bytes(int nmax) {
-  // X, C (float4), Q, M (int16), mov (uint8)
-  const int b = nmax * 16 * 2 + nmax * 2 * 2 + nmax;
+  // X (float4), ZR (float2), Q, M (int16), mov (uint8)
+  const int b = nmax * 16 + nmax * 8 + nmax * 2 * 2 + nmax;
   return (b + 15) / 16 * 16;
 }
 
-constexpr int kMaskWords = 128;   // invalid-angle bitmask of up to 4096 steps
+// invalid-angle bitmask of S steps (S <= 4096)
+__host__ __device__ inline int mask_bytes(int S) { return (4 * ((S + 31) / 32) + 15) / 16 * 16; }
 constexpr int kBasisFloats = 9;   // voxel-space rotation basis of one atom
 constexpr int kBasisBytes = kWave * kBasisFloats * 4;  // 64 atoms, component-major
 
@@ -56,13 +54,14 @@ __host__ __device__ constexpr int wave_scratch_bytes(bool lds_basis, int tg) {
              : kPairCap * 4;
 }
 
-__host__ __device__ inline int wave_lds_bytes(int nmax, bool lds_basis, int tg) {
-  return wave_head_bytes(nmax) + wave_scratch_bytes(lds_basis, tg) + kMaskWords * 4;
+__host__ __device__ inline int wave_lds_bytes(int nmax, bool lds_basis, int tg, int S) {
+  return wave_head_bytes(nmax) + wave_scratch_bytes(lds_basis, tg) + mask_bytes(S);
 }
 
 struct WaveLds {
   float4 *X;     // pose: x, y, z, voxel value
-  float4 *C;     // cylindrical coordinates about the current axis: r, z
+  float2 *ZR;    // axial coordinate and |r| about the current axis (the radial
+                 // vector itself is recomputed from X where it is needed)
   int16_t *Q;    // static cross set of the rotamer
   int16_t *M;    // moving set of the rotamer
   uint8_t *mov;  // moving flags
@@ -73,8 +72,8 @@ struct WaveLds {
   uint32_t *BM;  // bit k set: angle step k bumps
   __device__ WaveLds(char *base, int nmax, bool lds_basis, int tg) {
     X = (float4 *)base;
-    C = X + nmax;
-    Q = (int16_t *)(C + nmax);
+    ZR = (float2 *)(X + nmax);
+    Q = (int16_t *)(ZR + nmax);
     M = Q + nmax;
     mov = (uint8_t *)(M + nmax);
     char *scr = base + wave_head_bytes(nmax);
@@ -161,7 +160,7 @@ __device__ __forceinline__ RotState rotamer_setup(const WaveLds &W, int n, const
       if (!moving) v = xi.w;
       st = !moving && i != T.ra && i != T.rb;
       const Cyl c = cyl_of(xi, R.xa, R.u);
-      W.C[i] = make_float4(c.rx, c.ry, c.rz, c.z);
+      W.ZR[i] = make_float2(c.z, cyl_radius(make_float4(c.rx, c.ry, c.rz, c.z)));
     }
     cst = chunk_sum_wave(cst, v, base, n);
     const uint64_t mask = wave_ballot(st);
@@ -295,7 +294,9 @@ __device__ __forceinline__ void mark_kept_pairs(const WaveLds &W, const RotState
   const float steps_per_rad = (float)S * 0.15915494309189535f;  // S / (2 pi)
   for (int e = lane; e < cnt; e += kWave) {
     const int ij = W.PI[e];
-    mark_pair_arc(W.BM, W.C[ij >> 16], W.C[ij & 0xFFFF], R.u, r2, S, steps_per_rad);
+    const Cyl ci = cyl_of(W.X[ij >> 16], R.xa, R.u), cj = cyl_of(W.X[ij & 0xFFFF], R.xa, R.u);
+    mark_pair_arc(W.BM, make_float4(ci.rx, ci.ry, ci.rz, ci.z),
+                  make_float4(cj.rx, cj.ry, cj.rz, cj.z), R.u, r2, S, steps_per_rad);
   }
 }
 
@@ -329,17 +330,17 @@ __device__ __forceinline__ int rotamer_bump_mask(const WaveLds &W, const RotStat
     float zl = 0.f, rl = 0.f;
     if (lane < mc) {
       il = W.M[ib + lane];
-      const float4 ci = W.C[il];
-      zl = ci.w;
-      rl = cyl_radius(ci);
+      const float2 zr = W.ZR[il];
+      zl = zr.x;
+      rl = zr.y;
     }
     for (int jb = 0; jb < R.q; jb += kWave) {
       const bool jin = jb + lane < R.q;
       const int j = jin ? W.Q[jb + lane] : 0;
-      const float4 cj = W.C[j];
+      const float2 zrj = W.ZR[j];
       // lanes past the static list get an infinite radius: their bound is
       // +inf and never below thr
-      const float zj = cj.w, rj = jin ? cyl_radius(cj) : __builtin_inff();
+      const float zj = zrj.x, rj = jin ? zrj.y : __builtin_inff();
       for (int t = 0; t < mc; ++t) {
         const float dz = lane_bcast(zl, t) - zj;
         const float dr = lane_bcast(rl, t) - rj;
@@ -411,8 +412,8 @@ __device__ __forceinline__ void rotamer_scores(const WaveLds &W, const RotState 
     float b0 = 0.f, b1 = 0.f, b2 = 0.f, b3 = 0.f, b4 = 0.f, b5 = 0.f, b6 = 0.f, b7 = 0.f,
           b8 = 0.f;
     if (c0 + lane < R.m) {
-      const float4 ci = W.C[W.M[c0 + lane]];
-      const VoxBasis vb = voxel_basis(rot_basis(Cyl{ci.x, ci.y, ci.z, ci.w}, R.xa, R.u), G);
+      const Cyl ci = cyl_of(W.X[W.M[c0 + lane]], R.xa, R.u);
+      const VoxBasis vb = voxel_basis(rot_basis(ci, R.xa, R.u), G);
       b0 = vb.px, b1 = vb.py, b2 = vb.pz;
       b3 = vb.ex, b4 = vb.ey, b5 = vb.ez;
       b6 = vb.fx, b7 = vb.fy, b8 = vb.fz;
@@ -557,8 +558,7 @@ __device__ __forceinline__ void rotamer_apply(const WaveLds &W, const RotState &
   const GridScaled GS = grid_scaled(G);
   for (int t = lane; t < R.m; t += kWave) {
     const int i = W.M[t];
-    const float4 ci = W.C[i];
-    const RotBasis bs = rot_basis(Cyl{ci.x, ci.y, ci.z, ci.w}, R.xa, R.u);
+    const RotBasis bs = rot_basis(cyl_of(W.X[i], R.xa, R.u), R.xa, R.u);
     const float3 y = rot_apply(bs, c, s);
     const uint32_t off = basis_voxel_offset(GS, voxel_basis(bs, G), c, s);
     W.X[i] = make_float4(y.x, y.y, y.z, G.grid[off >> 2]);
@@ -577,13 +577,13 @@ __device__ __forceinline__ float rotamer_feature(const WaveLds &W, const RotStat
   float sx = 0.f, sy = 0.f, sz = 0.f, rmax = 0.f, zmin = 3.0e38f, zmax = -3.0e38f;
   for (int t = lane; t < R.m; t += kWave) {
     const int i = W.M[t];
-    const float4 ci = W.C[i];
-    sx += ci.x;
-    sy += ci.y;
-    sz += ci.z;
-    rmax = fmaxf(rmax, cyl_radius(W.C[i]));
-    zmin = fminf(zmin, ci.w);
-    zmax = fmaxf(zmax, ci.w);
+    const Cyl ci = cyl_of(W.X[i], R.xa, R.u);
+    sx += ci.rx;
+    sy += ci.ry;
+    sz += ci.rz;
+    rmax = fmaxf(rmax, W.ZR[i].y);
+    zmin = fminf(zmin, ci.z);
+    zmax = fmaxf(zmax, ci.z);
   }
   sx = wave_sum(sx);
   sy = wave_sum(sy);

@@ -45,7 +45,7 @@ __global__ void __launch_bounds__(WAVES *kWave)
   extern __shared__ float4 dyn_lds[];
   const int wv = threadIdx.x / kWave;
   const int lane = threadIdx.x % kWave;
-  const WaveLds W((char *)dyn_lds + (size_t)wv * wave_lds_bytes(nmax, LB, TG), nmax, LB, TG);
+  const WaveLds W((char *)dyn_lds + (size_t)wv * wave_lds_bytes(nmax, LB, TG, A.S), nmax, LB, TG);
   const GridView G = A.grid;
   const GridScaled GS = grid_scaled(G);
   const __amdgpu_buffer_rsrc_t grsrc = grid_rsrc(G);
@@ -163,9 +163,9 @@ __global__ void __launch_bounds__(WAVES *kWave)
 
 // Resident blocks per CU of one instantiation (0: its LDS exceeds a block's).
 template <int WAVES, int TG, bool LB, bool EMIT = false>
-static hipError_t pruned_occupancy(int nmax, int blocks_per_cu, int *bpc) {
+static hipError_t pruned_occupancy(int nmax, int S, int blocks_per_cu, int *bpc) {
   *bpc = 0;
-  const size_t shmem = (size_t)WAVES * wave_lds_bytes(nmax, LB, TG);
+  const size_t shmem = (size_t)WAVES * wave_lds_bytes(nmax, LB, TG, S);
   if (shmem > 65536) return hipSuccess;
   int occ = 0;
   hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
@@ -179,7 +179,7 @@ static hipError_t pruned_occupancy(int nmax, int blocks_per_cu, int *bpc) {
 template <int WAVES, int TG, bool LB, bool EMIT = false>
 static hipError_t launch_pruned_lb(const SweepArgs &A, int nmax, int bpc, int n_cu,
                                    hipStream_t st) {
-  const size_t shmem = (size_t)WAVES * wave_lds_bytes(nmax, LB, TG);
+  const size_t shmem = (size_t)WAVES * wave_lds_bytes(nmax, LB, TG, A.S);
   const int64_t need = (A.n_items + WAVES - 1) / WAVES;
   int64_t grid = (int64_t)(bpc > 0 ? bpc : 1) * n_cu;
   if (grid > need) grid = need;
@@ -195,10 +195,10 @@ template <int WAVES, int TG>
 struct PrunedChoice {
   int bpc = 0;
   bool lds_basis = false;
-  hipError_t query(int nmax, int blocks_per_cu) {
+  hipError_t query(int nmax, int S, int blocks_per_cu) {
     int occ_reg = 0, occ_lds = 0;
-    hipError_t e = pruned_occupancy<WAVES, TG, false>(nmax, blocks_per_cu, &occ_reg);
-    if (e == hipSuccess) e = pruned_occupancy<WAVES, TG, true>(nmax, blocks_per_cu, &occ_lds);
+    hipError_t e = pruned_occupancy<WAVES, TG, false>(nmax, S, blocks_per_cu, &occ_reg);
+    if (e == hipSuccess) e = pruned_occupancy<WAVES, TG, true>(nmax, S, blocks_per_cu, &occ_lds);
     lds_basis = occ_lds >= occ_reg && occ_lds > 0;
     bpc = lds_basis ? occ_lds : occ_reg;
     return e;
@@ -225,9 +225,9 @@ static hipError_t launch_pruned_tg(const SweepArgs &A, int nmax, const LaunchPla
   PrunedChoice<1, TG> c1;
   const int w = plan.waves_per_block;
   hipError_t e = hipSuccess;
-  if (w == 0 || w == 4) e = c4.query(nmax, plan.blocks_per_cu);
-  if (e == hipSuccess && (w == 0 || w == 2)) e = c2.query(nmax, plan.blocks_per_cu);
-  if (e == hipSuccess && (w == 0 || w == 1)) e = c1.query(nmax, plan.blocks_per_cu);
+  if (w == 0 || w == 4) e = c4.query(nmax, A.S, plan.blocks_per_cu);
+  if (e == hipSuccess && (w == 0 || w == 2)) e = c2.query(nmax, A.S, plan.blocks_per_cu);
+  if (e == hipSuccess && (w == 0 || w == 1)) e = c1.query(nmax, A.S, plan.blocks_per_cu);
   if (e != hipSuccess) return e;
   if (w == 4) return c4.launch(A, nmax, n_cu, st);
   if (w == 2) return c2.launch(A, nmax, n_cu, st);
@@ -259,7 +259,7 @@ hipError_t enqueue_sweep_pruned(const SweepArgs &A, int max_atoms, const LaunchP
   if (A.emit_x) {  // profile emission: S == 256 (checked by the caller)
     if (T != 4) return hipErrorInvalidValue;
     int bpc = 0;
-    hipError_t e = pruned_occupancy<4, 4, false, true>(nmax, plan.blocks_per_cu, &bpc);
+    hipError_t e = pruned_occupancy<4, 4, false, true>(nmax, A.S, plan.blocks_per_cu, &bpc);
     if (e != hipSuccess) return e;
     if (bpc < 1) return hipErrorInvalidValue;
     return launch_pruned_lb<4, 4, false, true>(A, nmax, bpc, n_cu, st);
