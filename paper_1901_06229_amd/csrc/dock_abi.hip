@@ -60,11 +60,11 @@ struct dock_pocket {
   hipEvent_t ev_align[2] = {nullptr, nullptr};  // alignment start/end
   bool align_timed = false;
   unsigned long long *h_work = nullptr;  // pinned copy of the sweep's two work counters
-  // grouped classes on by default: (64, 128) measured fastest among the
-  // bounds the autotuner tries on the 100,000-ligand uneven batch (170 ms
-  // one item per wave -> 95 ms) and on the 10,000-ligand batch (20.3 ->
-  // 14.6 ms)
-  LaunchPlan plan{0, 0, 16, 64, 128};
+  // grouped classes on by default: (80, 128) measured fastest among the
+  // bounds the autotuner tries on the 100,000-ligand uneven batch (135 ms
+  // one item per wave -> 87 ms) and on the 10,000-ligand batch (20.6 ->
+  // 13.6 ms)
+  LaunchPlan plan{0, 0, 16, 80, 128};
   void *scratch = nullptr;    // this device's copy of the static workspace
   std::vector<float> host_grid;  // host copy of the grid, made on first use (hybrid calls)
   HybridCache hybrid;            // the hybrid entry point's streams and buffers
@@ -701,7 +701,7 @@ int dock_autotune(dock_pocket *p, const dock_ligands *ligs, const float *orient,
   const int waves[] = {1, 2, 4};
   const int claims[] = {4, 16, 32, 64};
   // size classes docked in groups: none, and four (16-lane, 32-lane) bounds
-  const int groups[][2] = {{0, 0}, {40, 80}, {48, 96}, {56, 112}, {64, 128}};
+  const int groups[][2] = {{0, 0}, {48, 96}, {64, 128}, {80, 128}, {96, 128}};
   LaunchPlan best_plan = p->plan;
   float best_ms = 0.0f;
   int n = 0;

@@ -14,7 +14,7 @@ constexpr int kLptBuckets = 128;  // cost buckets per size class
 // per wave (32-lane groups), the rest one per wave; each class is a
 // contiguous range of the cost-sorted ligand order with its own kernel.
 constexpr int kClasses = 3;
-constexpr int kGroupMaxAtoms16 = 64;   // largest ligands the 16-lane class may take
+constexpr int kGroupMaxAtoms16 = 96;   // largest ligands the 16-lane class may take
 constexpr int kGroupMaxAtoms32 = 128;  // and the 32-lane class
 // small integer block at the head of the workspace:
 //   [0] work-queue counter of the one-item-per-wave sweep, [1] rejected-

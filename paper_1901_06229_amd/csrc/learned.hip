@@ -64,7 +64,7 @@ __device__ __forceinline__ void write_step_inputs(const LearnedArgs &A, const Wa
                                                   const RotState &RS, int item, int lane) {
   const GridView G = A.sw.grid;
   A.feat[(size_t)item * 64 + lane] = f32_to_bf16(rotamer_feature(W, RS, G, lane));
-  rotamer_bump_mask(W, RS, A.sw.r2, A.sw.r2 + kPruneMargin, A.sw.S, lane);
+  rotamer_bump_mask(W, RS, A.sw.r2, zr_threshold(A.sw.r2 + kPruneMargin), A.sw.S, lane);
   // lane t writes the valid mask of tile t; steps from S on are not angles
   if (lane < A.tiles) {
     const uint64_t bumps = ((uint64_t)W.BM[2 * lane + 1] << 32) | (uint64_t)W.BM[2 * lane];

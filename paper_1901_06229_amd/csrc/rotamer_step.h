@@ -10,8 +10,9 @@
 //     D' - 2 (cos(theta) A + sin(theta) B), A = r_i.r_j, B = u.(r_i x r_j),
 //     D' = |r_i|^2 + |r_j|^2 + (z_i - z_j)^2, never below
 //     (|r_i| - |r_j|)^2 + (z_i - z_j)^2.  Pairs whose bound clears
-//     r_bump^2 + kPruneMargin cannot bump at any angle and are dropped; each
-//     kept pair's clash arc is marked into a bitmask of the S steps.
+//     r_bump^2 + kPruneMargin cannot bump at any angle and are dropped (the
+//     bound is taken in fixed point, pack_zr below); each kept pair's clash
+//     arc is marked into a bitmask of the S steps.
 // Scoring takes TG angle slots per lane given by their (cos, sin); the slot-
 // to-angle mapping is the caller's (compacted valid steps for the sweep,
 // nominated steps for the learned proposal).
@@ -27,6 +28,38 @@ namespace dock {
 
 constexpr int kPairCap = 128;  // LDS pair-list entries per wave
 
+// The pair bound in fixed point.  An atom's (z, |r|) is stored as two int16
+// in units of 1/256 Angstrom (truncated, saturated; z in the low half), and a
+// pair's bound (dz^2 + dr^2) is one saturating packed subtract and one
+// saturating integer dot product.  Truncation moves each coordinate by less
+// than one unit and saturation only shortens differences, so the quantised
+// distance bound stays below 256 times the float bound plus 2 sqrt(2) units.
+// With the threshold widened by 3 units the test keeps every pair the float
+// bound keeps (the few extra ones have empty clash arcs, so results do not
+// change), in 4 bytes of LDS per atom instead of 8.
+typedef short zr2_t __attribute__((ext_vector_type(2)));
+constexpr float kZrUnits = 256.0f;
+
+__device__ __forceinline__ uint32_t pack_zr(float z, float r) {
+  const int zi = (int)__builtin_amdgcn_fmed3f(z * kZrUnits, -32768.0f, 32767.0f);
+  const int ri = (int)fminf(r * kZrUnits, 32767.0f);  // r >= 0
+  return __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pk_i16(zi, ri));
+}
+
+// quantised squared distance bound of two packed atoms (units^2)
+__device__ __forceinline__ int zr_bound(uint32_t a, uint32_t b) {
+  const zr2_t d = __builtin_elementwise_sub_sat(__builtin_bit_cast(zr2_t, a),
+                                                __builtin_bit_cast(zr2_t, b));
+  return __builtin_amdgcn_sdot2(d, d, 0, true);
+}
+
+// Pairs with zr_bound <= this may clash, for the float threshold thr
+// (r_bump^2 + kPruneMargin).  Saturates to keep-everything.
+__device__ __forceinline__ int zr_threshold(float thr) {
+  const double b = sqrt((double)thr) * (double)kZrUnits + 3.0;
+  return b * b >= 2147483647.0 ? 2147483647 : (int)(b * b) + 1;
+}
+
 // Most compacted tiles scored in one pass for a group of TG tiles: two (fewer
 // live registers, 6 waves per SIMD instead of 4).  Measured on gfx950: two-
 // tile passes take 4096 steps over 32-atom ligands from 4.02 M to 4.23 M
@@ -35,8 +68,8 @@ template <int TG>
 constexpr int kMaxScoreTiles = TG < 2 ? TG : 2;
 
 __host__ __device__ inline int wave_head_bytes(int nmax) {
-  // X (float4), ZR (float2), Q, M (int16), mov (uint8)
-  const int b = nmax * 16 + nmax * 8 + nmax * 2 * 2 + nmax;
+  // X (float4), ZR (packed int16 pair), Q, M (int16), mov (uint8)
+  const int b = nmax * 16 + nmax * 4 + nmax * 2 * 2 + nmax;
   return (b + 15) / 16 * 16;
 }
 
@@ -60,8 +93,9 @@ __host__ __device__ inline int wave_lds_bytes(int nmax, bool lds_basis, int tg, 
 
 struct WaveLds {
   float4 *X;     // pose: x, y, z, voxel value
-  float2 *ZR;    // axial coordinate and |r| about the current axis (the radial
-                 // vector itself is recomputed from X where it is needed)
+  uint32_t *ZR;  // axial coordinate and |r| about the current axis, packed
+                 // for the pair bound (pack_zr); the cylindrical coordinates
+                 // themselves are recomputed from X where they are needed
   int16_t *Q;    // static cross set of the rotamer
   int16_t *M;    // moving set of the rotamer
   uint8_t *mov;  // moving flags
@@ -72,7 +106,7 @@ struct WaveLds {
   uint32_t *BM;  // bit k set: angle step k bumps
   __device__ WaveLds(char *base, int nmax, bool lds_basis, int tg) {
     X = (float4 *)base;
-    ZR = (float2 *)(X + nmax);
+    ZR = (uint32_t *)(X + nmax);
     Q = (int16_t *)(ZR + nmax);
     M = Q + nmax;
     mov = (uint8_t *)(M + nmax);
@@ -160,7 +194,7 @@ __device__ __forceinline__ RotState rotamer_setup(const WaveLds &W, int n, const
       if (!moving) v = xi.w;
       st = !moving && i != T.ra && i != T.rb;
       const Cyl c = cyl_of(xi, R.xa, R.u);
-      W.ZR[i] = make_float2(c.z, cyl_radius(make_float4(c.rx, c.ry, c.rz, c.z)));
+      W.ZR[i] = pack_zr(c.z, cyl_radius(make_float4(c.rx, c.ry, c.rz, c.z)));
     }
     cst = chunk_sum_wave(cst, v, base, n);
     const uint64_t mask = wave_ballot(st);
@@ -305,7 +339,7 @@ __device__ __forceinline__ void mark_kept_pairs(const WaveLds &W, const RotState
 // bound does not clear r_bump, and mark each kept pair's clash arc.  Returns
 // the number of kept pairs.
 __device__ __forceinline__ int rotamer_bump_mask(const WaveLds &W, const RotState &R, float r2,
-                                                 float thr, int S, int lane) {
+                                                 int thr_q, int S, int lane) {
   for (int w = lane; w < (S + 31) / 32; w += kWave) W.BM[w] = 0u;
   int np = 0, kept = 0;
   // appends the lane's pair if act (mask: the wave's act bits); flushes the
@@ -327,26 +361,20 @@ __device__ __forceinline__ int rotamer_bump_mask(const WaveLds &W, const RotStat
     // wave-uniform; kept in a scalar register so the pair loop tests it there
     const int mc = __builtin_amdgcn_readfirstlane(min(kWave, R.m - ib));
     int il = 0;
-    float zl = 0.f, rl = 0.f;
+    uint32_t zl = 0u;
     if (lane < mc) {
       il = W.M[ib + lane];
-      const float2 zr = W.ZR[il];
-      zl = zr.x;
-      rl = zr.y;
+      zl = W.ZR[il];
     }
     for (int jb = 0; jb < R.q; jb += kWave) {
       const bool jin = jb + lane < R.q;
       const int j = jin ? W.Q[jb + lane] : 0;
-      const float2 zrj = W.ZR[j];
-      // lanes past the static list get an infinite radius: their bound is
-      // +inf and never below thr
-      const float zj = zrj.x, rj = jin ? zrj.y : __builtin_inff();
+      const uint32_t zrj = W.ZR[j];
+      // lanes past the static list keep nothing (bounds are never negative)
+      const int tj = jin ? thr_q : -1;
       for (int t = 0; t < mc; ++t) {
-        const float dz = lane_bcast(zl, t) - zj;
-        const float dr = lane_bcast(rl, t) - rj;
-        const float lb = fmaf(dr, dr, dz * dz);
-        // the ballot is the compare's own lane mask (4: ordered less-than)
-        push(__builtin_amdgcn_fcmpf(lb, thr, 4), lb < thr,
+        const int lb = zr_bound((uint32_t)__builtin_amdgcn_readlane((int)zl, t), zrj);
+        push(wave_ballot(lb <= tj), lb <= tj,
              (__builtin_amdgcn_readlane(il, t) << 16) | j);
       }
     }
@@ -581,7 +609,7 @@ __device__ __forceinline__ float rotamer_feature(const WaveLds &W, const RotStat
     sx += ci.rx;
     sy += ci.ry;
     sz += ci.rz;
-    rmax = fmaxf(rmax, W.ZR[i].y);
+    rmax = fmaxf(rmax, cyl_radius(make_float4(ci.rx, ci.ry, ci.rz, ci.z)));
     zmin = fminf(zmin, ci.z);
     zmax = fmaxf(zmax, ci.z);
   }

@@ -55,8 +55,9 @@ __host__ __device__ inline int round16(int b) { return (b + 15) / 16 * 16; }
 //            score; during the bump test all of it is the wave's kept-pair
 //            list (int [kWavePairCap])
 //   groups:  X (float4 [nmax]) pose, x y z and voxel value
-//            ZRc (float2 [nmax]) axial coordinate and |r| about the bond axis
-//            of the moving atoms (in list order), then of the static ones
+//            ZRc (uint32 [nmax]) axial coordinate and |r| about the bond axis,
+//            packed for the pair bound (pack_zr), of the moving atoms (in
+//            list order), then of the static ones
 //            BM (uint32 [(S + 31) / 32]) bump bits
 template <int G>
 __host__ __device__ inline int group_shared_bytes(int nmax) {
@@ -72,7 +73,7 @@ static_assert((kWave / 16) * group_scratch_bytes<16>() >= 4 * kWavePairCap, "pai
 static_assert((kWave / 32) * group_scratch_bytes<32>() >= 4 * kWavePairCap, "pair list");
 template <int G>
 __host__ __device__ inline int group_region_bytes(int nmax, int S) {
-  return nmax * 16 + nmax * 8 + round16(4 * ((S + 31) / 32));
+  return nmax * 16 + nmax * 4 + round16(4 * ((S + 31) / 32));
 }
 template <int G>
 __host__ __device__ inline int group_wave_bytes(int nmax, int S) {
@@ -90,7 +91,7 @@ struct GroupLds {
   int nmax;
   // this group's
   float4 *X;
-  float2 *ZRc;
+  uint32_t *ZRc;
   float *B;
   int16_t *CK;
   uint32_t *BM;
@@ -108,14 +109,14 @@ struct GroupLds {
     regions = scr0 + (kWave / G) * group_scratch_bytes<G>();
     region = group_region_bytes<G>(nmax, S);
     X = group_X(gid);
-    ZRc = (float2 *)(X + nmax);
+    ZRc = (uint32_t *)(X + nmax);
     BM = group_BM(gid);
   }
   __device__ __forceinline__ float4 *group_X(int g) const {
     return (float4 *)(regions + g * region);
   }
   __device__ __forceinline__ uint32_t *group_BM(int g) const {
-    return (uint32_t *)(regions + g * region + nmax * 24);
+    return (uint32_t *)(regions + g * region + nmax * 20);
   }
 };
 
@@ -259,7 +260,7 @@ __global__ void __launch_bounds__(WAVES *kWave)
   const __amdgpu_buffer_rsrc_t grsrc = grid_rsrc(GV);
   const int O = A.n_orient;
   const float r2 = A.r2;
-  const float thr = r2 + kPruneMargin;
+  const int thr_q = zr_threshold(r2 + kPruneMargin);
   const float steps_per_rad = (float)S * 0.15915494309189535f;  // S / (2 pi)
   const int words = (S + 31) / 32;
   // bits of a 32-bit bump word below this lane's step, per G-step half
@@ -337,7 +338,7 @@ __global__ void __launch_bounds__(WAVES *kWave)
             const int sl = W.slot[i];
             if (sl >= 0) {
               const Cyl c = cyl_of(xi, xa, u);
-              W.ZRc[sl] = make_float2(c.z, cyl_radius(make_float4(c.rx, c.ry, c.rz, c.z)));
+              W.ZRc[sl] = pack_zr(c.z, cyl_radius(make_float4(c.rx, c.ry, c.rz, c.z)));
             }
             if (sl < 0 || sl >= m) v = xi.w;  // everything that does not move
           }
@@ -389,21 +390,18 @@ __global__ void __launch_bounds__(WAVES *kWave)
         for (int jb = 0; jb < q; jb += G) {
           const bool jin = jb + g.gl < q;
           const int j = jin ? W.Q[jb + g.gl] : 0;
-          const float2 zrj = W.ZRc[jin ? m + jb + g.gl : 0];
-          const float zj = zrj.x, rj = jin ? zrj.y : __builtin_inff();
+          const uint32_t zrj = W.ZRc[jin ? m + jb + g.gl : 0];
+          const int tj = jin ? thr_q : -1;  // lanes past the list keep nothing
           const int pj = (g.gid << 16) | j;
-          // the ballot is the compare's own lane mask (4: ordered less-than)
-          auto test = [&](const float2 mz, int t) {
-            const float dz = mz.x - zj;
-            const float dr = mz.y - rj;
-            const float lb = fmaf(dr, dr, dz * dz);
-            const uint64_t keep = __builtin_amdgcn_fcmpf(lb, thr, 4);
-            if (lb < thr) W.PL[lanes_before(keep, np)] = pj | (t << 8);
+          auto test = [&](const uint32_t mz, int t) {
+            const int lb = zr_bound(mz, zrj);
+            const uint64_t keep = wave_ballot(lb <= tj);
+            if (lb <= tj) W.PL[lanes_before(keep, np)] = pj | (t << 8);
             np += __popcll(keep);
           };
           int t = 0;
           for (; t + 1 < m; t += 2) {  // two moving atoms per turn, both reads first
-            const float2 mz0 = W.ZRc[t], mz1 = W.ZRc[t + 1];  // group-uniform: broadcasts
+            const uint32_t mz0 = W.ZRc[t], mz1 = W.ZRc[t + 1];  // group-uniform: broadcasts
             test(mz0, t);
             test(mz1, t + 1);
             if (np > kWavePairCap - 2 * kWave) flush();

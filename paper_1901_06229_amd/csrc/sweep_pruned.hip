@@ -52,7 +52,7 @@ __global__ void __launch_bounds__(WAVES *kWave)
   const int O = A.n_orient, S = A.S;
   const int T = (S + kWave - 1) / kWave;
   const float r2 = A.r2;
-  const float thr = r2 + kPruneMargin;
+  const int thr_q = zr_threshold(r2 + kPruneMargin);
   constexpr bool emit = EMIT;  // profile emission: S == 256, TG == 4
   uint64_t kept_pairs = 0, evals = 0;  // work counters of this wave
 
@@ -89,7 +89,7 @@ __global__ void __launch_bounds__(WAVES *kWave)
           A.emit_x[(kbase + step) * 64 + lane] = f32_to_bf16(rotamer_feature(W, RS, G, lane));
 
         // invalid steps of the rotamer, for all S steps at once
-        kept_pairs += (uint64_t)rotamer_bump_mask(W, RS, r2, thr, S, lane);
+        kept_pairs += (uint64_t)rotamer_bump_mask(W, RS, r2, thr_q, S, lane);
         const RotTopo topo_next = more ? topo_finish(A.lig, words_next, lane) : topo;
 
         uint64_t best = 0ull;

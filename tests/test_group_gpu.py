@@ -14,7 +14,7 @@ from tests.checker import check_batch
 pytestmark = pytest.mark.gpu
 
 NAMES = ("best_score", "best_orient", "angle_idx", "xyz", "all_scores", "all_angle_idx", "status")
-MAPPINGS = [(0, 0), (32, 64), (40, 80), (48, 96), (64, 128), (0, 96), (48, 0)]
+MAPPINGS = [(0, 0), (32, 64), (40, 80), (48, 96), (64, 128), (80, 128), (96, 128), (0, 96), (48, 0)]
 
 
 @pytest.fixture(scope="module")
@@ -64,7 +64,7 @@ def test_grouped_step_counts(pockets, S):
     ligs = synth.ligands(2, count=24, first=900)
     orient = synth.orientations(2, 9)
     ref = _run(h, ligs, orient, S, (0, 0))
-    got = _run(h, ligs, orient, S, (64, 128))
+    got = _run(h, ligs, orient, S, (80, 128))
     _same(got, ref, S)
 
 
@@ -85,20 +85,22 @@ def test_grouped_parity_with_reference(pockets):
 
 
 def test_grouped_passes_and_class_limits(pockets):
-    """Two passes, and ligands at exactly the class bounds (64 atoms in the
-    16-lane class, 128 in the 32-lane class), next to larger ones."""
+    """Two passes, and ligands at exactly the class bounds (64, 80 and 96
+    atoms in the 16-lane class, 128 in the 32-lane class), next to larger
+    ones."""
     p, h = pockets(3)
     all_ligs = synth.ligands(3, count=3000)
     n = np.diff(all_ligs.atom_offset)
     pick = []
-    for lo, hi in ((60, 64), (120, 128), (129, 150), (8, 20)):
+    for lo, hi in ((60, 64), (76, 80), (92, 96), (120, 128), (129, 150), (8, 20)):
         pick += list(np.flatnonzero((n >= lo) & (n <= hi))[:4])
     ligs = all_ligs.subset(pick)
     print("atoms", np.diff(ligs.atom_offset).tolist(), flush=True)
     orient = synth.orientations(3, 10)
     ref = _run(h, ligs, orient, 128, (0, 0), passes=2)
-    _same(_run(h, ligs, orient, 128, (64, 128), passes=2), ref, "passes 2")
-    rep = check_batch(p, ligs, orient, 128, _run(h, ligs, orient, 128, (64, 128), passes=2),
+    for mp in ((64, 128), (80, 128), (96, 128)):
+        _same(_run(h, ligs, orient, 128, mp, passes=2), ref, ("passes 2", mp))
+    rep = check_batch(p, ligs, orient, 128, _run(h, ligs, orient, 128, (80, 128), passes=2),
                       passes=2, orients=[0, 9])
     assert rep.ok(), rep.summary()
 
@@ -134,7 +136,7 @@ def test_grouped_async_graph_replay(pockets):
 
 def test_group_mapping_arguments(pockets):
     p, h = pockets(1)
-    for a, b, code in ((65, 0, dock.DOCK_E_LIMIT), (0, 129, dock.DOCK_E_LIMIT),
+    for a, b, code in ((97, 0, dock.DOCK_E_LIMIT), (0, 129, dock.DOCK_E_LIMIT),
                        (48, 40, dock.DOCK_E_INVAL), (-1, 0, dock.DOCK_E_LIMIT)):
         with pytest.raises(dock.DockError) as e:
             dock.dock_set_group_mapping(h, a, b)
@@ -162,10 +164,10 @@ def test_grouped_degenerate_ligands(pockets):
         orient = synth.orientations(1, O)
         for S in (1, 16, 100):
             ref = _run(h, ligs, orient, S, (0, 0))
-            for mp in ((64, 128), (0, 128)):
+            for mp in ((80, 128), (0, 128)):
                 _same(_run(h, ligs, orient, S, mp), ref, (O, S, mp))
         ref = _run(h, ligs, orient, 16, (0, 0), r_bump=50.0)
-        got = _run(h, ligs, orient, 16, (64, 128), r_bump=50.0)
+        got = _run(h, ligs, orient, 16, (80, 128), r_bump=50.0)
         _same(got, ref, (O, "r_bump 50"))
         # every rotamer with moving atoms bumps at every angle; the one with
         # an empty moving set (the first rotamer of the batch) cannot bump
