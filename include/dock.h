@@ -370,7 +370,7 @@ typedef struct {
 } dock_tune_entry;
 
 /* Autotuner: time the sweep for every candidate mapping (waves per block
- * 1, 2, 4 x claim caps 4, 16, 32, 64 x group bounds (0, 0), (48, 96),
+ * 0 (automatic), 1, 2, 4 x claim caps 4, 16, 32, 64 x group bounds (0, 0), (48, 96),
  * (64, 128), (80, 128), (96, 128)) on a seeded subset of sample_ligands ligands of this
  * (host) batch, keep the fastest on the handle (dock_set_launch and
  * dock_set_group_mapping), and report each timing in entries[0..*n_entries).

@@ -698,7 +698,7 @@ int dock_autotune(dock_pocket *p, const dock_ligands *ligs, const float *orient,
   dock_results res{bs.data(), bo.data(), ai.data(), xo.data(), nullptr, nullptr, stv.data(), nullptr};
   dock_params tp = *prm;
   tp.flags |= DOCK_FLAG_TIME_SWEEP;
-  const int waves[] = {1, 2, 4};
+  const int waves[] = {0, 1, 2, 4};  // 0: per class, the size with the most resident waves
   const int claims[] = {4, 16, 32, 64};
   // size classes docked in groups: none, and four (16-lane, 32-lane) bounds
   const int groups[][2] = {{0, 0}, {48, 96}, {64, 128}, {80, 128}, {96, 128}};

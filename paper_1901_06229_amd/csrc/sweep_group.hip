@@ -45,10 +45,10 @@ __host__ __device__ inline int round16(int b) { return (b + 15) / 16 * 16; }
 // LDS of one wave.  LDS bounds how many waves a compute unit holds, and these
 // kernels run faster with every wave added (latency-bound), so it is kept
 // small.
-//   shared:  Q, M (int16 [nmax]) static and moving lists of the step,
-//            slot (int16 [nmax]) an atom's entry in ZRc: moving atom t -> t,
-//            static atom Q[p] -> m + p, axis atoms -1,
-//            AXU (float4 [NG][2]) each group's axis point and unit bond axis
+//   shared:  Q, M (uint8 [nmax]) static and moving lists of the step,
+//            slot (uint8 [nmax]) an atom's entry in ZRc: moving atom t -> t,
+//            static atom Q[p] -> m + p, axis atoms kNoSlot (ligands of the
+//            grouped classes have at most 128 atoms)
 //   scratch: one block per group, contiguous: the moving atoms' voxel-unit
 //            bases (float [9][G / 2]) and the ring of compacted steps (int16
 //            [4G]) while scoring; the moving atoms' values for the step-0
@@ -59,9 +59,11 @@ __host__ __device__ inline int round16(int b) { return (b + 15) / 16 * 16; }
 //            packed for the pair bound (pack_zr), of the moving atoms (in
 //            list order), then of the static ones
 //            BM (uint32 [(S + 31) / 32]) bump bits
+constexpr uint8_t kNoSlot = 0xFF;  // above every moving-list position
+static_assert(kGroupMaxAtoms16 < kNoSlot && kGroupMaxAtoms32 < kNoSlot, "uint8 atom lists");
 template <int G>
 __host__ __device__ inline int group_shared_bytes(int nmax) {
-  return round16(nmax * 6) + (kWave / G) * 32;
+  return round16(nmax * 3);
 }
 template <int G>
 __host__ __device__ constexpr int group_scratch_bytes() {
@@ -83,8 +85,7 @@ __host__ __device__ inline int group_wave_bytes(int nmax, int S) {
 
 template <int G>
 struct GroupLds {
-  int16_t *Q, *M, *slot;
-  float4 *AXU;    // [NG][2]
+  uint8_t *Q, *M, *slot;
   int *PL;        // the wave's kept-pair list
   char *regions;  // group 0's region; group g's at + g * region
   int region;
@@ -97,10 +98,9 @@ struct GroupLds {
   uint32_t *BM;
   __device__ GroupLds(char *wave_base, int nmax_, int S, int gid) {
     nmax = nmax_;
-    Q = (int16_t *)wave_base;
+    Q = (uint8_t *)wave_base;
     M = Q + nmax;
     slot = M + nmax;
-    AXU = (float4 *)(wave_base + round16(nmax * 6));
     char *scr0 = wave_base + group_shared_bytes<G>(nmax);
     PL = (int *)scr0;
     char *scr = scr0 + gid * group_scratch_bytes<G>();
@@ -305,23 +305,23 @@ __global__ void __launch_bounds__(WAVES *kWave)
         const int ms = A.lig.move_offset[rot];
         const int m = A.lig.move_offset[rot + 1] - ms;
         // moving list, static list and slots: once per wave (shared topology)
-        for (int i = lane; i < n; i += kWave) W.slot[i] = -1;
+        for (int i = lane; i < n; i += kWave) W.slot[i] = kNoSlot;
         wave_lds_sync();
         for (int t = lane; t < m; t += kWave) {
           const int i = A.lig.move_atoms[ms + t];
-          W.slot[i] = (int16_t)t;
-          W.M[t] = (int16_t)i;
+          W.slot[i] = (uint8_t)t;
+          W.M[t] = (uint8_t)i;
         }
         wave_lds_sync();
         int q = 0;
         for (int base = 0; base < n; base += kWave) {
           const int i = base + lane;
-          const bool st = i < n && W.slot[i] < 0 && i != ra && i != rb;
+          const bool st = i < n && W.slot[i] == kNoSlot && i != ra && i != rb;
           const uint64_t mask = wave_ballot(st);
           if (st) {
             const int pos = lanes_before(mask, q);
-            W.Q[pos] = (int16_t)i;
-            W.slot[i] = (int16_t)(m + pos);
+            W.Q[pos] = (uint8_t)i;
+            W.slot[i] = (uint8_t)(m + pos);
           }
           q += __popcll(mask);
         }
@@ -336,11 +336,11 @@ __global__ void __launch_bounds__(WAVES *kWave)
           if (i < n) {
             const float4 xi = W.X[i];
             const int sl = W.slot[i];
-            if (sl >= 0) {
+            if (sl != kNoSlot) {
               const Cyl c = cyl_of(xi, xa, u);
               W.ZRc[sl] = pack_zr(c.z, cyl_radius(make_float4(c.rx, c.ry, c.rz, c.z)));
             }
-            if (sl < 0 || sl >= m) v = xi.w;  // everything that does not move
+            if (sl >= m) v = xi.w;  // everything that does not move (kNoSlot too)
           }
           cst = chunk_sum_group<G>(cst, v, base, n, g.gl);
         }
@@ -360,11 +360,8 @@ __global__ void __launch_bounds__(WAVES *kWave)
         // bump bits: pairs whose cylinder bound does not clear r_bump go into
         // the wave's pair list (packed group << 16 | moving-list position << 8
         // | j); their clash arcs are then marked 64 pairs at a time, each
-        // lane into its pair's group
-        if (g.gl == 0) {
-          W.AXU[2 * g.gid] = xa;
-          W.AXU[2 * g.gid + 1] = make_float4(u.x, u.y, u.z, 0.0f);
-        }
+        // lane into its pair's group (whose axis it recomputes from that
+        // group's pose, the same bits as the group's own)
         int np = 0;  // pairs in the list (wave-uniform)
         auto flush = [&]() {
           wave_lds_sync();
@@ -375,8 +372,8 @@ __global__ void __launch_bounds__(WAVES *kWave)
               const int pk = W.PL[e];
               const int pg = pk >> 16, i = W.M[(pk >> 8) & 0xFF], j = pk & 0xFF;
               const float4 *Xg = W.group_X(pg);
-              const float4 pxa = W.AXU[2 * pg], pu4 = W.AXU[2 * pg + 1];
-              const float3 pu = make_float3(pu4.x, pu4.y, pu4.z);
+              const float4 pxa = Xg[ra];
+              const float3 pu = bond_axis(pxa, Xg[rb]);
               const Cyl ci = cyl_of(Xg[i], pxa, pu), cj = cyl_of(Xg[j], pxa, pu);
               mark_pair_arc(W.group_BM(pg), make_float4(ci.rx, ci.ry, ci.rz, ci.z),
                             make_float4(cj.rx, cj.ry, cj.rz, cj.z), pu, r2, S, steps_per_rad);

@@ -283,8 +283,8 @@ def test_autotune_picks_fastest_and_keeps_results(pockets):
     before = dock.dock_batch(h, ligs, orient, 128, want_all=True)
     entries = dock.dock_autotune(h, ligs, orient, 128, sample_ligands=100, seed=7)
     print(entries)
-    # waves {1, 2, 4} x claim caps {4, 16, 32, 64} x five group bounds
-    assert len(entries) == 60
+    # waves {0, 1, 2, 4} x claim caps {4, 16, 32, 64} x five group bounds
+    assert len(entries) == 80
     best = min(entries, key=lambda e: e["sweep_ms"])
     assert dock.dock_get_launch(h) == (best["waves_per_block"], best["blocks_per_cu"],
                                        best["items_per_claim"])
