@@ -243,8 +243,11 @@ __device__ __forceinline__ void group_scores(const GroupLds<G> &W, const Grp<G> 
   }
 }
 
+// 1-wave blocks are held to 80 VGPRs (6 waves per SIMD; they fit without
+// spills): where LDS allows more than 20 waves per compute unit (the 32-lane
+// class, the 16-lane class up to 64 atoms) the launch then picks them.
 template <int G, int WAVES>
-__global__ void __launch_bounds__(WAVES *kWave)
+__global__ void __launch_bounds__(WAVES *kWave) __attribute__((amdgpu_waves_per_eu(WAVES == 1 ? 6 : 1)))
     sweep_group_kernel(SweepArgs args, int nmax, int cls) {
   (void)args;
   const SweepArgs &A = *(const SweepArgs *)__builtin_amdgcn_kernarg_segment_ptr();
