@@ -755,7 +755,7 @@ def main():
                     help="most items a wave takes per work-queue atomic")
     ap.add_argument("--autotune", type=int, default=None,
                     help="time every launch mapping on this many sampled ligands first and keep "
-                         "the fastest (default: 30000 for the uneven-batch workload, else off)")
+                         "the fastest (default: the whole uneven batch, 100000 ligands; else off)")
     ap.add_argument("--graph", action=argparse.BooleanOptionalAction, default=None,
                     help="replay the batch's launch sequence as a captured HIP graph "
                          "(default: on for the uneven-batch workload)")
@@ -792,7 +792,7 @@ def main():
         legs = [x for x in legs if x != "learned"]
     if args.align <= 0:
         legs = [x for x in legs if x != "align"]
-    autotune = args.autotune if args.autotune is not None else (30000 if cfg == 3 else 0)
+    autotune = args.autotune if args.autotune is not None else (100000 if cfg == 3 else 0)
     graph = args.graph if args.graph is not None else cfg == 3
     head, ctx = plain_leg(cfg, args.steps, args.warmup, args.bump, args.waves, args.claim, autotune,
                           graph, args.ligands, end_to_end=not args.no_end_to_end)
