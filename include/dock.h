@@ -352,12 +352,12 @@ int dock_get_launch(dock_pocket *p, int *waves_per_block, int *blocks_per_cu,
  * kept pairs, applying the chosen angle, reductions) serves several items.
  * Each size class is a contiguous range of the cost-sorted order, docked by
  * its own persistent kernel.  0 disables a class; atoms16 <= 96,
- * atoms32 <= 128 and atoms32 > atoms16 unless 0 (DOCK_E_LIMIT /
+ * atoms32 <= 192 and atoms32 > atoms16 unless 0 (DOCK_E_LIMIT /
  * DOCK_E_INVAL).  Applies to plain pruned sweeps in cost order with at most
  * DOCK_GROUP_MAX_STEPS angle steps (not with DOCK_FLAG_NO_LPT or
  * DOCK_FLAG_DIRECT_BUMP, nor learned mode; above that step count scoring
  * dominates a rotamer step and one item per wave scores it faster).  Results
- * are bitwise identical under every mapping.  A new handle starts at (80, 128). */
+ * are bitwise identical under every mapping.  A new handle starts at (80, 192). */
 #define DOCK_GROUP_MAX_STEPS 2048
 int dock_set_group_mapping(dock_pocket *p, int atoms16, int atoms32);
 int dock_get_group_mapping(dock_pocket *p, int *atoms16, int *atoms32);
@@ -371,7 +371,7 @@ typedef struct {
 
 /* Autotuner: time the sweep for every candidate mapping (waves per block
  * 0 (automatic), 1, 2, 4 x claim caps 4, 16, 32, 64 x group bounds (0, 0), (48, 96),
- * (64, 128), (80, 128), (96, 128)) on a seeded subset of sample_ligands ligands of this
+ * (64, 128), (80, 128), (80, 192)) on a seeded subset of sample_ligands ligands of this
  * (host) batch, keep the fastest on the handle (dock_set_launch and
  * dock_set_group_mapping), and report each timing in entries[0..*n_entries).
  * Same validation and errors as dock_batch. */

@@ -60,11 +60,11 @@ struct dock_pocket {
   hipEvent_t ev_align[2] = {nullptr, nullptr};  // alignment start/end
   bool align_timed = false;
   unsigned long long *h_work = nullptr;  // pinned copy of the sweep's two work counters
-  // grouped classes on by default: (80, 128) measured fastest among the
-  // bounds the autotuner tries on the 100,000-ligand uneven batch (135 ms
-  // one item per wave -> 87 ms) and on the 10,000-ligand batch (20.6 ->
-  // 13.6 ms)
-  LaunchPlan plan{0, 0, 16, 80, 128};
+  // grouped classes on by default: (80, 192) is within 0.2 % of the fastest
+  // bounds on the 100,000-ligand uneven batch (135 ms one item per wave ->
+  // 87.5 ms) and the fastest on the 10,000-ligand batch (20.6 -> 13.6 ms) and
+  // on the large ligands (49.7 ms at (64, 128) -> 48.8 ms)
+  LaunchPlan plan{0, 0, 16, 80, 192};
   void *scratch = nullptr;    // this device's copy of the static workspace
   std::vector<float> host_grid;  // host copy of the grid, made on first use (hybrid calls)
   HybridCache hybrid;            // the hybrid entry point's streams and buffers
@@ -701,7 +701,7 @@ int dock_autotune(dock_pocket *p, const dock_ligands *ligs, const float *orient,
   const int waves[] = {0, 1, 2, 4};  // 0: per class, the size with the most resident waves
   const int claims[] = {4, 16, 32, 64};
   // size classes docked in groups: none, and four (16-lane, 32-lane) bounds
-  const int groups[][2] = {{0, 0}, {48, 96}, {64, 128}, {80, 128}, {96, 128}};
+  const int groups[][2] = {{0, 0}, {48, 96}, {64, 128}, {80, 128}, {80, 192}};
   LaunchPlan best_plan = p->plan;
   float best_ms = 0.0f;
   int n = 0;

@@ -15,7 +15,7 @@ constexpr int kLptBuckets = 128;  // cost buckets per size class
 // contiguous range of the cost-sorted ligand order with its own kernel.
 constexpr int kClasses = 3;
 constexpr int kGroupMaxAtoms16 = 96;   // largest ligands the 16-lane class may take
-constexpr int kGroupMaxAtoms32 = 128;  // and the 32-lane class
+constexpr int kGroupMaxAtoms32 = 192;  // and the 32-lane class
 // small integer block at the head of the workspace:
 //   [0] work-queue counter of the one-item-per-wave sweep, [1] rejected-
 //   ligand count, [4, 8) 64-bit work counters (kept pairs, evaluations),

@@ -48,7 +48,7 @@ __host__ __device__ inline int round16(int b) { return (b + 15) / 16 * 16; }
 //   shared:  Q, M (uint8 [nmax]) static and moving lists of the step,
 //            slot (uint8 [nmax]) an atom's entry in ZRc: moving atom t -> t,
 //            static atom Q[p] -> m + p, axis atoms kNoSlot (ligands of the
-//            grouped classes have at most 128 atoms)
+//            grouped classes have at most 192 atoms)
 //   scratch: one block per group, contiguous: the moving atoms' voxel-unit
 //            bases (float [9][G / 2]) and the ring of compacted steps (int16
 //            [4G]) while scoring; the moving atoms' values for the step-0

@@ -14,7 +14,8 @@ from tests.checker import check_batch
 pytestmark = pytest.mark.gpu
 
 NAMES = ("best_score", "best_orient", "angle_idx", "xyz", "all_scores", "all_angle_idx", "status")
-MAPPINGS = [(0, 0), (32, 64), (40, 80), (48, 96), (64, 128), (80, 128), (96, 128), (0, 96), (48, 0)]
+MAPPINGS = [(0, 0), (32, 64), (40, 80), (48, 96), (64, 128), (80, 128), (96, 128), (80, 192), (0, 160),
+            (0, 96), (48, 0)]
 
 
 @pytest.fixture(scope="module")
@@ -86,8 +87,8 @@ def test_grouped_parity_with_reference(pockets):
 
 def test_grouped_passes_and_class_limits(pockets):
     """Two passes, and ligands at exactly the class bounds (64, 80 and 96
-    atoms in the 16-lane class, 128 in the 32-lane class), next to larger
-    ones."""
+    atoms in the 16-lane class, 128 and 150 in the 32-lane class), next to
+    larger ones."""
     p, h = pockets(3)
     all_ligs = synth.ligands(3, count=3000)
     n = np.diff(all_ligs.atom_offset)
@@ -98,11 +99,29 @@ def test_grouped_passes_and_class_limits(pockets):
     print("atoms", np.diff(ligs.atom_offset).tolist(), flush=True)
     orient = synth.orientations(3, 10)
     ref = _run(h, ligs, orient, 128, (0, 0), passes=2)
-    for mp in ((64, 128), (80, 128), (96, 128)):
+    for mp in ((64, 128), (80, 128), (96, 128), (80, 150), (64, 192)):
         _same(_run(h, ligs, orient, 128, mp, passes=2), ref, ("passes 2", mp))
-    rep = check_batch(p, ligs, orient, 128, _run(h, ligs, orient, 128, (80, 128), passes=2),
+    rep = check_batch(p, ligs, orient, 128, _run(h, ligs, orient, 128, (80, 192), passes=2),
                       passes=2, orients=[0, 9])
     assert rep.ok(), rep.summary()
+
+
+def test_grouped_large_ligands(pockets):
+    """The 32-lane class up to its 192-atom limit on the large-ligand pocket
+    (256^3 grid, 360 steps, 60-120 rotamers): ligands of 100-192 atoms, with
+    one at or next to each bound, bitwise equal to one item per wave."""
+    p, h = pockets(5)
+    all_ligs = synth.ligands(5, count=400)
+    n = np.diff(all_ligs.atom_offset)
+    pick = []
+    for lo, hi in ((100, 128), (129, 160), (180, 192), (193, 250)):
+        pick += list(np.flatnonzero((n >= lo) & (n <= hi))[:3])
+    ligs = all_ligs.subset(pick)
+    print("atoms", np.diff(ligs.atom_offset).tolist(), flush=True)
+    orient = synth.orientations(5, 4)
+    ref = _run(h, ligs, orient, 360, (0, 0))
+    for mp in ((80, 192), (0, 160), (64, 128)):
+        _same(_run(h, ligs, orient, 360, mp), ref, mp)
 
 
 def test_grouped_async_graph_replay(pockets):
@@ -136,7 +155,7 @@ def test_grouped_async_graph_replay(pockets):
 
 def test_group_mapping_arguments(pockets):
     p, h = pockets(1)
-    for a, b, code in ((97, 0, dock.DOCK_E_LIMIT), (0, 129, dock.DOCK_E_LIMIT),
+    for a, b, code in ((97, 0, dock.DOCK_E_LIMIT), (0, 193, dock.DOCK_E_LIMIT),
                        (48, 40, dock.DOCK_E_INVAL), (-1, 0, dock.DOCK_E_LIMIT)):
         with pytest.raises(dock.DockError) as e:
             dock.dock_set_group_mapping(h, a, b)

@@ -293,7 +293,7 @@ def test_autotune_picks_fastest_and_keeps_results(pockets):
     for k in ("best_score", "best_orient", "angle_idx", "xyz", "all_scores", "all_angle_idx"):
         assert np.array_equal(before[k], after[k]), k
     dock.dock_set_launch(h, 0, 0, 16)
-    dock.dock_set_group_mapping(h, 80, 128)
+    dock.dock_set_group_mapping(h, 80, 192)
 
 
 def _device_batch(ligs, orient, S, torch):
@@ -543,4 +543,4 @@ def test_full_c3_batch_autotuned_graph_sampled_replay(pockets):
     assert rep.ok(), rep.summary()
     rep.assert_rare()
     dock.dock_set_launch(h, 0, 0, 16)
-    dock.dock_set_group_mapping(h, 80, 128)
+    dock.dock_set_group_mapping(h, 80, 192)
