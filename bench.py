@@ -529,6 +529,7 @@ def plain_leg(cfg, steps, warmup, bump="pruned", waves=0, claim=16, autotune=0, 
                                   r_bump=synth.R_BUMP, flags=flags & dock.DOCK_FLAG_DIRECT_BUMP)
     launch = dict(zip(("waves_per_block", "blocks_per_cu", "items_per_claim"), dock.dock_get_launch(h)))
     launch.update(zip(("group16_atoms", "group32_atoms"), dock.dock_get_group_mapping(h)))
+    launch["group32_split"] = dock.dock_get_group_split(h)
     stream = torch.cuda.Stream()
     torch.cuda.synchronize()
 

@@ -64,7 +64,7 @@ struct dock_pocket {
   // bounds on the 100,000-ligand uneven batch (135 ms one item per wave ->
   // 87.5 ms) and the fastest on the 10,000-ligand batch (20.6 -> 13.6 ms) and
   // on the large ligands (49.7 ms at (64, 128) -> 48.8 ms)
-  LaunchPlan plan{0, 0, 16, 80, 192};
+  LaunchPlan plan{0, 0, 16, 80, 192, 0};
   void *scratch = nullptr;    // this device's copy of the static workspace
   std::vector<float> host_grid;  // host copy of the grid, made on first use (hybrid calls)
   HybridCache hybrid;            // the hybrid entry point's streams and buffers
@@ -386,8 +386,9 @@ int enqueue_batch(dock_pocket *p, const dock_ligands *ligs, const float *orient,
     plan.group16_atoms = plan.group32_atoms = 0;
   const int c16 = min(plan.group16_atoms, max_atoms);
   const int c32 = max(c16, min(plan.group32_atoms, max_atoms));
-  hipError_t e = enqueue_prepare(A, max_atoms, learned ? max_rot : DOCK_MAX_ROT, lpt, c16, c32,
-                                 (int32_t *)(base + w.bucket), counts, cursor,
+  const int c32s = plan.group32_split > c16 && plan.group32_split < c32 ? plan.group32_split : c32;
+  hipError_t e = enqueue_prepare(A, max_atoms, learned ? max_rot : DOCK_MAX_ROT, lpt, c16, c32s,
+                                 c32, (int32_t *)(base + w.bucket), counts, cursor,
                                  A.small + 1, st);
   if (e != hipSuccess) return hip_fail(e, "prepare kernels");
   const int maxn = maxn_bucket(max_atoms);
@@ -601,7 +602,7 @@ int dock_set_launch(dock_pocket *p, int waves_per_block, int blocks_per_cu,
   if (items_per_claim < 1 || items_per_claim > 64)
     return fail(DOCK_E_INVAL, "items_per_claim must be in [1, 64]");
   p->plan = LaunchPlan{waves_per_block, blocks_per_cu, items_per_claim, p->plan.group16_atoms,
-                       p->plan.group32_atoms};
+                       p->plan.group32_atoms, p->plan.group32_split};
   return DOCK_OK;
 }
 
@@ -615,6 +616,22 @@ int dock_set_group_mapping(dock_pocket *p, int atoms16, int atoms32) {
     return fail(DOCK_E_INVAL, "the 32-lane class must hold larger ligands than the 16-lane class");
   p->plan.group16_atoms = atoms16;
   p->plan.group32_atoms = atoms32;
+  return DOCK_OK;
+}
+
+int dock_set_group_split(dock_pocket *p, int atoms) {
+  g_last_error.clear();
+  if (!p) return fail(DOCK_E_INVAL, "NULL pocket");
+  if (atoms < 0 || atoms > kGroupMaxAtoms32)
+    return fail(DOCK_E_LIMIT, "group split %d outside [0, %d]", atoms, kGroupMaxAtoms32);
+  p->plan.group32_split = atoms;
+  return DOCK_OK;
+}
+
+int dock_get_group_split(dock_pocket *p, int *atoms) {
+  g_last_error.clear();
+  if (!p || !atoms) return fail(DOCK_E_INVAL, "NULL argument");
+  *atoms = p->plan.group32_split;
   return DOCK_OK;
 }
 
@@ -700,15 +717,17 @@ int dock_autotune(dock_pocket *p, const dock_ligands *ligs, const float *orient,
   tp.flags |= DOCK_FLAG_TIME_SWEEP;
   const int waves[] = {0, 1, 2, 4};  // 0: per class, the size with the most resident waves
   const int claims[] = {4, 16, 32, 64};
-  // size classes docked in groups: none, and four (16-lane, 32-lane) bounds
-  const int groups[][2] = {{0, 0}, {48, 96}, {64, 128}, {80, 128}, {80, 192}};
+  // size classes docked in groups: none, four (16-lane, 32-lane) bounds, and
+  // one with the 32-lane ligands split at 128 atoms
+  const int groups[][3] = {{0, 0, 0},    {48, 96, 0},  {64, 128, 0},
+                           {80, 128, 0}, {80, 192, 0}, {64, 160, 128}};
   LaunchPlan best_plan = p->plan;
   float best_ms = 0.0f;
   int n = 0;
   for (const auto &gm : groups)
    for (int w : waves)
     for (int c : claims) {
-      p->plan = LaunchPlan{w, 0, c, gm[0], gm[1]};
+      p->plan = LaunchPlan{w, 0, c, gm[0], gm[1], gm[2]};
       float ms_sum = 0.0f;
       for (int rep = 0; rep < 3; ++rep) {
         rc = dock_batch(p, &sub, orient, n_orient, angle_steps, &tp, &res);
@@ -722,11 +741,11 @@ int dock_autotune(dock_pocket *p, const dock_ligands *ligs, const float *orient,
         if (rep > 0) ms_sum += ms;  // first run warms caches
       }
       const float ms = ms_sum / 2.0f;
-      if (entries && n < max_entries) entries[n] = dock_tune_entry{w, 0, c, ms, gm[0], gm[1]};
+      if (entries && n < max_entries) entries[n] = dock_tune_entry{w, 0, c, ms, gm[0], gm[1], gm[2]};
       ++n;
       if (best_ms == 0.0f || ms < best_ms) {
         best_ms = ms;
-        best_plan = LaunchPlan{w, 0, c, gm[0], gm[1]};
+        best_plan = LaunchPlan{w, 0, c, gm[0], gm[1], gm[2]};
       }
     }
   p->plan = best_plan;

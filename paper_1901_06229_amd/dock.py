@@ -50,7 +50,8 @@ class dock_results(ctypes.Structure):
 class dock_tune_entry(ctypes.Structure):
     _fields_ = [("waves_per_block", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
                 ("items_per_claim", ctypes.c_int32), ("sweep_ms", ctypes.c_float),
-                ("group16_atoms", ctypes.c_int32), ("group32_atoms", ctypes.c_int32)]
+                ("group16_atoms", ctypes.c_int32), ("group32_atoms", ctypes.c_int32),
+                ("group32_split", ctypes.c_int32)]
 
 
 class dock_hybrid_opts(ctypes.Structure):
@@ -145,6 +146,10 @@ def load_library(path: str = None):
         getattr(lib, name).restype = c.c_int
     lib.dock_get_group_mapping.argtypes = [_P, c.POINTER(c.c_int), c.POINTER(c.c_int)]
     lib.dock_get_group_mapping.restype = c.c_int
+    lib.dock_set_group_split.argtypes = [_P, c.c_int]
+    lib.dock_set_group_split.restype = c.c_int
+    lib.dock_get_group_split.argtypes = [_P, c.POINTER(c.c_int)]
+    lib.dock_get_group_split.restype = c.c_int
     lib.dock_autotune.argtypes = [_P, c.POINTER(dock_ligands), _P, c.c_int, c.c_int,
                                   c.POINTER(dock_params), c.c_int, c.c_uint64,
                                   c.POINTER(dock_tune_entry), c.c_int, c.POINTER(c.c_int)]
@@ -430,7 +435,8 @@ def dock_autotune(pocket: Pocket, ligs, orient, angle_steps: int, sample_ligands
                              entries, 256, ctypes.byref(n)), "dock_autotune")
     return [dict(waves_per_block=e.waves_per_block, blocks_per_cu=e.blocks_per_cu,
                  items_per_claim=e.items_per_claim, sweep_ms=e.sweep_ms,
-                 group16_atoms=e.group16_atoms, group32_atoms=e.group32_atoms)
+                 group16_atoms=e.group16_atoms, group32_atoms=e.group32_atoms,
+                 group32_split=e.group32_split)
             for e in entries[:n.value]]
 
 
@@ -446,6 +452,18 @@ def dock_get_group_mapping(pocket: Pocket):
     _check(load_library().dock_get_group_mapping(pocket.handle, ctypes.byref(a), ctypes.byref(b)),
            "dock_get_group_mapping")
     return int(a.value), int(b.value)
+
+
+def dock_set_group_split(pocket: Pocket, atoms: int = 0):
+    """32-lane ligands above `atoms` atoms get a kernel of their own (0: none)."""
+    _check(load_library().dock_set_group_split(pocket.handle, int(atoms)), "dock_set_group_split")
+
+
+def dock_get_group_split(pocket: Pocket):
+    a = ctypes.c_int()
+    _check(load_library().dock_get_group_split(pocket.handle, ctypes.byref(a)),
+           "dock_get_group_split")
+    return int(a.value)
 
 
 def _tptr(t):

@@ -33,10 +33,11 @@ def pockets():
         h.close()
 
 
-def _run(h, ligs, orient, S, mapping, **kw):
+def _run(h, ligs, orient, S, mapping, split=0, **kw):
     dock.dock_set_group_mapping(h, *mapping)
-    print(f"[group] mapping {mapping}: {ligs.n_ligands} ligands x {orient.shape[0]} orientations, "
-          f"S={S} {kw}", flush=True)
+    dock.dock_set_group_split(h, split)
+    print(f"[group] mapping {mapping} split {split}: {ligs.n_ligands} ligands x "
+          f"{orient.shape[0]} orientations, S={S} {kw}", flush=True)
     return dock.dock_batch(h, ligs, orient, S, want_all=True, **kw)
 
 
@@ -54,6 +55,10 @@ def test_grouped_results_are_bitwise_the_single_item_ones(pockets):
     ref = _run(h, ligs, orient, 128, (0, 0))
     for mp in MAPPINGS[1:]:
         _same(_run(h, ligs, orient, 128, mp), ref, mp)
+    # the 32-lane ligands split into two classes (and splits that are no-ops)
+    for mp, split in (((64, 160), 128), ((48, 150), 96), ((0, 128), 64), ((64, 128), 64),
+                      ((64, 128), 128)):
+        _same(_run(h, ligs, orient, 128, mp, split), ref, (mp, split))
 
 
 @pytest.mark.parametrize("S", [1, 7, 16, 17, 33, 127, 128, 129, 255, 257, 360, 2048])
@@ -122,6 +127,8 @@ def test_grouped_large_ligands(pockets):
     ref = _run(h, ligs, orient, 360, (0, 0))
     for mp in ((80, 192), (0, 160), (64, 128)):
         _same(_run(h, ligs, orient, 360, mp), ref, mp)
+    for mp, split in (((80, 192), 128), ((0, 192), 150)):
+        _same(_run(h, ligs, orient, 360, mp, split), ref, (mp, split))
 
 
 def test_grouped_async_graph_replay(pockets):
@@ -163,6 +170,14 @@ def test_group_mapping_arguments(pockets):
     dock.dock_set_group_mapping(h, 32, 64)
     assert dock.dock_get_group_mapping(h) == (32, 64)
     dock.dock_set_group_mapping(h, 0, 0)
+    for bad in (-1, 193):
+        with pytest.raises(dock.DockError) as e:
+            dock.dock_set_group_split(h, bad)
+        assert e.value.code == dock.DOCK_E_LIMIT
+    dock.dock_set_group_split(h, 128)
+    assert dock.dock_get_group_split(h) == 128
+    dock.dock_set_group_split(h, 0)
+    assert dock.dock_get_group_split(h) == 0
 
 
 def test_grouped_degenerate_ligands(pockets):

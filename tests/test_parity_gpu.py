@@ -283,17 +283,19 @@ def test_autotune_picks_fastest_and_keeps_results(pockets):
     before = dock.dock_batch(h, ligs, orient, 128, want_all=True)
     entries = dock.dock_autotune(h, ligs, orient, 128, sample_ligands=100, seed=7)
     print(entries)
-    # waves {0, 1, 2, 4} x claim caps {4, 16, 32, 64} x five group bounds
-    assert len(entries) == 80
+    # waves {0, 1, 2, 4} x claim caps {4, 16, 32, 64} x six group bounds and splits
+    assert len(entries) == 96
     best = min(entries, key=lambda e: e["sweep_ms"])
     assert dock.dock_get_launch(h) == (best["waves_per_block"], best["blocks_per_cu"],
                                        best["items_per_claim"])
     assert dock.dock_get_group_mapping(h) == (best["group16_atoms"], best["group32_atoms"])
+    assert dock.dock_get_group_split(h) == best["group32_split"]
     after = dock.dock_batch(h, ligs, orient, 128, want_all=True)
     for k in ("best_score", "best_orient", "angle_idx", "xyz", "all_scores", "all_angle_idx"):
         assert np.array_equal(before[k], after[k]), k
     dock.dock_set_launch(h, 0, 0, 16)
     dock.dock_set_group_mapping(h, 80, 192)
+    dock.dock_set_group_split(h, 0)
 
 
 def _device_batch(ligs, orient, S, torch):
@@ -544,3 +546,4 @@ def test_full_c3_batch_autotuned_graph_sampled_replay(pockets):
     rep.assert_rare()
     dock.dock_set_launch(h, 0, 0, 16)
     dock.dock_set_group_mapping(h, 80, 192)
+    dock.dock_set_group_split(h, 0)
