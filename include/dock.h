@@ -382,7 +382,7 @@ typedef struct {
 
 /* Autotuner: time the sweep for every candidate mapping (waves per block
  * 0 (automatic), 1, 2, 4 x claim caps 4, 16, 32, 64 x group bounds (0, 0), (48, 96),
- * (64, 128), (80, 128), (80, 192), and (64, 160) split at 128) on a seeded subset of
+ * (64, 128), (80, 128), (80, 192), and (64, 192) split at 96) on a seeded subset of
  * sample_ligands ligands of this (host) batch, keep the fastest on the handle
  * (dock_set_launch, dock_set_group_mapping, dock_set_group_split), and report each timing
  * in entries[0..*n_entries).

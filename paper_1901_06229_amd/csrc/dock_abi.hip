@@ -718,9 +718,9 @@ int dock_autotune(dock_pocket *p, const dock_ligands *ligs, const float *orient,
   const int waves[] = {0, 1, 2, 4};  // 0: per class, the size with the most resident waves
   const int claims[] = {4, 16, 32, 64};
   // size classes docked in groups: none, four (16-lane, 32-lane) bounds, and
-  // one with the 32-lane ligands split at 128 atoms
+  // one with the 32-lane ligands split at 96 atoms
   const int groups[][3] = {{0, 0, 0},    {48, 96, 0},  {64, 128, 0},
-                           {80, 128, 0}, {80, 192, 0}, {64, 160, 128}};
+                           {80, 128, 0}, {80, 192, 0}, {64, 192, 96}};
   LaunchPlan best_plan = p->plan;
   float best_ms = 0.0f;
   int n = 0;
