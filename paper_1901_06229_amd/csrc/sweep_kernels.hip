@@ -83,41 +83,61 @@ __global__ void __launch_bounds__(kValidateWaves * kWave)
 // expensive down.  Order inside a bucket is irrelevant to the results.
 // Size class c (0: at most c16 atoms, 1: at most c32s, 2: at most c32, 3:
 // the rest; c16 <= c32s <= c32) leads the sort key, so every class is a
-// contiguous range of the order.
-__global__ void lpt_bucket_kernel(LigView L, int S, const int32_t *status, int c16, int c32s,
-                                  int c32, int32_t *bucket_of, int32_t *counts) {
-  int l = blockIdx.x * blockDim.x + threadIdx.x;
-  if (l >= L.n_ligands) return;
-  float cost = 1.0f;
-  int cls = kClasses - 1;
-  if (status[l] == 0) {
-    int n = L.atom_offset[l + 1] - L.atom_offset[l];
-    cls = n <= c16 ? 0 : (n <= c32s ? 1 : (n <= c32 ? 2 : 3));
-    for (int r = L.rot_offset[l]; r < L.rot_offset[l + 1]; ++r) {
-      int m = L.move_offset[r + 1] - L.move_offset[r];
-      cost += (float)m * ((float)S + (float)(n - m - 2));
+// contiguous range of the order.  A block counts its ligands per bucket in
+// LDS and adds each nonzero count to the global one (one atomic per block
+// and bucket instead of one per ligand on a few hundred addresses).
+constexpr int kLptThreads = 256;
+static_assert(kSortBuckets <= 1024, "one scan thread per bucket");
+__global__ void __launch_bounds__(kLptThreads)
+    lpt_bucket_kernel(LigView L, int S, const int32_t *status, int c16, int c32s, int c32,
+                      int32_t *bucket_of, int32_t *counts) {
+  __shared__ int32_t hist[kSortBuckets];
+  for (int i = threadIdx.x; i < kSortBuckets; i += kLptThreads) hist[i] = 0;
+  __syncthreads();
+  const int l = blockIdx.x * kLptThreads + threadIdx.x;
+  if (l < L.n_ligands) {
+    float cost = 1.0f;
+    int cls = kClasses - 1;
+    if (status[l] == 0) {
+      int n = L.atom_offset[l + 1] - L.atom_offset[l];
+      cls = n <= c16 ? 0 : (n <= c32s ? 1 : (n <= c32 ? 2 : 3));
+      for (int r = L.rot_offset[l]; r < L.rot_offset[l + 1]; ++r) {
+        int m = L.move_offset[r + 1] - L.move_offset[r];
+        cost += (float)m * ((float)S + (float)(n - m - 2));
+      }
     }
+    int b = (int)(log2f(cost) * 2.0f);
+    b = b < 0 ? 0 : (b >= kLptBuckets ? kLptBuckets - 1 : b);
+    b += cls * kLptBuckets;
+    bucket_of[l] = b;
+    atomicAdd(&hist[b], 1);
   }
-  int b = (int)(log2f(cost) * 2.0f);
-  b = b < 0 ? 0 : (b >= kLptBuckets ? kLptBuckets - 1 : b);
-  b += cls * kLptBuckets;
-  bucket_of[l] = b;
-  atomicAdd(&counts[b], 1);
+  __syncthreads();
+  for (int i = threadIdx.x; i < kSortBuckets; i += kLptThreads)
+    if (hist[i]) atomicAdd(&counts[i], hist[i]);
 }
 
 // Cursors: classes in order, inside a class the most expensive bucket first;
-// the class ranges are recorded for the sweep kernels.
-__global__ void lpt_scan_kernel(const int32_t *counts, int32_t *cursor, int32_t *small) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  int acc = 0;
-  for (int c = 0; c < kClasses; ++c) {
-    small[kClassBegin + c] = acc;
-    for (int b = kLptBuckets - 1; b >= 0; --b) {
-      cursor[c * kLptBuckets + b] = acc;
-      acc += counts[c * kLptBuckets + b];
-    }
-    small[kClassEnd + c] = acc;
+// the class ranges are recorded for the sweep kernels.  One thread per
+// bucket (in that order), an exclusive scan in LDS.
+__global__ void __launch_bounds__(kSortBuckets)
+    lpt_scan_kernel(const int32_t *counts, int32_t *cursor, int32_t *small) {
+  __shared__ int32_t s[2][kSortBuckets];
+  const int p = threadIdx.x;  // position in the scan order
+  const int c = p / kLptBuckets, bucket = c * kLptBuckets + (kLptBuckets - 1 - p % kLptBuckets);
+  const int v = counts[bucket];
+  int in = 0;
+  s[0][p] = v;
+  __syncthreads();
+  for (int d = 1; d < kSortBuckets; d *= 2) {  // inclusive Hillis-Steele scan
+    s[in ^ 1][p] = s[in][p] + (p >= d ? s[in][p - d] : 0);
+    in ^= 1;
+    __syncthreads();
   }
+  const int incl = s[in][p];
+  cursor[bucket] = incl - v;
+  if (p % kLptBuckets == 0) small[kClassBegin + c] = incl - v;
+  if (p % kLptBuckets == kLptBuckets - 1) small[kClassEnd + c] = incl;
 }
 
 // Input order: every ligand is in the last class.
@@ -129,12 +149,27 @@ __global__ void single_class_kernel(int n_ligands, int32_t *small) {
   }
 }
 
-__global__ void lpt_scatter_kernel(int n_ligands, const int32_t *bucket_of,
-                                   int32_t *cursor, int32_t *order) {
-  int l = blockIdx.x * blockDim.x + threadIdx.x;
-  if (l >= n_ligands) return;
-  int pos = atomicAdd(&cursor[bucket_of[l]], 1);
-  order[pos] = l;
+// Each ligand's slot in the order: its rank among the block's ligands of its
+// bucket (LDS atomics) after the range the block reserves in that bucket
+// (one global atomic per block and bucket).  Order inside a bucket does not
+// affect any result.
+__global__ void __launch_bounds__(kLptThreads)
+    lpt_scatter_kernel(int n_ligands, const int32_t *bucket_of, int32_t *cursor,
+                       int32_t *order) {
+  __shared__ int32_t cnt[kSortBuckets], base[kSortBuckets];
+  for (int i = threadIdx.x; i < kSortBuckets; i += kLptThreads) cnt[i] = 0;
+  __syncthreads();
+  const int l = blockIdx.x * kLptThreads + threadIdx.x;
+  int b = 0, rank = 0;
+  if (l < n_ligands) {
+    b = bucket_of[l];
+    rank = atomicAdd(&cnt[b], 1);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < kSortBuckets; i += kLptThreads)
+    if (cnt[i]) base[i] = atomicAdd(&cursor[i], cnt[i]);
+  __syncthreads();
+  if (l < n_ligands) order[base[b] + rank] = l;
 }
 
 __global__ void fill_i32_kernel(int32_t *p, int n, int32_t v) {
@@ -369,11 +404,12 @@ hipError_t enqueue_prepare(const SweepArgs &A, int max_atoms, int max_rot, bool 
     hipLaunchKernelGGL(validate_kernel, dim3(blocks_for(L, kValidateWaves)), dim3(kValidateWaves * kWave),
                        0, st, A.lig, max_atoms, max_rot, const_cast<int32_t *>(A.status), n_bad);
     if (lpt) {
-      hipLaunchKernelGGL(lpt_bucket_kernel, dim3(blocks_for(L, 256)), dim3(256), 0, st,
-                         A.lig, A.S, A.status, c16, c32s, c32, bucket_of, counts);
-      hipLaunchKernelGGL(lpt_scan_kernel, dim3(1), dim3(64), 0, st, counts, cursor, A.small);
-      hipLaunchKernelGGL(lpt_scatter_kernel, dim3(blocks_for(L, 256)), dim3(256), 0, st, L,
-                         bucket_of, cursor, const_cast<int32_t *>(A.order));
+      hipLaunchKernelGGL(lpt_bucket_kernel, dim3(blocks_for(L, kLptThreads)), dim3(kLptThreads),
+                         0, st, A.lig, A.S, A.status, c16, c32s, c32, bucket_of, counts);
+      hipLaunchKernelGGL(lpt_scan_kernel, dim3(1), dim3(kSortBuckets), 0, st, counts, cursor,
+                         A.small);
+      hipLaunchKernelGGL(lpt_scatter_kernel, dim3(blocks_for(L, kLptThreads)), dim3(kLptThreads),
+                         0, st, L, bucket_of, cursor, const_cast<int32_t *>(A.order));
     } else {
       hipLaunchKernelGGL(identity_order_kernel, dim3(blocks_for(L, 256)), dim3(256), 0, st,
                          L, const_cast<int32_t *>(A.order));
