@@ -48,7 +48,9 @@ __host__ __device__ inline int round16(int b) { return (b + 15) / 16 * 16; }
 //   shared:  Q, M (uint8 [nmax]) static and moving lists of the step,
 //            slot (uint8 [nmax]) an atom's entry in ZRc: moving atom t -> t,
 //            static atom Q[p] -> m + p, axis atoms kNoSlot (ligands of the
-//            grouped classes have at most 192 atoms)
+//            grouped classes have at most 192 atoms),
+//            U (float4 [NG]) each group's unit bond axis (its axis point is
+//            the pose's atom ra)
 //   scratch: one block per group, contiguous: the moving atoms' voxel-unit
 //            bases (float [9][G / 2]) and the ring of compacted steps (int16
 //            [4G]) while scoring; the moving atoms' values for the step-0
@@ -63,7 +65,7 @@ constexpr uint8_t kNoSlot = 0xFF;  // above every moving-list position
 static_assert(kGroupMaxAtoms16 < kNoSlot && kGroupMaxAtoms32 < kNoSlot, "uint8 atom lists");
 template <int G>
 __host__ __device__ inline int group_shared_bytes(int nmax) {
-  return round16(nmax * 3);
+  return round16(nmax * 3) + (kWave / G) * 16;
 }
 template <int G>
 __host__ __device__ constexpr int group_scratch_bytes() {
@@ -86,6 +88,7 @@ __host__ __device__ inline int group_wave_bytes(int nmax, int S) {
 template <int G>
 struct GroupLds {
   uint8_t *Q, *M, *slot;
+  float4 *U;      // [NG]
   int *PL;        // the wave's kept-pair list
   char *regions;  // group 0's region; group g's at + g * region
   int region;
@@ -101,6 +104,7 @@ struct GroupLds {
     Q = (uint8_t *)wave_base;
     M = Q + nmax;
     slot = M + nmax;
+    U = (float4 *)(wave_base + round16(nmax * 3));
     char *scr0 = wave_base + group_shared_bytes<G>(nmax);
     PL = (int *)scr0;
     char *scr = scr0 + gid * group_scratch_bytes<G>();
@@ -363,8 +367,9 @@ __global__ void __launch_bounds__(WAVES *kWave) __attribute__((amdgpu_waves_per_
         // bump bits: pairs whose cylinder bound does not clear r_bump go into
         // the wave's pair list (packed group << 16 | moving-list position << 8
         // | j); their clash arcs are then marked 64 pairs at a time, each
-        // lane into its pair's group (whose axis it recomputes from that
-        // group's pose, the same bits as the group's own)
+        // lane into its pair's group (that group's axis point is its atom ra,
+        // its unit axis is in U)
+        if (g.gl == 0) W.U[g.gid] = make_float4(u.x, u.y, u.z, 0.0f);
         int np = 0;  // pairs in the list (wave-uniform)
         auto flush = [&]() {
           wave_lds_sync();
@@ -375,8 +380,8 @@ __global__ void __launch_bounds__(WAVES *kWave) __attribute__((amdgpu_waves_per_
               const int pk = W.PL[e];
               const int pg = pk >> 16, i = W.M[(pk >> 8) & 0xFF], j = pk & 0xFF;
               const float4 *Xg = W.group_X(pg);
-              const float4 pxa = Xg[ra];
-              const float3 pu = bond_axis(pxa, Xg[rb]);
+              const float4 pxa = Xg[ra], pu4 = W.U[pg];
+              const float3 pu = make_float3(pu4.x, pu4.y, pu4.z);
               const Cyl ci = cyl_of(Xg[i], pxa, pu), cj = cyl_of(Xg[j], pxa, pu);
               mark_pair_arc(W.group_BM(pg), make_float4(ci.rx, ci.ry, ci.rz, ci.z),
                             make_float4(cj.rx, cj.ry, cj.rz, cj.z), pu, r2, S, steps_per_rad);
