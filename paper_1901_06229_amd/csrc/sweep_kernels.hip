@@ -59,14 +59,24 @@ __global__ void __launch_bounds__(kValidateWaves * kWave)
         bad = true;
         break;
       }
+      // the list is read 8 entries at a time (all loads in flight, then the
+      // checks in order): the same verdict as one entry at a time, with an
+      // eighth of the memory round trips
       int prev = -1;
-      for (int t = m0; t < m1; ++t) {
-        const int i = L.move_atoms[t];
-        if (i <= prev || i >= n || i == a || i == b) {
-          bad = true;
-          break;
+      for (int t0 = m0; t0 < m1 && !bad; t0 += 8) {
+        int e[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) e[q] = t0 + q < m1 ? (int)L.move_atoms[t0 + q] : 0;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          if (t0 + q >= m1) break;
+          const int i = e[q];
+          if (i <= prev || i >= n || i == a || i == b) {
+            bad = true;
+            break;
+          }
+          prev = i;
         }
-        prev = i;
       }
     }
     if (__ballot(bad) != 0ull) err = -1;
@@ -340,34 +350,51 @@ __global__ void __launch_bounds__(kWave) finalize_kernel(SweepArgs A, FinalOut F
   }
   wave_lds_sync();
   const int16_t *ks = A.kstar + ((size_t)r0 * O + (size_t)o * R) * A.passes;
-  int step = 0;
-  for (int pass = 0; pass < A.passes; ++pass)
-    for (int r = 0; r < R; ++r, ++step) {
-      const int k = ks[step];
-      if (lane == 0) F.angle_idx[(size_t)r0 * A.passes + step] = (int16_t)k;
+  // The replay is serial in the steps, so each step's inputs (choice, axis
+  // atoms, moving-list range, cos/sin) are loaded up front, 64 steps at a
+  // time with one step per lane, and taken from the owning lane in the loop:
+  // no step waits on a chain of global loads.
+  const int steps = R * A.passes;
+  for (int c0 = 0; c0 < steps; c0 += kWave) {
+    int k = -1, ra = 0, rb = 0, ms = 0, m = 0;
+    float cx = 1.0f, sy = 0.0f;
+    if (c0 + lane < steps) {
+      const int s = c0 + lane, r = s % R;
+      k = ks[s];
+      F.angle_idx[(size_t)r0 * A.passes + s] = (int16_t)k;
       if (k > 0) {
-        const int ra = A.lig.rot_axis[2 * (r0 + r)];
-        const int rb = A.lig.rot_axis[2 * (r0 + r) + 1];
-        const int ms = A.lig.move_offset[r0 + r];
-        const int m = A.lig.move_offset[r0 + r + 1] - ms;
-        const float4 xa = X[ra];
-        const float3 u = bond_axis(xa, X[rb]);
+        ra = A.lig.rot_axis[2 * (r0 + r)];
+        rb = A.lig.rot_axis[2 * (r0 + r) + 1];
+        ms = A.lig.move_offset[r0 + r];
+        m = A.lig.move_offset[r0 + r + 1] - ms;
         const float2 cs = A.cs[k];
-        wave_lds_sync();
-        for (int t = lane; t < m; t += kWave) {
-          const int i = A.lig.move_atoms[ms + t];
-          float3 y;
-          if (MODE == kSweepPruned) {
-            const Cyl c = cyl_of(X[i], xa, u);
-            y = rot_apply(rot_basis(c, xa, u), cs.x, cs.y);
-          } else {
-            y = rodrigues(X[i], xa, u, cs.x, cs.y);
-          }
-          X[i] = make_float4(y.x, y.y, y.z, 0.0f);
+        cx = cs.x;
+        sy = cs.y;
+      }
+    }
+    const int cnt = min(kWave, steps - c0);
+    for (int j = 0; j < cnt; ++j) {
+      if (__builtin_amdgcn_readlane(k, j) <= 0) continue;  // wave-uniform
+      const int sra = __builtin_amdgcn_readlane(ra, j), srb = __builtin_amdgcn_readlane(rb, j);
+      const int sms = __builtin_amdgcn_readlane(ms, j), sm = __builtin_amdgcn_readlane(m, j);
+      const float scx = lane_bcast(cx, j), ssy = lane_bcast(sy, j);
+      const float4 xa = X[sra];
+      const float3 u = bond_axis(xa, X[srb]);
+      wave_lds_sync();
+      for (int t = lane; t < sm; t += kWave) {
+        const int i = A.lig.move_atoms[sms + t];
+        float3 y;
+        if (MODE == kSweepPruned) {
+          const Cyl c = cyl_of(X[i], xa, u);
+          y = rot_apply(rot_basis(c, xa, u), scx, ssy);
+        } else {
+          y = rodrigues(X[i], xa, u, scx, ssy);
         }
+        X[i] = make_float4(y.x, y.y, y.z, 0.0f);
       }
       wave_lds_sync();
     }
+  }
   for (int i = lane; i < n; i += kWave) {
     float *q = F.xyz_out + 3 * (size_t)(a0 + i);
     q[0] = X[i].x;
