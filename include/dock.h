@@ -362,12 +362,13 @@ int dock_get_launch(dock_pocket *p, int *waves_per_block, int *blocks_per_cu,
 int dock_set_group_mapping(dock_pocket *p, int atoms16, int atoms32);
 int dock_get_group_mapping(dock_pocket *p, int *atoms16, int *atoms32);
 
-/* Split of the 32-lane class: when atoms16 < atoms < atoms32, the 32-lane
- * ligands above atoms atoms are docked by a kernel of their own.  A class's
- * LDS per wave follows its largest ligand, so the smaller 32-lane ligands then
- * keep more waves resident, for the price of one more kernel (and the tail of
- * its last items).  0 (a new handle's value) or any value outside that range:
- * one 32-lane class.  0 <= atoms <= 192 (DOCK_E_LIMIT); NULL: DOCK_E_INVAL.
+/* Split of the 32-lane class: the 32-lane ligands (more than atoms16, at most
+ * atoms32 atoms) are docked in classes atoms wide, (atoms16, atoms16 + atoms],
+ * (atoms16 + atoms, atoms16 + 2 atoms], ..., each by a kernel of its own.  A
+ * class's LDS per wave follows its largest ligand, so the smaller 32-lane
+ * ligands then keep more waves resident, for the price of more kernels (and
+ * the tails of their last items).  0 (a new handle's value): one 32-lane
+ * class.  atoms is 0 or within [32, 192] (DOCK_E_LIMIT); NULL: DOCK_E_INVAL.
  * Results are bitwise identical either way. */
 int dock_set_group_split(dock_pocket *p, int atoms);
 int dock_get_group_split(dock_pocket *p, int *atoms);
@@ -382,7 +383,7 @@ typedef struct {
 
 /* Autotuner: time the sweep for every candidate mapping (waves per block
  * 0 (automatic), 1, 2, 4 x claim caps 4, 16, 32, 64 x group bounds (0, 0), (48, 96),
- * (64, 128), (80, 128), (80, 192), and (64, 192) split at 96) on a seeded subset of
+ * (64, 128), (80, 128), (80, 192), and (64, 192) split every 32 atoms) on a seeded subset of
  * sample_ligands ligands of this (host) batch, keep the fastest on the handle
  * (dock_set_launch, dock_set_group_mapping, dock_set_group_split), and report each timing
  * in entries[0..*n_entries).

@@ -386,8 +386,8 @@ int enqueue_batch(dock_pocket *p, const dock_ligands *ligs, const float *orient,
     plan.group16_atoms = plan.group32_atoms = 0;
   const int c16 = min(plan.group16_atoms, max_atoms);
   const int c32 = max(c16, min(plan.group32_atoms, max_atoms));
-  const int c32s = plan.group32_split > c16 && plan.group32_split < c32 ? plan.group32_split : c32;
-  hipError_t e = enqueue_prepare(A, max_atoms, learned ? max_rot : DOCK_MAX_ROT, lpt, c16, c32s,
+  const int split = c32 > c16 ? plan.group32_split : 0;
+  hipError_t e = enqueue_prepare(A, max_atoms, learned ? max_rot : DOCK_MAX_ROT, lpt, c16, split,
                                  c32, (int32_t *)(base + w.bucket), counts, cursor,
                                  A.small + 1, st);
   if (e != hipSuccess) return hip_fail(e, "prepare kernels");
@@ -622,8 +622,9 @@ int dock_set_group_mapping(dock_pocket *p, int atoms16, int atoms32) {
 int dock_set_group_split(dock_pocket *p, int atoms) {
   g_last_error.clear();
   if (!p) return fail(DOCK_E_INVAL, "NULL pocket");
-  if (atoms < 0 || atoms > kGroupMaxAtoms32)
-    return fail(DOCK_E_LIMIT, "group split %d outside [0, %d]", atoms, kGroupMaxAtoms32);
+  if (atoms != 0 && (atoms < kGroupSplitMin || atoms > kGroupMaxAtoms32))
+    return fail(DOCK_E_LIMIT, "group split %d: 0 or within [%d, %d]", atoms, kGroupSplitMin,
+                kGroupMaxAtoms32);
   p->plan.group32_split = atoms;
   return DOCK_OK;
 }
@@ -718,9 +719,9 @@ int dock_autotune(dock_pocket *p, const dock_ligands *ligs, const float *orient,
   const int waves[] = {0, 1, 2, 4};  // 0: per class, the size with the most resident waves
   const int claims[] = {4, 16, 32, 64};
   // size classes docked in groups: none, four (16-lane, 32-lane) bounds, and
-  // one with the 32-lane ligands split at 96 atoms
+  // one with the 32-lane ligands in classes 32 atoms wide
   const int groups[][3] = {{0, 0, 0},    {48, 96, 0},  {64, 128, 0},
-                           {80, 128, 0}, {80, 192, 0}, {64, 192, 96}};
+                           {80, 128, 0}, {80, 192, 0}, {64, 192, 32}};
   LaunchPlan best_plan = p->plan;
   float best_ms = 0.0f;
   int n = 0;

@@ -13,22 +13,25 @@ constexpr int kLptBuckets = 128;  // cost buckets per size class
 // four orientations per wave (16-lane groups), those of at most group32 two
 // per wave (32-lane groups), the rest one per wave; each class is a
 // contiguous range of the cost-sorted ligand order with its own kernel.  The
-// 32-lane ligands may be split at group32_split atoms into two classes: a
+// 32-lane ligands may be split into classes group32_split atoms wide: a
 // class's LDS per wave follows its largest ligand, so the smaller ones then
 // keep more resident waves (at the price of one more kernel and its tail).
-//   class 0: n <= group16, 1: n <= group32 (or the split), 2: n <= group32
-//   above the split, 3: the rest (one item per wave)
-constexpr int kClasses = 4;
+//   class 0: n <= group16; 1 .. kClasses - 2: the 32-lane ligands, class
+//   1 + (n - group16 - 1) / split (all in class 1 without a split);
+//   kClasses - 1: the rest (one item per wave)
+constexpr int kClasses = 8;
+constexpr int kGroupSplitMin = 32;  // narrowest 32-lane class: at most 6 of them
 constexpr int kGroupMaxAtoms16 = 96;   // largest ligands the 16-lane class may take
 constexpr int kGroupMaxAtoms32 = 192;  // and the 32-lane class
 // small integer block at the head of the workspace:
 //   [0] work-queue counter of the one-item-per-wave sweep, [1] rejected-
 //   ligand count, [4, 8) 64-bit work counters (kept pairs, evaluations),
-//   [8 + c] first and [12 + c] end slot of size class c in the order,
-//   [16 + c] work-queue counter of class c's grouped sweep,
-//   [64, 64+B) bucket counts, [64+B, 64+2B) bucket cursors, B = 4 x 128
-constexpr int kClassBegin = 8, kClassEnd = 12, kClassQueue = 16;
-static_assert(kClasses <= 4, "class slots in the small block");
+//   [8 + c] first and [16 + c] end slot of size class c in the order,
+//   [24 + c] work-queue counter of class c's grouped sweep,
+//   [64, 64+B) bucket counts, [64+B, 64+2B) bucket cursors, B = 8 x 128
+constexpr int kClassBegin = 8, kClassEnd = 16, kClassQueue = 24;
+static_assert(kClasses <= 8, "class slots in the small block");
+static_assert(kGroupMaxAtoms32 / kGroupSplitMin <= kClasses - 2, "32-lane classes");
 constexpr int kSortBuckets = kClasses * kLptBuckets;
 constexpr int kSmallInts = 64 + 2 * kSortBuckets;
 // pruned sweep: margin (A^2) added to r_bump^2 when dropping the pairs whose
@@ -110,18 +113,17 @@ struct LaunchPlan {
   int items_per_claim;  // 1 .. 64
   int group16_atoms;    // size class docked in 16-lane groups: n <= this (0: none)
   int group32_atoms;    // size class docked in 32-lane groups: n <= this (0: none)
-  int group32_split;    // 32-lane ligands above this many atoms form a class of their
-                        // own when group16_atoms < it < group32_atoms (0: no split)
+  int group32_split;    // width in atoms of each 32-lane class (0: one class)
 };
 
 // max_rot: ligands with more rotamers get status DOCK_E_LIMIT (at most 255).
 // With lpt, ligands are ordered by size class (class bounds c16, c32: atoms
-// of the 16- and 32-lane classes, 0 for none; c32s: the 32-lane split, or c32
-// for none) and, within a class, by cost;
+// of the 16- and 32-lane classes, 0 for none; split: the width of each
+// 32-lane class, 0 for one) and, within a class, by cost;
 // the class ranges go to A.small[kClassBegin/kClassEnd + c].  Without, the
 // order is the input order and every ligand is in the last class.
 hipError_t enqueue_prepare(const SweepArgs &A, int max_atoms, int max_rot, bool lpt, int c16,
-                           int c32s, int c32, int32_t *bucket_of, int32_t *counts,
+                           int split, int c32, int32_t *bucket_of, int32_t *counts,
                            int32_t *cursor, int32_t *n_bad, hipStream_t st);
 hipError_t enqueue_fill_i32(int32_t *p, int n, int32_t v, hipStream_t st);
 hipError_t enqueue_sweep(const SweepArgs &A, int maxn, const LaunchPlan &plan, int n_cu,

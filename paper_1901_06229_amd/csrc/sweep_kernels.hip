@@ -91,15 +91,16 @@ __global__ void __launch_bounds__(kValidateWaves * kWave)
 // Cost of a ligand: sum_r m_r (S + q_r) (per-angle atom work plus pair setup),
 // bucketed on a log2 scale; a counting sort emits buckets from the most
 // expensive down.  Order inside a bucket is irrelevant to the results.
-// Size class c (0: at most c16 atoms, 1: at most c32s, 2: at most c32, 3:
-// the rest; c16 <= c32s <= c32) leads the sort key, so every class is a
-// contiguous range of the order.  A block counts its ligands per bucket in
+// Size class c (0: at most c16 atoms; then the 32-lane ligands, at most c32,
+// in classes split atoms wide from c16 up, one class when split is 0; the
+// rest last) leads the sort key, so every class is a contiguous range of the
+// order.  A block counts its ligands per bucket in
 // LDS and adds each nonzero count to the global one (one atomic per block
 // and bucket instead of one per ligand on a few hundred addresses).
 constexpr int kLptThreads = 256;
 static_assert(kSortBuckets <= 1024, "one scan thread per bucket");
 __global__ void __launch_bounds__(kLptThreads)
-    lpt_bucket_kernel(LigView L, int S, const int32_t *status, int c16, int c32s, int c32,
+    lpt_bucket_kernel(LigView L, int S, const int32_t *status, int c16, int split, int c32,
                       int32_t *bucket_of, int32_t *counts) {
   __shared__ int32_t hist[kSortBuckets];
   for (int i = threadIdx.x; i < kSortBuckets; i += kLptThreads) hist[i] = 0;
@@ -110,7 +111,9 @@ __global__ void __launch_bounds__(kLptThreads)
     int cls = kClasses - 1;
     if (status[l] == 0) {
       int n = L.atom_offset[l + 1] - L.atom_offset[l];
-      cls = n <= c16 ? 0 : (n <= c32s ? 1 : (n <= c32 ? 2 : 3));
+      cls = n <= c16   ? 0
+            : n <= c32 ? 1 + (split > 0 ? (n - c16 - 1) / split : 0)
+                       : kClasses - 1;
       for (int r = L.rot_offset[l]; r < L.rot_offset[l + 1]; ++r) {
         int m = L.move_offset[r + 1] - L.move_offset[r];
         cost += (float)m * ((float)S + (float)(n - m - 2));
@@ -418,7 +421,7 @@ hipError_t enqueue_fill_i32(int32_t *p, int n, int32_t v, hipStream_t st) {
 }
 
 hipError_t enqueue_prepare(const SweepArgs &A, int max_atoms, int max_rot, bool lpt, int c16,
-                           int c32s, int c32, int32_t *bucket_of, int32_t *counts,
+                           int split, int c32, int32_t *bucket_of, int32_t *counts,
                            int32_t *cursor, int32_t *n_bad, hipStream_t st) {
   const int L = A.lig.n_ligands;
   const int nsmall = kSmallInts;
@@ -432,7 +435,7 @@ hipError_t enqueue_prepare(const SweepArgs &A, int max_atoms, int max_rot, bool 
                        0, st, A.lig, max_atoms, max_rot, const_cast<int32_t *>(A.status), n_bad);
     if (lpt) {
       hipLaunchKernelGGL(lpt_bucket_kernel, dim3(blocks_for(L, kLptThreads)), dim3(kLptThreads),
-                         0, st, A.lig, A.S, A.status, c16, c32s, c32, bucket_of, counts);
+                         0, st, A.lig, A.S, A.status, c16, split, c32, bucket_of, counts);
       hipLaunchKernelGGL(lpt_scan_kernel, dim3(1), dim3(kSortBuckets), 0, st, counts, cursor,
                          A.small);
       hipLaunchKernelGGL(lpt_scatter_kernel, dim3(blocks_for(L, kLptThreads)), dim3(kLptThreads),

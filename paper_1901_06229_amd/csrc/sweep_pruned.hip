@@ -249,13 +249,16 @@ hipError_t enqueue_sweep_pruned(const SweepArgs &A, int max_atoms, const LaunchP
     // the 32-lane ligands in one or (split) two classes
     const int c16 = min(plan.group16_atoms, max_atoms);
     const int c32 = min(plan.group32_atoms, max_atoms);
-    const int c32s = plan.group32_split > c16 && plan.group32_split < c32 ? plan.group32_split : c32;
+    const int split = c32 > c16 ? plan.group32_split : 0;
     hipError_t e = hipSuccess;
     if (c16 > 0) e = enqueue_sweep_group(A, 16, 0, (c16 + 15) / 16 * 16, plan, n_cu, st);
-    if (e == hipSuccess && c32s > c16)
-      e = enqueue_sweep_group(A, 32, 1, (c32s + 15) / 16 * 16, plan, n_cu, st);
-    if (e == hipSuccess && c32 > c32s)
-      e = enqueue_sweep_group(A, 32, 2, (c32 + 15) / 16 * 16, plan, n_cu, st);
+    // the 32-lane classes (the same bounds the LPT kernel sorted by), each
+    // with the LDS of its largest ligand
+    for (int cls = 1, lo = c16; e == hipSuccess && lo < c32; ++cls) {
+      const int hi = split > 0 ? min(c32, lo + split) : c32;
+      e = enqueue_sweep_group(A, 32, cls, (hi + 15) / 16 * 16, plan, n_cu, st);
+      lo = hi;
+    }
     if (e != hipSuccess) return e;
     if (max_atoms <= max(c16, c32)) return hipSuccess;  // the last class is empty
   }

@@ -455,7 +455,7 @@ def dock_get_group_mapping(pocket: Pocket):
 
 
 def dock_set_group_split(pocket: Pocket, atoms: int = 0):
-    """32-lane ligands above `atoms` atoms get a kernel of their own (0: none)."""
+    """32-lane ligands in classes `atoms` wide, a kernel each (0: one class)."""
     _check(load_library().dock_set_group_split(pocket.handle, int(atoms)), "dock_set_group_split")
 
 

@@ -55,9 +55,10 @@ def test_grouped_results_are_bitwise_the_single_item_ones(pockets):
     ref = _run(h, ligs, orient, 128, (0, 0))
     for mp in MAPPINGS[1:]:
         _same(_run(h, ligs, orient, 128, mp), ref, mp)
-    # the 32-lane ligands split into two classes (and splits that are no-ops)
-    for mp, split in (((64, 160), 128), ((48, 150), 96), ((0, 128), 64), ((64, 128), 64),
-                      ((64, 128), 128)):
+    # the 32-lane ligands in classes of 32, 48 or 64 atoms (up to 6 of them),
+    # and widths that leave one class
+    for mp, split in (((64, 160), 32), ((48, 150), 48), ((0, 192), 32), ((0, 128), 64),
+                      ((64, 128), 64), ((64, 128), 128)):
         _same(_run(h, ligs, orient, 128, mp, split), ref, (mp, split))
 
 
@@ -127,7 +128,7 @@ def test_grouped_large_ligands(pockets):
     ref = _run(h, ligs, orient, 360, (0, 0))
     for mp in ((80, 192), (0, 160), (64, 128)):
         _same(_run(h, ligs, orient, 360, mp), ref, mp)
-    for mp, split in (((80, 192), 128), ((0, 192), 150)):
+    for mp, split in (((80, 192), 48), ((80, 192), 32), ((0, 192), 150)):
         _same(_run(h, ligs, orient, 360, mp, split), ref, (mp, split))
 
 
@@ -170,12 +171,12 @@ def test_group_mapping_arguments(pockets):
     dock.dock_set_group_mapping(h, 32, 64)
     assert dock.dock_get_group_mapping(h) == (32, 64)
     dock.dock_set_group_mapping(h, 0, 0)
-    for bad in (-1, 193):
+    for bad in (-1, 16, 31, 193):
         with pytest.raises(dock.DockError) as e:
             dock.dock_set_group_split(h, bad)
         assert e.value.code == dock.DOCK_E_LIMIT
-    dock.dock_set_group_split(h, 128)
-    assert dock.dock_get_group_split(h) == 128
+    dock.dock_set_group_split(h, 32)
+    assert dock.dock_get_group_split(h) == 32
     dock.dock_set_group_split(h, 0)
     assert dock.dock_get_group_split(h) == 0
 
