@@ -75,3 +75,37 @@ def test_bench_traffic_is_reported_only_for_the_measured_kernel(tmp_path, monkey
     assert bench.measured_traffic(3) is None
     monkeypatch.setattr(bench, "TRAFFIC_FILES", {3: str(tmp_path / "missing.md")})
     assert bench.measured_traffic(3) is None
+
+
+def test_binding_structs_match_the_header():
+    """Every struct the header typedefs has a ctypes mirror in the binding
+    with the same fields, in the same order and of the same sizes, so a field
+    added on one side only cannot shift the others silently."""
+    import ctypes
+    import re
+    from paper_1901_06229_amd import dock as binding
+    header = open(os.path.join(ROOT, "include", "dock.h")).read()
+    header = re.sub(r"/\*.*?\*/", " ", header, flags=re.S)
+    sizes = {"int8_t": 1, "int16_t": 2, "int32_t": 4, "uint32_t": 4, "int": 4, "float": 4,
+             "int64_t": 8, "uint64_t": 8, "double": 8, "size_t": 8}
+    structs = re.findall(r"typedef struct \{(.*?)\}\s*(\w+);", header, flags=re.S)
+    assert len(structs) >= 6
+    for body, name in structs:
+        fields = []
+        for decl in body.split(";"):
+            decl = decl.replace("const ", " ").strip()
+            if not decl:
+                continue
+            base, rest = decl.split(None, 1)
+            for d in rest.split(","):
+                d = d.strip()
+                fields.append((d.lstrip("*").strip(), 8 if d.startswith("*") else sizes[base]))
+        mirror = getattr(binding, name)
+        got = [(f, ctypes.sizeof(t)) for f, t in mirror._fields_]
+        assert got == fields, (name, got, fields)
+        # natural alignment: the C layout's size
+        off = 0
+        for _, sz in fields:
+            off = (off + sz - 1) // sz * sz + sz
+        align = max(sz for _, sz in fields)
+        assert ctypes.sizeof(mirror) == (off + align - 1) // align * align, name
