@@ -134,31 +134,37 @@ def test_grouped_large_ligands(pockets):
 
 def test_grouped_async_graph_replay(pockets):
     """Device-array calls, eager and as a replayed HIP graph, with the grouped
-    mapping: equal to the synchronous one-item-per-wave call."""
+    mapping (one 32-lane class, and the 32-lane ligands in classes 32 atoms
+    wide, the launch the bench replays): equal to the synchronous
+    one-item-per-wave call."""
     import torch
     from tests.test_parity_gpu import _device_batch
     p, h = pockets(3)
     ligs = synth.ligands(3, count=500, first=7000)
     orient = synth.orientations(3, 16)
     ref = _run(h, ligs, orient, 128, (0, 0))
-    dock.dock_set_group_mapping(h, 40, 80)
     d, od, out = _device_batch(ligs, orient, 128, torch)
     ws = torch.empty(dock.dock_workspace_size(ligs.n_ligands, d["total_rot"], 16, 128),
                      dtype=torch.uint8, device="cuda:0")
     st = torch.cuda.Stream()
     mx = int(np.diff(ligs.atom_offset).max())
     names = NAMES[:-1]
-    for flags in (0, dock.DOCK_FLAG_GRAPH, dock.DOCK_FLAG_GRAPH):
-        for k in names:
-            out[k].fill_(0)
-        torch.cuda.synchronize()
-        dock.dock_batch_async(h, d, od, 128, out, dock.make_params(max_atoms=mx, flags=flags),
-                              workspace=ws, stream=st)
-        st.synchronize()
-        got = {k: out[k].cpu().numpy() for k in names}
-        got["xyz"] = got["xyz"].reshape(-1, 3)
-        for k in names:
-            assert np.array_equal(np.asarray(ref[k]).reshape(got[k].shape), got[k]), (flags, k)
+    for mp, split in (((40, 80), 0), ((64, 192), 32)):
+        dock.dock_set_group_mapping(h, *mp)
+        dock.dock_set_group_split(h, split)
+        for flags in (0, dock.DOCK_FLAG_GRAPH, dock.DOCK_FLAG_GRAPH):
+            for k in names:
+                out[k].fill_(0)
+            torch.cuda.synchronize()
+            dock.dock_batch_async(h, d, od, 128, out, dock.make_params(max_atoms=mx, flags=flags),
+                                  workspace=ws, stream=st)
+            st.synchronize()
+            got = {k: out[k].cpu().numpy() for k in names}
+            got["xyz"] = got["xyz"].reshape(-1, 3)
+            for k in names:
+                assert np.array_equal(np.asarray(ref[k]).reshape(got[k].shape), got[k]), \
+                    (mp, split, flags, k)
+    dock.dock_set_group_split(h, 0)
 
 
 def test_group_mapping_arguments(pockets):
